@@ -1,0 +1,165 @@
+/*
+ * pm.h -- C ABI of the MI355X product-matrix regenerating-code engine.
+ *
+ * The engine computes, over GF(2^8), the data phase of the product-matrix
+ * (PM) regenerating codes of "Fast Product-Matrix Regenerating Codes"
+ * (Le Scouarnec, arXiv 1412.3022): encoding with the linearized generator G
+ * or the systematic generator G' = [I; G''] (Sections 3.1-3.3), repair of one
+ * node from d helpers, and decoding from any k nodes (Section 2).  Every
+ * operation is one region matrix product out[r] = XOR_c A[r][c] * in[c] over
+ * byte regions, run by hand-written gfx950 kernels.
+ *
+ * Conventions for every data call:
+ *  - A "region set" is R blocks of block_bytes bytes in device memory; block
+ *    r starts at base + r * ld.  base must be 16-byte aligned, ld a multiple
+ *    of 16 with ld >= block_bytes.  block_bytes may be any value >= 1.
+ *  - Input and output region sets must not overlap (PM_EINVAL).
+ *  - Calls only enqueue work on `stream` (a hipStream_t, NULL = the default
+ *    stream) and return; the caller owns every buffer and must keep it alive
+ *    until the stream has passed the call.  Host-side matrix construction for
+ *    a new failure pattern runs synchronously inside the call (the paper's
+ *    "initialization" phase, Section 4) and is cached in the code object.
+ *  - Errors come back as a pm_status; nothing is thrown across the ABI.
+ *    PM_EHIP means a HIP call failed (its message: pm_last_hip_error()).
+ *  - A pm_code is immutable after creation apart from internal caches that
+ *    are locked; it may be used from several host threads and streams at
+ *    once.  The device copy of its tables is made on first use per device.
+ *
+ * Field: GF(2^8) with polynomial x^8+x^4+x^3+x^2+1 (0x11D) and generator 2,
+ * the default field of GF-Complete that the paper uses (Section 3.3).
+ */
+#ifndef PM_H
+#define PM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *pm_stream; /* same object as hipStream_t */
+
+typedef enum {
+    PM_OK = 0,
+    PM_EINVAL = -1,        /* bad argument: ids, sizes, alignment, aliasing */
+    PM_EUNSUPPORTED = -2,  /* parameters outside the constructions */
+    PM_ESINGULAR = -3,     /* helper set / node set cannot repair / decode */
+    PM_ENOMEM = -4,        /* host or device allocation failed */
+    PM_EHIP = -5,          /* a HIP runtime call failed */
+    PM_EBUSY = -6          /* a queue is full; retry later */
+} pm_status;
+
+typedef enum {
+    PM_MSR = 0,  /* minimum-storage: alpha = d-k+1, d = 2k-2 (Section 2) */
+    PM_MBR = 1,  /* minimum-bandwidth: alpha = d (Section 2) */
+    PM_RS = 2    /* Reed-Solomon baseline, Vandermonde, systematic (Section 4) */
+} pm_kind;
+
+typedef enum {
+    PM_VANILLA = 0,  /* Vandermonde Psi of the seminal construction (Section 3.3) */
+    PM_SPARSE = 1    /* identity-over-Cauchy Psi proposed by the paper (Section 3.3) */
+} pm_construction;
+
+typedef struct {
+    uint32_t w;            /* field width; only 8 is supported */
+    uint32_t k, d, n;      /* MSR: d = 2k-2, n >= d+1 (sparse: n in {2k-1, 2k});
+                              MBR: k <= d <= n-1; RS: d ignored, k < n; n <= 255 */
+    int32_t kind;          /* pm_kind */
+    int32_t construction;  /* pm_construction (MSR only) */
+    uint32_t systematic;   /* MSR: 1 = encode with G' = G inverse(G~) (Section 3.2),
+                              0 = with G.  MBR and RS are always systematic. */
+    const uint8_t *x;      /* MSR vanilla only: n distinct evaluation points
+                              (host memory, copied), NULL = x_i = g^i */
+} pm_params;
+
+typedef struct pm_code pm_code;
+
+/* Build a code: Psi, index matrix L, linearized G (Section 3.1), systematic
+ * G' (Section 3.2), the validity check of Section 3.3 (distinct Lambda, every
+ * d rows of Psi independent).  Host only: touches no GPU.  *out receives a
+ * handle owned by the caller (free with pm_code_destroy).
+ * Errors: PM_EINVAL (NULL, w != 8, shape), PM_EUNSUPPORTED (construction
+ * invalid for these parameters), PM_ESINGULAR, PM_ENOMEM. */
+pm_status pm_code_create(const pm_params *params, pm_code **out);
+
+/* Free a code and its device tables.  The caller must make sure no stream is
+ * still running a call on it. */
+void pm_code_destroy(pm_code *code);
+
+/* alpha (blocks per node), beta (= 1, blocks sent per helper), B (message
+ * blocks = k Delta), enc_rows (blocks written by pm_encode: the parity rows
+ * (n alpha - B for systematic MSR, (n-k) d for MBR, n-k for RS) or all
+ * n alpha rows for non-systematic MSR).  Any pointer may be NULL. */
+pm_status pm_code_dims(const pm_code *code, uint32_t *alpha, uint32_t *beta,
+                       uint32_t *B, uint32_t *enc_rows);
+
+/* Copy a host matrix of the code into host buffer `dst` of `cap` bytes
+ * (row-major), and its shape into *rows, *cols.  which: 0 = Psi (n x d; RS:
+ * the n x k generator), 1 = Lambda (1 x n, MSR), 2 = G linearized
+ * (n alpha x B), 3 = the generator node contents follow (G' or G),
+ * 4 = the encode matrix (enc_rows x B).  PM_EINVAL if cap is too small. */
+pm_status pm_code_matrix(const pm_code *code, int which, uint8_t *dst, size_t cap,
+                         uint32_t *rows, uint32_t *cols);
+
+/* Where each of the n alpha node blocks lives after pm_encode: map[t] for
+ * node t / alpha, block t % alpha, is v < B for message block v (uncoded),
+ * or B + r for row r of pm_encode's output.  cap = entries of map. */
+pm_status pm_code_node_map(const pm_code *code, int32_t *map, size_t cap);
+
+/* Encode (Section 3.1 / 3.2): out[r] = XOR_c E[r][c] * X[c] for the enc_rows
+ * rows E of the encode matrix (G'' for systematic codes, so the message blocks
+ * are not rewritten; G for non-systematic MSR).  X: B blocks (device), out:
+ * enc_rows blocks (device). */
+pm_status pm_encode(const pm_code *code, const uint8_t *X, size_t x_ld, uint8_t *out,
+                    size_t out_ld, size_t block_bytes, pm_stream stream);
+
+/* Repair, helper side (Section 2, repair with d helpers sending beta = 1
+ * block each): a surviving node projects its alpha blocks onto the failed
+ * node's vector -- phi_f for MSR (a unit vector for the first alpha nodes of
+ * the sparse code: the helper reads one block, Section 3.3), psi_f for MBR,
+ * the block itself for RS.  node: alpha blocks (device); out: 1 block. */
+pm_status pm_repair_helper(const pm_code *code, uint32_t failed, const uint8_t *node,
+                           size_t node_ld, uint8_t *out, size_t block_bytes,
+                           pm_stream stream);
+
+/* Repair, newcomer side: from the d helper blocks (recv, in the order of
+ * helpers[], device) rebuild the alpha blocks of node `failed` (out, device).
+ * helpers: d distinct node ids != failed (host array).  MSR uses
+ * [I | lambda_f I] inverse(Psi_H), MBR inverse(Psi_H), RS row f of G times
+ * inverse(G_H) with d = k.  PM_ESINGULAR when Psi_H is singular. */
+pm_status pm_repair_newcomer(const pm_code *code, uint32_t failed, const uint32_t *helpers,
+                             const uint8_t *recv, size_t recv_ld, uint8_t *out,
+                             size_t out_ld, size_t block_bytes, pm_stream stream);
+
+/* Decode (Section 2: X = inverse(G~) Y~): from k distinct nodes (host array
+ * `nodes`) whose k alpha blocks are in Y (node-major, in the order of
+ * nodes[], device), rebuild the B message blocks X (device).  Message blocks
+ * found uncoded in Y are copied, the rest computed (the lazy decoding of
+ * Section 3.1).  For MBR the first B independent received rows are used. */
+pm_status pm_decode(const pm_code *code, const uint32_t *nodes, const uint8_t *Y,
+                    size_t y_ld, uint8_t *X, size_t x_ld, size_t block_bytes,
+                    pm_stream stream);
+
+/* The region engine itself (the constant-times-region multiply-XOR of the
+ * paper's Section 4, batched over a matrix): out[r] = XOR_c A[r][c] * in[c]
+ * for a host row-major rows x cols matrix A.  Tables are cached by content. */
+pm_status pm_apply(const uint8_t *A, uint32_t rows, uint32_t cols, const uint8_t *in,
+                   size_t in_ld, uint8_t *out, size_t out_ld, size_t block_bytes,
+                   pm_stream stream);
+
+/* Kernel variant for one operation of a code (set by the autotuner or the
+ * caller).  op: 0 encode, 1 repair helper, 2 repair newcomer, 3 decode,
+ * 4 pm_apply (global).  rows_per_group in {4, 8, 16}, dwords_per_lane in
+ * {2, 4}; 0, 0 restores the built-in cost model. */
+pm_status pm_set_variant(pm_code *code, int op, uint32_t rows_per_group,
+                         uint32_t dwords_per_lane);
+
+/* Message of the last failing HIP call on this thread ("" if none). */
+const char *pm_last_hip_error(void);
+const char *pm_status_string(pm_status st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PM_H */

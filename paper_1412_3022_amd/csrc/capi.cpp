@@ -1,0 +1,442 @@
+// C ABI of the engine (declared in include/pm.h): code objects, per-failure
+// pattern matrix caches, device copies of the kernel tables, and dispatch of
+// the region kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "construct.hpp"
+#include "engine.hpp"
+#include "pm.h"
+#include "program.hpp"
+
+using namespace pmrc;
+
+namespace pmrc {
+
+thread_local std::string g_hip_msg;
+
+int hip_fail(hipError_t e) {
+    g_hip_msg = hipGetErrorString(e);
+    return ST_EHIP;
+}
+
+// ---- device copies of programs ---------------------------------------------
+// Process-lifetime objects are heap allocated and never destroyed, so no HIP
+// call runs from a static destructor after the runtime has shut down.
+static std::mutex g_dev_mu;
+static std::map<int, hipStream_t> &g_upload_stream = *new std::map<int, hipStream_t>();
+
+static int upload_stream(int dev, hipStream_t *out) {
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto it = g_upload_stream.find(dev);
+    if (it != g_upload_stream.end()) { *out = it->second; return ST_OK; }
+    hipStream_t s;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e);
+    g_upload_stream[dev] = s;
+    *out = s;
+    return ST_OK;
+}
+
+ProgEntry::~ProgEntry() {
+    for (auto &kv : dev) {
+        if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
+        if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+    }
+}
+
+int ProgEntry::device_ptr(hipStream_t user, const uint32_t **out) {
+    int devid = 0;
+    hipError_t e = hipGetDevice(&devid);
+    if (e != hipSuccess) return hip_fail(e);
+    std::lock_guard<std::mutex> lk(mu);
+    DevCopy &dc = dev[devid];
+    if (!dc.ptr) {
+        hipStream_t up = nullptr;
+        int st = upload_stream(devid, &up);
+        if (st != ST_OK) return st;
+        const size_t bytes = prog.blob.size() * sizeof(uint32_t);
+        if ((e = hipMalloc(&dc.ptr, bytes)) != hipSuccess) { dc.ptr = nullptr; return hip_fail(e); }
+        if ((e = hipMemcpyAsync(dc.ptr, prog.blob.data(), bytes, hipMemcpyHostToDevice, up)) != hipSuccess)
+            return hip_fail(e);
+        if ((e = hipEventCreateWithFlags(&dc.ready, hipEventDisableTiming)) != hipSuccess) return hip_fail(e);
+        if ((e = hipEventRecord(dc.ready, up)) != hipSuccess) return hip_fail(e);
+    }
+    if (!dc.done) {
+        e = hipEventQuery(dc.ready);
+        if (e == hipSuccess) {
+            dc.done = true;
+        } else if (e == hipErrorNotReady) {
+            if ((e = hipStreamWaitEvent(user, dc.ready, 0)) != hipSuccess) return hip_fail(e);
+        } else {
+            return hip_fail(e);
+        }
+    }
+    *out = static_cast<const uint32_t *>(dc.ptr);
+    return ST_OK;
+}
+
+// ---- variant choice ----------------------------------------------------------
+// VALU cost per lane dword of a program: each evaluated slot costs three
+// byte-permutes and 1.5 three-input XORs plus its share of table moves; each
+// group column costs its source-field extraction and a load.
+static double program_cost(const Program &p) {
+    return static_cast<double>(p.slots) * 4.8 + static_cast<double>(p.col_reads) * 7.0 +
+           static_cast<double>(p.copies) * 2.0;
+}
+
+int Variant::pick_rg(const Mat &A) {
+    double best = 1e300;
+    int best_rg = 8;
+    for (int rg : {4, 8, 16}) {
+        Program p = build_program(A, rg);
+        double c = program_cost(p);
+        if (c < best - 1e-9) { best = c; best_rg = rg; }
+    }
+    return best_rg;
+}
+
+// ---- launching -----------------------------------------------------------------
+static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+int check_regions(const void *base, size_t ld, size_t nblocks, size_t s) {
+    if (nblocks == 0) return ST_OK;
+    if (!base || !aligned16(base) || ld % 16 != 0 || ld < s) return ST_EINVAL;
+    return ST_OK;
+}
+
+static bool overlaps(const void *a, size_t a_ld, size_t a_n, const void *b, size_t b_ld, size_t b_n,
+                     size_t s) {
+    if (!a_n || !b_n) return false;
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(a), a1 = a0 + (a_n - 1) * a_ld + s;
+    const uintptr_t b0 = reinterpret_cast<uintptr_t>(b), b1 = b0 + (b_n - 1) * b_ld + s;
+    return a0 < b1 && b0 < a1;
+}
+
+int launch_program(ProgEntry &pe, int vec, const uint8_t *in, size_t in_ld, size_t in_n, uint8_t *out,
+                   size_t out_ld, size_t out_n, size_t s, hipStream_t stream) {
+    if (s == 0) return ST_EINVAL;
+    int st;
+    if ((st = check_regions(in, in_ld, in_n, s)) != ST_OK) return st;
+    if ((st = check_regions(out, out_ld, out_n, s)) != ST_OK) return st;
+    if (overlaps(in, in_ld, in_n, out, out_ld, out_n, s)) return ST_EINVAL;
+    if (pe.prog.ngroups == 0) return ST_OK;
+    const uint32_t *dprog = nullptr;
+    if ((st = pe.device_ptr(stream, &dprog)) != ST_OK) return st;
+    PmkApply a{in, in_ld, out, out_ld, s, dprog, static_cast<uint32_t>(pe.prog.ngroups)};
+    hipError_t e = pmk_apply(pe.prog.rg, vec, &a, stream);
+    if (e != hipSuccess) return hip_fail(e);
+    return ST_OK;
+}
+
+// ---- pm_apply: programs cached by matrix content ----------------------------------
+static std::mutex g_apply_mu;
+static std::map<std::tuple<int, int, std::vector<uint8_t>, int>, std::unique_ptr<ProgEntry>> &g_apply =
+    *new std::map<std::tuple<int, int, std::vector<uint8_t>, int>, std::unique_ptr<ProgEntry>>();
+static Variant g_apply_var;
+
+void set_apply_variant(int rg, int vec) {
+    std::lock_guard<std::mutex> lk(g_apply_mu);
+    g_apply_var.rg = rg;
+    g_apply_var.vec = vec;
+}
+
+ProgEntry *apply_program(const Mat &A, int *vec) {
+    std::lock_guard<std::mutex> lk(g_apply_mu);
+    const int rg = g_apply_var.rg ? g_apply_var.rg : Variant::pick_rg(A);
+    *vec = g_apply_var.vec ? g_apply_var.vec : 4;
+    auto key = std::make_tuple(A.rows, A.cols, A.v, rg);
+    auto it = g_apply.find(key);
+    if (it != g_apply.end()) return it->second.get();
+    auto pe = std::make_unique<ProgEntry>();
+    pe->prog = build_program(A, rg);
+    ProgEntry *raw = pe.get();
+    g_apply.emplace(std::move(key), std::move(pe));
+    return raw;
+}
+
+}  // namespace pmrc
+
+// ---- the code object -------------------------------------------------------------
+struct pm_code {
+    CodeMats m;
+    std::mutex mu;
+    Variant var[4];
+    std::map<std::tuple<int>, std::unique_ptr<ProgEntry>> enc;                      // rg
+    std::map<std::pair<int, int>, std::unique_ptr<ProgEntry>> helper;              // failed, rg
+    std::map<std::tuple<int, std::vector<int>, int>, std::unique_ptr<ProgEntry>> newcomer;
+    std::map<std::pair<std::vector<int>, int>, std::unique_ptr<ProgEntry>> decode;  // nodes, rg
+    std::map<int, Mat> helper_mat;
+    std::map<std::pair<int, std::vector<int>>, Mat> newcomer_mat;
+    std::map<std::vector<int>, std::pair<Mat, std::vector<int>>> decode_mat;
+};
+
+namespace {
+
+// Find or build the program for matrix A under variant v (rg chosen once per
+// matrix when v.rg == 0).  Caller holds code->mu.
+template <class Map, class Key>
+ProgEntry *get_prog(Map &map, const Key &key_prefix_rg, const Mat &A, const std::vector<int> &in_map) {
+    auto it = map.find(key_prefix_rg);
+    if (it != map.end()) return it->second.get();
+    auto pe = std::make_unique<ProgEntry>();
+    int rg = std::get<std::tuple_size<Key>::value - 1>(key_prefix_rg);
+    pe->prog = build_program(A, rg, in_map);
+    ProgEntry *raw = pe.get();
+    map.emplace(key_prefix_rg, std::move(pe));
+    return raw;
+}
+
+int resolve_rg(Variant &v, const Mat &A, std::map<std::vector<uint8_t>, int> *memo = nullptr) {
+    if (v.rg) return v.rg;
+    if (memo) {
+        auto it = memo->find(A.v);
+        if (it != memo->end()) return it->second;
+    }
+    int rg = Variant::pick_rg(A);
+    if (memo) (*memo)[A.v] = rg;
+    return rg;
+}
+
+std::map<std::vector<uint8_t>, int> &rg_memo() {
+    static std::map<std::vector<uint8_t>, int> m;
+    return m;
+}
+std::mutex g_memo_mu;
+
+int pick_rg_cached(Variant &v, const Mat &A) {
+    if (v.rg) return v.rg;
+    std::lock_guard<std::mutex> lk(g_memo_mu);
+    return resolve_rg(v, A, &rg_memo());
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pm_status_string(pm_status st) {
+    switch (st) {
+        case PM_OK: return "ok";
+        case PM_EINVAL: return "invalid argument";
+        case PM_EUNSUPPORTED: return "unsupported parameters";
+        case PM_ESINGULAR: return "singular matrix (node set cannot repair or decode)";
+        case PM_ENOMEM: return "out of memory";
+        case PM_EHIP: return "HIP runtime error";
+        case PM_EBUSY: return "busy";
+    }
+    return "unknown status";
+}
+
+const char *pm_last_hip_error(void) { return g_hip_msg.c_str(); }
+
+pm_status pm_code_create(const pm_params *p, pm_code **out) {
+    if (!p || !out) return PM_EINVAL;
+    *out = nullptr;
+    if (p->w != 8) return PM_EUNSUPPORTED;
+    if (p->kind < 0 || p->kind > 2) return PM_EINVAL;
+    CodeSpec spec;
+    spec.kind = p->kind;
+    spec.construction = p->construction;
+    spec.systematic = (p->kind == PM_MSR) ? (p->systematic ? 1 : 0) : 1;
+    spec.k = static_cast<int>(p->k);
+    spec.d = static_cast<int>(p->d);
+    spec.n = static_cast<int>(p->n);
+    if (p->kind == PM_MSR && p->construction != PM_VANILLA && p->construction != PM_SPARSE) return PM_EINVAL;
+    if (p->x) {
+        if (p->kind != PM_MSR || p->construction != PM_VANILLA || p->n > 255) return PM_EINVAL;
+        spec.x.assign(p->x, p->x + p->n);
+    }
+    try {
+        std::unique_ptr<pm_code> c(new pm_code());
+        int st = build_code(spec, c->m);
+        if (st != ST_OK) return static_cast<pm_status>(st);
+        *out = c.release();
+        return PM_OK;
+    } catch (const std::bad_alloc &) {
+        return PM_ENOMEM;
+    }
+}
+
+void pm_code_destroy(pm_code *code) { delete code; }
+
+pm_status pm_code_dims(const pm_code *c, uint32_t *alpha, uint32_t *beta, uint32_t *B, uint32_t *enc_rows) {
+    if (!c) return PM_EINVAL;
+    if (alpha) *alpha = static_cast<uint32_t>(c->m.alpha);
+    if (beta) *beta = 1;
+    if (B) *B = static_cast<uint32_t>(c->m.B);
+    if (enc_rows) *enc_rows = static_cast<uint32_t>(c->m.enc.rows);
+    return PM_OK;
+}
+
+pm_status pm_code_matrix(const pm_code *c, int which, uint8_t *dst, size_t cap, uint32_t *rows, uint32_t *cols) {
+    if (!c) return PM_EINVAL;
+    const Mat *M = nullptr;
+    Mat lam;
+    switch (which) {
+        case 0: M = &c->m.psi; break;
+        case 1:
+            if (c->m.kind != KIND_MSR) return PM_EINVAL;
+            lam = Mat(1, c->m.n);
+            std::copy(c->m.lambda.begin(), c->m.lambda.end(), lam.v.begin());
+            M = &lam;
+            break;
+        case 2: M = &c->m.G; break;
+        case 3: M = &c->m.Gsys; break;
+        case 4: M = &c->m.enc; break;
+        default: return PM_EINVAL;
+    }
+    if (rows) *rows = static_cast<uint32_t>(M->rows);
+    if (cols) *cols = static_cast<uint32_t>(M->cols);
+    if (!dst) return PM_OK;
+    if (cap < M->v.size()) return PM_EINVAL;
+    std::memcpy(dst, M->v.data(), M->v.size());
+    return PM_OK;
+}
+
+pm_status pm_code_node_map(const pm_code *c, int32_t *map, size_t cap) {
+    if (!c || !map || cap < c->m.node_map.size()) return PM_EINVAL;
+    std::copy(c->m.node_map.begin(), c->m.node_map.end(), map);
+    return PM_OK;
+}
+
+pm_status pm_set_variant(pm_code *c, int op, uint32_t rg, uint32_t vec) {
+    const bool reset = rg == 0 && vec == 0;
+    if (!reset && ((rg != 4 && rg != 8 && rg != 16) || (vec != 2 && vec != 4))) return PM_EINVAL;
+    if (op == 4) {
+        set_apply_variant(static_cast<int>(rg), static_cast<int>(vec));
+        return PM_OK;
+    }
+    if (!c || op < 0 || op > 3) return PM_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->var[op].rg = static_cast<int>(rg);
+    c->var[op].vec = reset ? 0 : static_cast<int>(vec);
+    return PM_OK;
+}
+
+pm_status pm_encode(const pm_code *cc, const uint8_t *X, size_t x_ld, uint8_t *out, size_t out_ld,
+                    size_t s, pm_stream stream) {
+    pm_code *c = const_cast<pm_code *>(cc);
+    if (!c || s == 0) return PM_EINVAL;
+    ProgEntry *pe;
+    int vec;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        const int rg = pick_rg_cached(c->var[0], c->m.enc);
+        vec = c->var[0].vec ? c->var[0].vec : 4;
+        pe = get_prog(c->enc, std::make_tuple(rg), c->m.enc, {});
+    }
+    return static_cast<pm_status>(launch_program(*pe, vec, X, x_ld, static_cast<size_t>(c->m.B), out, out_ld,
+                                                 static_cast<size_t>(c->m.enc.rows), s,
+                                                 reinterpret_cast<hipStream_t>(stream)));
+}
+
+pm_status pm_repair_helper(const pm_code *cc, uint32_t failed, const uint8_t *node, size_t node_ld,
+                           uint8_t *out, size_t s, pm_stream stream) {
+    pm_code *c = const_cast<pm_code *>(cc);
+    if (!c || s == 0 || failed >= static_cast<uint32_t>(c->m.n)) return PM_EINVAL;
+    ProgEntry *pe;
+    int vec;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        auto it = c->helper_mat.find(static_cast<int>(failed));
+        if (it == c->helper_mat.end())
+            it = c->helper_mat.emplace(static_cast<int>(failed), helper_row(c->m, static_cast<int>(failed))).first;
+        const int rg = c->var[1].rg ? c->var[1].rg : 4;
+        vec = c->var[1].vec ? c->var[1].vec : 4;
+        pe = get_prog(c->helper, std::make_pair(static_cast<int>(failed), rg), it->second, {});
+    }
+    const size_t in_n = static_cast<size_t>(c->m.kind == KIND_RS ? 1 : c->m.alpha);
+    const size_t out_ld = (s + 15) / 16 * 16;   // one output block: ld only has to be valid
+    return static_cast<pm_status>(launch_program(*pe, vec, node, node_ld, in_n, out, out_ld, 1, s,
+                                                 reinterpret_cast<hipStream_t>(stream)));
+}
+
+pm_status pm_repair_newcomer(const pm_code *cc, uint32_t failed, const uint32_t *helpers, const uint8_t *recv,
+                             size_t recv_ld, uint8_t *out, size_t out_ld, size_t s, pm_stream stream) {
+    pm_code *c = const_cast<pm_code *>(cc);
+    if (!c || !helpers || s == 0 || failed >= static_cast<uint32_t>(c->m.n)) return PM_EINVAL;
+    const int d = c->m.d;
+    std::vector<int> H(helpers, helpers + d);
+    {
+        std::vector<int> sorted = H;
+        std::sort(sorted.begin(), sorted.end());
+        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) return PM_EINVAL;
+        for (int h : H)
+            if (h < 0 || h >= c->m.n || h == static_cast<int>(failed)) return PM_EINVAL;
+    }
+    ProgEntry *pe;
+    int vec;
+    int out_rows;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        auto key = std::make_pair(static_cast<int>(failed), H);
+        auto it = c->newcomer_mat.find(key);
+        if (it == c->newcomer_mat.end()) {
+            Mat R;
+            int st = newcomer_matrix(c->m, static_cast<int>(failed), H, R);
+            if (st != ST_OK) return static_cast<pm_status>(st);
+            it = c->newcomer_mat.emplace(key, std::move(R)).first;
+        }
+        const int rg = pick_rg_cached(c->var[2], it->second);
+        vec = c->var[2].vec ? c->var[2].vec : 4;
+        out_rows = it->second.rows;
+        pe = get_prog(c->newcomer, std::make_tuple(static_cast<int>(failed), H, rg), it->second, {});
+    }
+    return static_cast<pm_status>(launch_program(*pe, vec, recv, recv_ld, static_cast<size_t>(d), out, out_ld,
+                                                 static_cast<size_t>(out_rows), s,
+                                                 reinterpret_cast<hipStream_t>(stream)));
+}
+
+pm_status pm_decode(const pm_code *cc, const uint32_t *nodes, const uint8_t *Y, size_t y_ld, uint8_t *X,
+                    size_t x_ld, size_t s, pm_stream stream) {
+    pm_code *c = const_cast<pm_code *>(cc);
+    if (!c || !nodes || s == 0) return PM_EINVAL;
+    std::vector<int> K(nodes, nodes + c->m.k);
+    {
+        std::vector<int> sorted = K;
+        std::sort(sorted.begin(), sorted.end());
+        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) return PM_EINVAL;
+        for (int v : K)
+            if (v < 0 || v >= c->m.n) return PM_EINVAL;
+    }
+    ProgEntry *pe;
+    int vec;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        auto it = c->decode_mat.find(K);
+        if (it == c->decode_mat.end()) {
+            Mat D;
+            std::vector<int> used;
+            int st = decode_matrix(c->m, K, D, used);
+            if (st != ST_OK) return static_cast<pm_status>(st);
+            it = c->decode_mat.emplace(K, std::make_pair(std::move(D), std::move(used))).first;
+        }
+        const int rg = pick_rg_cached(c->var[3], it->second.first);
+        vec = c->var[3].vec ? c->var[3].vec : 4;
+        pe = get_prog(c->decode, std::make_pair(K, rg), it->second.first, it->second.second);
+    }
+    const size_t in_n = static_cast<size_t>(c->m.k) * static_cast<size_t>(c->m.alpha);
+    return static_cast<pm_status>(launch_program(*pe, vec, Y, y_ld, in_n, X, x_ld, static_cast<size_t>(c->m.B), s,
+                                                 reinterpret_cast<hipStream_t>(stream)));
+}
+
+pm_status pm_apply(const uint8_t *A, uint32_t rows, uint32_t cols, const uint8_t *in, size_t in_ld, uint8_t *out,
+                   size_t out_ld, size_t s, pm_stream stream) {
+    if (!A || rows == 0 || cols == 0 || s == 0) return PM_EINVAL;
+    Mat M(static_cast<int>(rows), static_cast<int>(cols));
+    std::memcpy(M.v.data(), A, M.v.size());
+    int vec = 0;
+    ProgEntry *pe = apply_program(M, &vec);
+    return static_cast<pm_status>(launch_program(*pe, vec, in, in_ld, cols, out, out_ld, rows, s,
+                                                 reinterpret_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

@@ -1,0 +1,49 @@
+// Host construction of PM-MSR / PM-MBR codes (the "initialization" phase of
+// the paper's Section 4): encoding matrix Psi, index matrix L, linearized
+// generator G (Section 3.1), systematic generator G' = [I; G''] (Section 3.2),
+// and the per-failure-pattern repair and decode matrices.
+#pragma once
+#include <cstdint>
+#include <vector>
+
+#include "gf256.hpp"
+
+namespace pmrc {
+
+enum Kind { KIND_MSR = 0, KIND_MBR = 1, KIND_RS = 2 };
+enum Construction { CONS_VANILLA = 0, CONS_SPARSE = 1 };
+
+struct CodeSpec {
+    int kind = KIND_MSR, construction = CONS_SPARSE, systematic = 1;
+    int k = 0, d = 0, n = 0;
+    std::vector<uint8_t> x;  // optional vanilla evaluation points (n entries)
+};
+
+struct CodeMats {
+    int kind = 0, construction = 0, systematic = 1;
+    int k = 0, d = 0, n = 0, alpha = 0, B = 0;
+    Mat psi;                      // n x d (RS: the n x k generator)
+    std::vector<uint8_t> lambda;  // MSR only, n entries
+    std::vector<int> L;           // index matrix (MSR d x alpha, MBR d x d), -1 = zero
+    Mat G;                        // linearized generator, (n alpha) x B
+    Mat Gsys;                     // generator the node contents follow
+    Mat enc;                      // rows written by encode
+    std::vector<int32_t> node_map;  // per node block: < B -> X block, >= B -> enc row + B
+};
+
+// Status codes shared with the C ABI.
+enum {
+    ST_OK = 0, ST_EINVAL = -1, ST_EUNSUPPORTED = -2, ST_ESINGULAR = -3,
+    ST_ENOMEM = -4, ST_EHIP = -5, ST_EBUSY = -6,
+};
+
+int build_code(const CodeSpec &spec, CodeMats &out);
+
+// Repair: the helper's projection row (1 x alpha; RS 1 x 1).
+Mat helper_row(const CodeMats &c, int failed);
+// Repair: the newcomer's matrix for helpers H (alpha x d; RS 1 x k).
+int newcomer_matrix(const CodeMats &c, int failed, const std::vector<int> &helpers, Mat &R);
+// Decode from nodes K: D (B x B) and the received block indices it reads.
+int decode_matrix(const CodeMats &c, const std::vector<int> &nodes, Mat &D, std::vector<int> &used);
+
+}  // namespace pmrc

@@ -1,0 +1,62 @@
+// Internal interfaces shared by the C ABI, the batch planner and the server:
+// device copies of kernel programs and the region-kernel launcher.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "gf256.hpp"
+#include "program.hpp"
+
+// Arguments of one plain region-kernel launch (defined in kernels.hip).
+struct PmkApply {
+    const uint8_t *in;
+    uint64_t in_ld;
+    uint8_t *out;
+    uint64_t out_ld;
+    uint64_t s;
+    const uint32_t *prog;
+    uint32_t ngroups;
+};
+extern "C" hipError_t pmk_apply(int rg, int vec, const PmkApply *h, hipStream_t st);
+extern "C" int pmk_tile_bytes(int vec);
+
+namespace pmrc {
+
+extern thread_local std::string g_hip_msg;
+int hip_fail(hipError_t e);
+
+struct DevCopy {
+    void *ptr = nullptr;
+    hipEvent_t ready = nullptr;
+    bool done = false;
+};
+
+// A program plus its per-device copies.  device_ptr() uploads on first use
+// on the current device (on an internal stream) and makes `user` wait for
+// the upload until it is known to be complete.
+struct ProgEntry {
+    Program prog;
+    std::mutex mu;
+    std::map<int, DevCopy> dev;
+    ~ProgEntry();
+    int device_ptr(hipStream_t user, const uint32_t **out);
+};
+
+struct Variant {
+    int rg = 0;   // 0 = cost model
+    int vec = 0;  // 0 = default (4)
+    static int pick_rg(const Mat &A);
+};
+
+int check_regions(const void *base, size_t ld, size_t nblocks, size_t s);
+int launch_program(ProgEntry &pe, int vec, const uint8_t *in, size_t in_ld, size_t in_n, uint8_t *out,
+                   size_t out_ld, size_t out_n, size_t s, hipStream_t stream);
+
+ProgEntry *apply_program(const Mat &A, int *vec);
+void set_apply_variant(int rg, int vec);
+
+}  // namespace pmrc

@@ -1,0 +1,228 @@
+"""ctypes binding of the engine's C ABI (include/pm.h).
+
+Argument marshalling only: every computation runs in the HIP library.  The
+functions keep the C names (pm_encode, pm_repair_helper, pm_repair_newcomer,
+pm_decode, ...) and take device pointers as integers; ``Code`` wraps them for
+torch uint8 tensors on a ROCm device (torch supplies memory and streams).
+
+If the library is not built this module raises at first use; there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "_lib", "libpmrc.so")
+
+PM_OK, PM_EINVAL, PM_EUNSUPPORTED, PM_ESINGULAR, PM_ENOMEM, PM_EHIP, PM_EBUSY = 0, -1, -2, -3, -4, -5, -6
+PM_MSR, PM_MBR, PM_RS = 0, 1, 2
+PM_VANILLA, PM_SPARSE = 0, 1
+MAT_PSI, MAT_LAMBDA, MAT_G, MAT_GSYS, MAT_ENC = 0, 1, 2, 3, 4
+OP_ENCODE, OP_HELPER, OP_NEWCOMER, OP_DECODE, OP_APPLY = 0, 1, 2, 3, 4
+
+
+class PMError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        msg = "%s failed: %s" % (what, status_string(status))
+        if status == PM_EHIP:
+            msg += " (%s)" % _lib().pm_last_hip_error().decode()
+        super().__init__(msg)
+        self.status = status
+
+
+class pm_params(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_uint32), ("k", ctypes.c_uint32), ("d", ctypes.c_uint32),
+                ("n", ctypes.c_uint32), ("kind", ctypes.c_int32), ("construction", ctypes.c_int32),
+                ("systematic", ctypes.c_uint32), ("x", ctypes.POINTER(ctypes.c_uint8))]
+
+
+_L = None
+
+
+def _lib():
+    global _L
+    if _L is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("HIP engine library not built (%s); run "
+                               "`python -m paper_1412_3022_amd.build`" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz, u32, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_int
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        L.pm_code_create.argtypes = [ctypes.POINTER(pm_params), ctypes.POINTER(vp)]
+        L.pm_code_destroy.argtypes = [vp]
+        L.pm_code_destroy.restype = None
+        L.pm_code_dims.argtypes = [vp, u32p, u32p, u32p, u32p]
+        L.pm_code_matrix.argtypes = [vp, i32, vp, sz, u32p, u32p]
+        L.pm_code_node_map.argtypes = [vp, vp, sz]
+        L.pm_encode.argtypes = [vp, vp, sz, vp, sz, sz, vp]
+        L.pm_repair_helper.argtypes = [vp, u32, vp, sz, vp, sz, vp]
+        L.pm_repair_newcomer.argtypes = [vp, u32, u32p, vp, sz, vp, sz, sz, vp]
+        L.pm_decode.argtypes = [vp, u32p, vp, sz, vp, sz, sz, vp]
+        L.pm_apply.argtypes = [vp, u32, u32, vp, sz, vp, sz, sz, vp]
+        L.pm_set_variant.argtypes = [vp, i32, u32, u32]
+        L.pm_last_hip_error.restype = ctypes.c_char_p
+        L.pm_status_string.argtypes = [i32]
+        L.pm_status_string.restype = ctypes.c_char_p
+        for name in ("pm_code_create", "pm_code_dims", "pm_code_matrix", "pm_code_node_map", "pm_encode",
+                     "pm_repair_helper", "pm_repair_newcomer", "pm_decode", "pm_apply", "pm_set_variant"):
+            getattr(L, name).restype = i32
+        _L = L
+    return _L
+
+
+def lib():
+    return _lib()
+
+
+def status_string(st: int) -> str:
+    return _lib().pm_status_string(st).decode()
+
+
+def _check(st: int, what: str):
+    if st != PM_OK:
+        raise PMError(st, what)
+
+
+def _u32arr(vals):
+    arr = (ctypes.c_uint32 * max(1, len(vals)))(*[int(v) for v in vals])
+    return arr
+
+
+# ---- raw entry points (same names as the C ABI) ---------------------------
+def pm_code_create(k, d, n, kind=PM_MSR, construction=PM_SPARSE, systematic=True, x=None, w=8):
+    p = pm_params()
+    p.w, p.k, p.d, p.n = w, k, d, n
+    p.kind, p.construction, p.systematic = kind, construction, 1 if systematic else 0
+    xbuf = None
+    if x is not None:
+        xbuf = (ctypes.c_uint8 * len(x))(*[int(v) for v in x])
+        p.x = ctypes.cast(xbuf, ctypes.POINTER(ctypes.c_uint8))
+    h = ctypes.c_void_p()
+    st = _lib().pm_code_create(ctypes.byref(p), ctypes.byref(h))
+    return st, h.value
+
+
+def pm_code_destroy(h):
+    _lib().pm_code_destroy(h)
+
+
+def pm_encode(h, x_ptr, x_ld, out_ptr, out_ld, block_bytes, stream=0):
+    return _lib().pm_encode(h, x_ptr, x_ld, out_ptr, out_ld, block_bytes, stream or None)
+
+
+def pm_repair_helper(h, failed, node_ptr, node_ld, out_ptr, block_bytes, stream=0):
+    return _lib().pm_repair_helper(h, failed, node_ptr, node_ld, out_ptr, block_bytes, stream or None)
+
+
+def pm_repair_newcomer(h, failed, helpers, recv_ptr, recv_ld, out_ptr, out_ld, block_bytes, stream=0):
+    return _lib().pm_repair_newcomer(h, failed, _u32arr(helpers), recv_ptr, recv_ld, out_ptr, out_ld,
+                                     block_bytes, stream or None)
+
+
+def pm_decode(h, nodes, y_ptr, y_ld, x_ptr, x_ld, block_bytes, stream=0):
+    return _lib().pm_decode(h, _u32arr(nodes), y_ptr, y_ld, x_ptr, x_ld, block_bytes, stream or None)
+
+
+def pm_apply(A, in_ptr, in_ld, out_ptr, out_ld, block_bytes, stream=0):
+    import numpy as np
+    A = np.ascontiguousarray(A, dtype=np.uint8)
+    return _lib().pm_apply(A.ctypes.data, A.shape[0], A.shape[1], in_ptr, in_ld, out_ptr, out_ld,
+                           block_bytes, stream or None)
+
+
+def pm_set_variant(h, op, rows_per_group, dwords_per_lane):
+    return _lib().pm_set_variant(h, op, rows_per_group, dwords_per_lane)
+
+
+# ---- convenience wrapper over torch tensors -------------------------------
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _regions(t, rows):
+    """(pointer, ld) of a 2-D uint8 region tensor with at least `rows` rows."""
+    import torch
+    if t.dtype != torch.uint8 or t.dim() != 2 or not t.is_cuda:
+        raise ValueError("regions must be a 2-D torch.uint8 device tensor")
+    if t.stride(1) != 1 or t.shape[0] < rows:
+        raise ValueError("regions must be row-contiguous with %d rows" % rows)
+    return t.data_ptr(), t.stride(0)
+
+
+class Code:
+    """A PM-MSR / PM-MBR / RS code; data calls take torch uint8 device tensors
+    shaped [blocks, >= block_bytes] (row stride = ld)."""
+
+    def __init__(self, k, d, n, kind=PM_MSR, construction=PM_SPARSE, systematic=True, x=None):
+        st, h = pm_code_create(k, d, n, kind, construction, systematic, x)
+        _check(st, "pm_code_create")
+        self.h = h
+        self.k, self.n, self.kind = k, n, kind
+        a, b, B, e = (ctypes.c_uint32() for _ in range(4))
+        _check(_lib().pm_code_dims(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(B), ctypes.byref(e)),
+               "pm_code_dims")
+        self.alpha, self.beta, self.B, self.enc_rows = a.value, b.value, B.value, e.value
+        self.d = k if kind == PM_RS else d
+
+    def __del__(self):
+        import sys
+        h, self.h = getattr(self, "h", None), None
+        # At interpreter exit the HIP runtime may already be gone; the process
+        # frees everything anyway.
+        if h and _L is not None and not sys.is_finalizing():
+            _L.pm_code_destroy(h)
+
+    def matrix(self, which):
+        import numpy as np
+        r, c = ctypes.c_uint32(), ctypes.c_uint32()
+        _check(_lib().pm_code_matrix(self.h, which, None, 0, ctypes.byref(r), ctypes.byref(c)), "pm_code_matrix")
+        buf = np.zeros((r.value, c.value), np.uint8)
+        _check(_lib().pm_code_matrix(self.h, which, buf.ctypes.data, buf.size, None, None), "pm_code_matrix")
+        return buf
+
+    def node_map(self):
+        import numpy as np
+        m = np.zeros(self.n * self.alpha, np.int32)
+        _check(_lib().pm_code_node_map(self.h, m.ctypes.data, m.size), "pm_code_node_map")
+        return m
+
+    def set_variant(self, op, rows_per_group, dwords_per_lane):
+        _check(pm_set_variant(self.h, op, rows_per_group, dwords_per_lane), "pm_set_variant")
+
+    def encode(self, X, out, block_bytes, stream=None):
+        xp, xld = _regions(X, self.B)
+        op, old = _regions(out, self.enc_rows)
+        _check(pm_encode(self.h, xp, xld, op, old, block_bytes, _stream_handle(stream)), "pm_encode")
+
+    def repair_helper(self, failed, node, out, block_bytes, stream=None):
+        nrows = 1 if self.kind == PM_RS else self.alpha
+        np_, nld = _regions(node, nrows)
+        if out.dim() == 2:
+            out_ptr = _regions(out, 1)[0]
+        else:
+            out_ptr = out.data_ptr()
+        _check(pm_repair_helper(self.h, failed, np_, nld, out_ptr, block_bytes, _stream_handle(stream)),
+               "pm_repair_helper")
+
+    def repair_newcomer(self, failed, helpers, recv, out, block_bytes, stream=None):
+        rp, rld = _regions(recv, len(helpers))
+        orows = 1 if self.kind == PM_RS else self.alpha
+        op, old = _regions(out, orows)
+        _check(pm_repair_newcomer(self.h, failed, helpers, rp, rld, op, old, block_bytes, _stream_handle(stream)),
+               "pm_repair_newcomer")
+
+    def decode(self, nodes, Y, X, block_bytes, stream=None):
+        yp, yld = _regions(Y, len(nodes) * self.alpha)
+        xp, xld = _regions(X, self.B)
+        _check(pm_decode(self.h, nodes, yp, yld, xp, xld, block_bytes, _stream_handle(stream)), "pm_decode")
+
+
+def apply(A, inp, out, block_bytes, stream=None):
+    ip, ild = _regions(inp, A.shape[1])
+    op, old = _regions(out, A.shape[0])
+    _check(pm_apply(A, ip, ild, op, old, block_bytes, _stream_handle(stream)), "pm_apply")

@@ -1,0 +1,269 @@
+"""Bit-exact parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Small cases compare every byte; the configurations' full sizes compare
+sampled byte positions that the oracle computes one by one.  Output rows are
+pre-filled with a guard byte to catch writes past block_bytes."""
+from itertools import combinations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from gpu_util import device, out_regions, read, to_regions
+from paper_1412_3022_amd import pm, synth
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = [(4, 2), (4, 4), (8, 2), (8, 4), (16, 2), (16, 4)]
+
+
+def _rand(seed, rows, s):
+    return synth.random_bytes(seed, rows * s).reshape(rows, s)
+
+
+def _oracle_for(kw):
+    kind = {pm.PM_MSR: O.MSR, pm.PM_MBR: O.MBR, pm.PM_RS: O.RS}[kw["kind"]]
+    cons = O.VANILLA if kw.get("construction", pm.PM_SPARSE) == pm.PM_VANILLA else O.SPARSE
+    x = np.array(kw["x"]) if kw.get("x") is not None else None
+    return O.Code(kind, kw["k"], kw["d"], kw["n"], cons, kw.get("systematic", True), x=x)
+
+
+# --------------------------------------------------------------- engine ---
+@pytest.mark.parametrize("rg,vec", VARIANTS)
+@pytest.mark.parametrize("s", [1, 15, 16, 17, 100, 1023, 4096, 4097, 12289, 65536 + 13])
+def test_apply_random_matrix_every_variant(rg, vec, s):
+    print("apply rg=%d vec=%d s=%d" % (rg, vec, s), flush=True)
+    rng = np.random.default_rng(s * 31 + rg * 7 + vec)
+    rows, cols = 11, 9
+    A = rng.integers(0, 256, (rows, cols), dtype=np.uint8)
+    A[2] = 0                       # zero row -> zero fill
+    A[3] = 0
+    A[3, 4] = 1                    # unit row -> copy
+    A[5, ::2] = 0                  # partial sparsity
+    A[:, 7] = 0                    # unused column
+    X = _rand(1000 + s, cols, s)
+    want = O.apply(A, X)
+    pm.lib()
+    pm.pm_set_variant(None, pm.OP_APPLY, rg, vec)
+    try:
+        xin = to_regions(X, extra=1, offset_rows=1)
+        out = out_regions(rows, s, extra=2)
+        pm.apply(A, xin, out, s)
+        assert np.array_equal(read(out, s), want)
+    finally:
+        pm.pm_set_variant(None, pm.OP_APPLY, 0, 0)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 30), (56, 56), (17, 3), (240, 240), (112, 84)])
+def test_apply_dense_shapes(shape):
+    rows, cols = shape
+    s = 3 * 4096 + 77
+    print("apply dense %s s=%d" % (shape, s), flush=True)
+    rng = np.random.default_rng(rows * 1000 + cols)
+    A = rng.integers(1, 256, (rows, cols), dtype=np.uint8)
+    X = _rand(rows + cols, cols, s)
+    xin = to_regions(X)
+    out = out_regions(rows, s)
+    pm.apply(A, xin, out, s)
+    assert np.array_equal(read(out, s), O.apply(A, X, nthreads=8))
+
+
+# ----------------------------------------------------------- small codes --
+SMALL = [
+    dict(k=3, d=4, n=6, kind=pm.PM_MSR, construction=pm.PM_VANILLA, x=list(range(1, 7))),
+    dict(k=3, d=4, n=6, kind=pm.PM_MSR, construction=pm.PM_SPARSE),
+    dict(k=4, d=6, n=8, kind=pm.PM_MSR, construction=pm.PM_SPARSE),
+    dict(k=4, d=6, n=7, kind=pm.PM_MSR, construction=pm.PM_SPARSE, systematic=False),
+    dict(k=3, d=4, n=6, kind=pm.PM_MBR),
+    dict(k=4, d=5, n=7, kind=pm.PM_MBR),
+    dict(k=3, d=3, n=6, kind=pm.PM_RS),
+]
+
+
+def _gpu_encode(c, X, s):
+    xin = to_regions(X, extra=1)
+    out = out_regions(c.enc_rows, s)
+    c.encode(xin, out, s)
+    return read(out, s)
+
+
+def _nodes(c, X, P):
+    nm = c.node_map()
+    return {i: np.stack([X[v] if v < c.B else P[v - c.B] for v in nm[i * c.alpha:(i + 1) * c.alpha]])
+            for i in range(c.n)}
+
+
+@pytest.mark.parametrize("kw", SMALL, ids=lambda kw: "%d-%d-%d-%d-%d" % (
+    kw["kind"], kw.get("construction", 1), kw["k"], kw["d"], kw["n"]))
+@pytest.mark.parametrize("s", [64, 4099])
+def test_small_code_roundtrips_on_gpu(kw, s):
+    """Encode, every k-subset decode and every (f, H) repair on the GPU,
+    checked against the oracle byte for byte."""
+    print("small code %s s=%d" % (kw, s), flush=True)
+    c = pm.Code(**kw)
+    o = _oracle_for(kw)
+    X = _rand(7 + s + kw["k"] * 13 + kw["n"], c.B, s)
+    P = _gpu_encode(c, X, s)
+    assert np.array_equal(P, o.encode(X))
+    nodes = _nodes(c, X, P)
+    for K in combinations(range(c.n), c.k):
+        Y = np.concatenate([nodes[i] for i in K])
+        xout = out_regions(c.B, s)
+        c.decode(list(K), to_regions(Y), xout, s)
+        assert np.array_equal(read(xout, s), X), K
+    for f in range(c.n):
+        others = [i for i in range(c.n) if i != f]
+        hrow = o.helper_row(f)
+        for H in combinations(others, c.d):
+            recv = np.zeros((c.d, s), np.uint8)
+            for j, h in enumerate(H):
+                hb = out_regions(1, s)
+                c.repair_helper(f, to_regions(nodes[h][:1 if c.kind == pm.PM_RS else c.alpha]), hb, s)
+                recv[j] = read(hb, s)[0]
+                assert np.array_equal(recv[j], O.apply(hrow, nodes[h])[0])
+            rout = out_regions(1 if c.kind == pm.PM_RS else c.alpha, s)
+            c.repair_newcomer(f, list(H), to_regions(recv), rout, s)
+            assert np.array_equal(read(rout, s), nodes[f]), (f, H)
+
+
+# ------------------------------------------------------- configurations ---
+def _sample_positions(s, seed, count=2048):
+    st = synth.Stream(seed)
+    pos = {0, 1, 2, s - 1, s - 2}
+    pos |= set(range(max(0, s - 64), s))
+    while len(pos) < count:
+        pos.add(st.below(s))
+    return np.array(sorted(pos))
+
+
+def _check_sampled(out_dev, A, X, s, seed):
+    torch.cuda.synchronize()
+    pos = _sample_positions(s, seed)
+    got = out_dev[:, :s].cpu().numpy()[:, pos]
+    want = O.apply(A, X[:, pos])
+    assert np.array_equal(got, want)
+
+
+def test_config1_msr_vanilla_k3_full():
+    """MSR vanilla (3,4,6), x_i = i+1, 1 MiB object: encode all parity,
+    repair node 0 from helpers 1..4, decode from nodes {3,4,5}; every byte."""
+    print("config1", flush=True)
+    S = 1 << 20
+    c = pm.Code(k=3, d=4, n=6, kind=pm.PM_MSR, construction=pm.PM_VANILLA, x=list(range(1, 7)))
+    o = O.Code(O.MSR, 3, 4, 6, O.VANILLA, True, x=np.arange(1, 7))
+    X, s = synth.split_object(S, c.B, synth.CONFIG_SEED + 0)
+    assert s == 174784
+    P = _gpu_encode(c, X, s)
+    assert np.array_equal(P, o.encode(X, nthreads=8))
+    nodes = _nodes(c, X, P)
+    recv = np.zeros((4, s), np.uint8)
+    for j, h in enumerate([1, 2, 3, 4]):
+        hb = out_regions(1, s)
+        c.repair_helper(0, to_regions(nodes[h]), hb, s)
+        recv[j] = read(hb, s)[0]
+    rout = out_regions(2, s)
+    c.repair_newcomer(0, [1, 2, 3, 4], to_regions(recv), rout, s)
+    assert np.array_equal(read(rout, s), nodes[0])
+    Y = np.concatenate([nodes[i] for i in (3, 4, 5)])
+    xo = out_regions(c.B, s)
+    c.decode([3, 4, 5], to_regions(Y), xo, s)
+    assert np.array_equal(read(xo, s), X)
+
+
+CFG2 = [
+    ("sparse-sys", dict(k=8, d=14, n=16, kind=pm.PM_MSR, construction=pm.PM_SPARSE)),
+    ("vanilla-nonsys", dict(k=8, d=14, n=16, kind=pm.PM_MSR, construction=pm.PM_VANILLA, systematic=False)),
+    ("vanilla-sys", dict(k=8, d=14, n=16, kind=pm.PM_MSR, construction=pm.PM_VANILLA)),
+    ("rs-16-8", dict(k=8, d=8, n=16, kind=pm.PM_RS)),
+]
+
+
+@pytest.mark.parametrize("name,kw", CFG2, ids=[c[0] for c in CFG2])
+def test_config2_encode_64mib_sampled(name, kw):
+    print("config2 %s" % name, flush=True)
+    c = pm.Code(**kw)
+    o = _oracle_for(kw)
+    X, s = synth.split_object(64 << 20, c.B, synth.CONFIG_SEED + 1)
+    xin = torch.from_numpy(X).to(device())
+    out = torch.empty((c.enc_rows, s), dtype=torch.uint8, device=device())
+    c.encode(xin, out, s)
+    _check_sampled(out, o.enc, X, s, seed=len(name))
+
+
+@pytest.mark.parametrize("name,kw", CFG2, ids=[c[0] for c in CFG2])
+def test_config2_codes_full_compare_small_object(name, kw):
+    """The same codes on an object spanning several tiles and a ragged tail."""
+    c = pm.Code(**kw)
+    o = _oracle_for(kw)
+    X, s = synth.split_object(c.B * 9000 + 37, c.B, 99, align=1)
+    assert np.array_equal(_gpu_encode(c, X, s), o.encode(X, nthreads=8))
+
+
+def test_config3_mbr_k8_full_size():
+    """MBR (8,14,16), 64 MiB: systematic encode (sampled), repair of node 0
+    (copy-only helpers) and node 8 from the first 14 survivors, decode from a
+    seeded random 8-subset (sampled outputs)."""
+    print("config3", flush=True)
+    c = pm.Code(k=8, d=14, n=16, kind=pm.PM_MBR)
+    o = O.Code(O.MBR, 8, 14, 16)
+    X, s = synth.split_object(64 << 20, c.B, synth.CONFIG_SEED + 2)
+    assert s == 798976
+    dev = device()
+    xin = torch.from_numpy(X).to(dev)
+    P = torch.empty((c.enc_rows, s), dtype=torch.uint8, device=dev)
+    c.encode(xin, P, s)
+    _check_sampled(P, o.enc, X, s, seed=3)
+    nm = c.node_map()
+
+    def node(i):
+        rows = [xin[v] if v < c.B else P[v - c.B] for v in nm[i * c.alpha:(i + 1) * c.alpha]]
+        return torch.stack(rows)
+
+    for f in (0, 8):
+        H = [i for i in range(c.n) if i != f][:c.d]
+        recv = torch.empty((c.d, s), dtype=torch.uint8, device=dev)
+        for j, h in enumerate(H):
+            c.repair_helper(f, node(h), recv[j:j + 1], s)
+        rout = torch.empty((c.alpha, s), dtype=torch.uint8, device=dev)
+        c.repair_newcomer(f, H, recv, rout, s)
+        torch.cuda.synchronize()
+        assert torch.equal(rout, node(f)), f
+    K = synth.Stream(synth.CONFIG_SEED + 2).subset(c.n, c.k)
+    Y = torch.cat([node(i) for i in K])
+    xo = torch.empty((c.B, s), dtype=torch.uint8, device=dev)
+    c.decode(K, Y, xo, s)
+    torch.cuda.synchronize()
+    assert torch.equal(xo, xin)
+
+
+@pytest.mark.parametrize("rg,vec", VARIANTS)
+def test_every_variant_encodes_identically(rg, vec):
+    c = pm.Code(k=8, d=14, n=16)
+    o = O.Code(O.MSR, 8, 14, 16, O.SPARSE)
+    X, s = synth.split_object(c.B * 20000 + 5, c.B, 5, align=1)
+    c.set_variant(pm.OP_ENCODE, rg, vec)
+    assert np.array_equal(_gpu_encode(c, X, s), o.encode(X, nthreads=8))
+
+
+def test_k16_sparse_encode_repair_decode():
+    c = pm.Code(k=16, d=30, n=32)
+    o = O.Code(O.MSR, 16, 30, 32, O.SPARSE)
+    s = 4096 + 48
+    X = _rand(16, c.B, s)
+    P = _gpu_encode(c, X, s)
+    assert np.array_equal(P, o.encode(X, nthreads=8))
+    nodes = _nodes(c, X, P)
+    st = synth.Stream(161)
+    for f in (0, 14, 15, 31):
+        H = st.subset(c.n, c.d, exclude=[f])
+        recv = np.stack([O.apply(o.helper_row(f), nodes[h])[0] for h in H])
+        rout = out_regions(c.alpha, s)
+        c.repair_newcomer(f, H, to_regions(recv), rout, s)
+        assert np.array_equal(read(rout, s), nodes[f])
+    for _ in range(3):
+        K = st.subset(c.n, c.k)
+        Y = np.concatenate([nodes[i] for i in K])
+        xo = out_regions(c.B, s)
+        c.decode(K, to_regions(Y), xo, s)
+        assert np.array_equal(read(xo, s), X)

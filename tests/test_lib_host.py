@@ -1,0 +1,115 @@
+"""Host-side checks of the HIP library (no GPU needed): the C ABI loads and
+exports every declared entry point, the library's own construction equals
+the oracle's byte for byte, and argument errors come back as statuses."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1412_3022_amd import pm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(pm_[a-z_]+)\s*\(", text))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = pm.lib()
+    declared = _declared()
+    assert {"pm_code_create", "pm_encode", "pm_repair_helper", "pm_repair_newcomer", "pm_decode"} <= declared
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+
+
+CODES = [
+    dict(k=3, d=4, n=6, kind=pm.PM_MSR, construction=pm.PM_VANILLA, x=list(range(1, 7))),
+    dict(k=3, d=4, n=6, kind=pm.PM_MSR, construction=pm.PM_SPARSE),
+    dict(k=4, d=6, n=8, kind=pm.PM_MSR, construction=pm.PM_SPARSE),
+    dict(k=8, d=14, n=16, kind=pm.PM_MSR, construction=pm.PM_SPARSE),
+    dict(k=8, d=14, n=15, kind=pm.PM_MSR, construction=pm.PM_SPARSE),
+    dict(k=16, d=30, n=32, kind=pm.PM_MSR, construction=pm.PM_SPARSE),
+    dict(k=8, d=14, n=16, kind=pm.PM_MSR, construction=pm.PM_VANILLA),
+    dict(k=8, d=14, n=16, kind=pm.PM_MSR, construction=pm.PM_VANILLA, systematic=False),
+    dict(k=8, d=14, n=16, kind=pm.PM_MSR, construction=pm.PM_SPARSE, systematic=False),
+    dict(k=3, d=4, n=6, kind=pm.PM_MBR),
+    dict(k=8, d=14, n=16, kind=pm.PM_MBR),
+    dict(k=5, d=5, n=7, kind=pm.PM_MBR),
+    dict(k=8, d=8, n=16, kind=pm.PM_RS),
+]
+
+
+def _oracle_code(kw):
+    kind = {pm.PM_MSR: O.MSR, pm.PM_MBR: O.MBR, pm.PM_RS: O.RS}[kw["kind"]]
+    cons = O.VANILLA if kw.get("construction", pm.PM_SPARSE) == pm.PM_VANILLA else O.SPARSE
+    x = np.array(kw["x"]) if "x" in kw else None
+    return O.Code(kind, kw["k"], kw["d"], kw["n"], cons, kw.get("systematic", True), x=x)
+
+
+@pytest.mark.parametrize("kw", CODES, ids=lambda kw: "%d-%d-%d-%d-%d" % (kw["kind"], kw.get("construction", 1),
+                                                                        kw["k"], kw["d"], kw["n"]))
+def test_construction_matches_oracle(kw):
+    c = pm.Code(**kw)
+    o = _oracle_code(kw)
+    assert (c.alpha, c.B, c.enc_rows) == (o.alpha, o.B, o.enc.shape[0])
+    assert np.array_equal(c.matrix(pm.MAT_PSI), o.psi)
+    assert np.array_equal(c.matrix(pm.MAT_G), o.G)
+    assert np.array_equal(c.matrix(pm.MAT_GSYS), o.Gsys)
+    assert np.array_equal(c.matrix(pm.MAT_ENC), o.enc)
+    if kw["kind"] == pm.PM_MSR:
+        assert np.array_equal(c.matrix(pm.MAT_LAMBDA)[0], o.lam)
+    nm = c.node_map()
+    for t, (src, idx) in enumerate(o.node_map):
+        assert nm[t] == (idx if src == "x" else c.B + idx)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(k=16, d=30, n=32, kind=pm.PM_MSR, construction=pm.PM_VANILLA), pm.PM_EUNSUPPORTED),
+    (dict(k=8, d=13, n=16, kind=pm.PM_MSR, construction=pm.PM_SPARSE), pm.PM_EUNSUPPORTED),
+    (dict(k=8, d=14, n=17, kind=pm.PM_MSR, construction=pm.PM_SPARSE), pm.PM_EUNSUPPORTED),
+    (dict(k=40, d=78, n=79, kind=pm.PM_MSR, construction=pm.PM_SPARSE), pm.PM_EUNSUPPORTED),
+    (dict(k=8, d=14, n=14, kind=pm.PM_MSR, construction=pm.PM_SPARSE), pm.PM_EINVAL),
+    (dict(k=8, d=14, n=300, kind=pm.PM_MSR, construction=pm.PM_VANILLA), pm.PM_EINVAL),
+    (dict(k=8, d=7, n=16, kind=pm.PM_MBR), pm.PM_EINVAL),
+    (dict(k=8, d=14, n=16, kind=pm.PM_MSR, construction=pm.PM_SPARSE, w=16), pm.PM_EUNSUPPORTED),
+    (dict(k=3, d=4, n=6, kind=pm.PM_MSR, construction=pm.PM_VANILLA, x=[1, 2, 3, 4, 5, 5]), pm.PM_EINVAL),
+])
+def test_create_errors(kw, status):
+    st, h = pm.pm_code_create(**kw)
+    assert st == status
+    assert not h
+
+
+def test_data_call_argument_errors_need_no_gpu():
+    c = pm.Code(k=4, d=6, n=8)
+    # NULL / misaligned regions and zero sizes are rejected before any device work
+    assert pm.pm_encode(c.h, 0, 64, 0, 64, 64) == pm.PM_EINVAL
+    assert pm.pm_encode(c.h, 16, 64, 4096, 64, 0) == pm.PM_EINVAL
+    assert pm.pm_encode(c.h, 8, 64, 4096, 64, 64) == pm.PM_EINVAL         # misaligned base
+    assert pm.pm_encode(c.h, 4096, 24, 1 << 20, 64, 16) == pm.PM_EINVAL   # ld not a multiple of 16
+    assert pm.pm_encode(c.h, 4096, 64, 1 << 20, 64, 128) == pm.PM_EINVAL  # ld < block_bytes
+    assert pm.pm_encode(c.h, 4096, 64, 4096 + 64, 64, 64) == pm.PM_EINVAL  # overlap
+    assert pm.pm_repair_helper(c.h, 99, 4096, 64, 1 << 20, 64) == pm.PM_EINVAL
+    assert pm.pm_repair_newcomer(c.h, 0, [1, 2, 3, 4, 5, 5], 4096, 64, 1 << 20, 64, 64) == pm.PM_EINVAL
+    assert pm.pm_repair_newcomer(c.h, 0, [0, 2, 3, 4, 5, 6], 4096, 64, 1 << 20, 64, 64) == pm.PM_EINVAL
+    assert pm.pm_decode(c.h, [0, 1, 2, 2], 4096, 64, 1 << 20, 64, 64) == pm.PM_EINVAL
+    assert pm.pm_decode(c.h, [0, 1, 2, 9], 4096, 64, 1 << 20, 64, 64) == pm.PM_EINVAL
+    assert pm.pm_set_variant(c.h, 0, 5, 4) == pm.PM_EINVAL
+    assert pm.pm_set_variant(c.h, 0, 8, 3) == pm.PM_EINVAL
+    assert pm.pm_set_variant(c.h, 0, 8, 4) == pm.PM_OK
+    assert pm.pm_set_variant(c.h, 0, 0, 0) == pm.PM_OK
+
+
+def test_status_strings():
+    for st in range(-6, 1):
+        assert pm.status_string(st)
