@@ -1,0 +1,328 @@
+#!/usr/bin/env python3
+"""Benchmark of the PM regenerating-code hot path on one MI355X.
+
+Headline: GB/s of source bytes for the systematic sparse PM-MSR k=8, d=14,
+n=16 encode of a 64 MiB object (56 sub-blocks of 1 198 400 B), one plain
+launch per object, inputs resident in HBM.  A step encodes one object; K
+steps rotate over 8 buffer sets (1 GiB) so the 256 MB Infinity Cache cannot
+serve them.  The kernel's average launch time comes from HIP events on the
+launch stream; the roofline figure divides the launch's algorithmic bytes
+(read B sub-blocks, write the (n-k) alpha parity sub-blocks) by it.
+
+Beside the headline the JSON line carries the other configuration-2 encodes
+(vanilla non-systematic, vanilla systematic, Reed-Solomon), the MBR k=8
+encode/repair/decode of configuration 3, and the CPU oracle timed on the host
+cores over a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+NBUF = 8
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_msr_k8_sparse_encode_64MiB.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1412_3022_amd", "csrc", "kernels.hip")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-extra", action="store_true", help="headline only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--sweep", action="store_true", help="print the headline kernel time of every variant")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
+    return ap.parse_args()
+
+
+def calibrate_copy(torch, reps=10):
+    """A plain device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE
+    counters convert the engine's counters into HBM bytes."""
+    n = 1 << 30
+    src = torch.randint(0, 255, (n,), dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes": n, "reps": reps}), flush=True)
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    if not os.path.exists(PROFILE_TRAFFIC):
+        return None
+    vals = {}
+    with open(PROFILE_TRAFFIC) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_sha256_16") != kernel_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+class Timer:
+    """Wall clock plus HIP events on the stream the kernels run on."""
+
+    def __init__(self, torch):
+        self.torch = torch
+
+    def run(self, fn, steps, warmup):
+        torch = self.torch
+        for i in range(warmup):
+            fn(i)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for i in range(steps):
+            fn(i)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return wall, e0.elapsed_time(e1) / 1e3
+
+
+def encode_case(torch, pm, synth, kw, S, seed, steps, warmup, nbuf=NBUF, tune=True, sweep=False):
+    dev = torch.device("cuda:0")
+    code = pm.Code(**kw)
+    X, s = synth.split_object(S, code.B, seed)
+    xs = [torch.from_numpy(X).to(dev) for _ in range(nbuf)]
+    outs = [torch.empty((code.enc_rows, s), dtype=torch.uint8, device=dev) for _ in range(nbuf)]
+    stream = torch.cuda.current_stream().cuda_stream
+    variant = None
+    if sweep:
+        for rg in (4, 8, 16):
+            for vec in (2, 4, 12, 14):
+                code.set_variant(pm.OP_ENCODE, rg, vec)
+                def one(i):
+                    j = i % nbuf
+                    pm.pm_encode(code.h, xs[j].data_ptr(), s, outs[j].data_ptr(), s, s, stream)
+                _, ev = Timer(torch).run(one, 40, 4)
+                print(json.dumps({"variant": [rg, vec], "kernel_us": round(ev / 40 * 1e6, 2)}), file=sys.stderr,
+                      flush=True)
+        code.set_variant(pm.OP_ENCODE, 0, 0)
+    if tune:
+        st, rg, vec = pm.pm_autotune_encode(code.h, xs[0].data_ptr(), s, outs[0].data_ptr(), s, s, 10, stream)
+        if st != pm.PM_OK:
+            raise pm.PMError(st, "pm_autotune_encode")
+        variant = [rg, vec]
+
+    def step(i):
+        j = i % nbuf
+        st = pm.pm_encode(code.h, xs[j].data_ptr(), s, outs[j].data_ptr(), s, s, stream)
+        if st != pm.PM_OK:
+            raise pm.PMError(st, "pm_encode")
+
+    wall, ev = Timer(torch).run(step, steps, warmup)
+    alg_bytes = (code.B + code.enc_rows) * s
+    res = {"source_bytes": S, "block_bytes": s, "wall_s": wall, "event_s": ev,
+           "gbps": S * steps / wall / 1e9, "kernel_us": ev / steps * 1e6,
+           "alg_bytes_per_launch": alg_bytes, "hbm_gbps": alg_bytes * steps / ev / 1e9, "variant": variant}
+    del xs, outs
+    return code, res
+
+
+def mbr_cases(torch, pm, synth, steps, warmup):
+    """Configuration 3: PM-MBR (8,14,16), 64 MiB: encode, repair of node 8 from
+    14 helpers (helper projections + newcomer solve), decode from a seeded
+    random 8-subset."""
+    dev = torch.device("cuda:0")
+    code = pm.Code(k=8, d=14, n=16, kind=pm.PM_MBR)
+    S = 64 << 20
+    X, s = synth.split_object(S, code.B, synth.CONFIG_SEED + 2)
+    x = torch.from_numpy(X).to(dev)
+    P = torch.empty((code.enc_rows, s), dtype=torch.uint8, device=dev)
+    code.encode(x, P, s)
+    nm = code.node_map()
+
+    def node(i):
+        return torch.stack([x[v] if v < code.B else P[v - code.B] for v in nm[i * code.alpha:(i + 1) * code.alpha]])
+
+    out = {}
+    stream = torch.cuda.current_stream().cuda_stream
+    P2 = torch.empty_like(P)
+    wall, ev = Timer(torch).run(lambda i: pm.pm_encode(code.h, x.data_ptr(), s, P2.data_ptr(), s, s, stream),
+                                steps, warmup)
+    out["mbr_encode_gbps"] = S * steps / wall / 1e9
+    f = 8
+    H = [i for i in range(code.n) if i != f][:code.d]
+    nodes = [node(h) for h in H]
+    recv = torch.empty((code.d, s), dtype=torch.uint8, device=dev)
+    rout = torch.empty((code.alpha, s), dtype=torch.uint8, device=dev)
+
+    def repair(i):
+        for j, h in enumerate(H):
+            pm.pm_repair_helper(code.h, f, nodes[j].data_ptr(), s, recv[j].data_ptr(), s, stream)
+        pm.pm_repair_newcomer(code.h, f, H, recv.data_ptr(), s, rout.data_ptr(), s, s, stream)
+
+    wall, ev = Timer(torch).run(repair, max(1, steps // 4), max(1, warmup // 4))
+    out["mbr_repair_gbps"] = code.alpha * s * max(1, steps // 4) / wall / 1e9   # repaired bytes
+    K = synth.Stream(synth.CONFIG_SEED + 2).subset(code.n, code.k)
+    Y = torch.cat([node(i) for i in K])
+    xo = torch.empty_like(x)
+    wall, ev = Timer(torch).run(lambda i: pm.pm_decode(code.h, K, Y.data_ptr(), s, xo.data_ptr(), s, s, stream),
+                                max(1, steps // 4), max(1, warmup // 4))
+    out["mbr_decode_gbps"] = S * max(1, steps // 4) / wall / 1e9
+    out["mbr_decode_nodes"] = K
+    return out
+
+
+def msr_repair_decode(torch, pm, synth, steps, warmup):
+    """PM-MSR (8,14,16) sparse on the configuration-2 object: repair of node 8
+    (full helpers) and decode from a seeded random 8-subset."""
+    dev = torch.device("cuda:0")
+    code = pm.Code(k=8, d=14, n=16)
+    S = 64 << 20
+    X, s = synth.split_object(S, code.B, synth.CONFIG_SEED + 1)
+    x = torch.from_numpy(X).to(dev)
+    P = torch.empty((code.enc_rows, s), dtype=torch.uint8, device=dev)
+    code.encode(x, P, s)
+    nm = code.node_map()
+
+    def node(i):
+        return torch.stack([x[v] if v < code.B else P[v - code.B] for v in nm[i * code.alpha:(i + 1) * code.alpha]])
+
+    stream = torch.cuda.current_stream().cuda_stream
+    out = {}
+    f = 8
+    H = [i for i in range(code.n) if i != f][:code.d]
+    nodes = [node(h) for h in H]
+    recv = torch.empty((code.d, s), dtype=torch.uint8, device=dev)
+    rout = torch.empty((code.alpha, s), dtype=torch.uint8, device=dev)
+
+    def repair(i):
+        for j, h in enumerate(H):
+            pm.pm_repair_helper(code.h, f, nodes[j].data_ptr(), s, recv[j].data_ptr(), s, stream)
+        pm.pm_repair_newcomer(code.h, f, H, recv.data_ptr(), s, rout.data_ptr(), s, s, stream)
+
+    n = max(1, steps // 4)
+    wall, ev = Timer(torch).run(repair, n, max(1, warmup // 4))
+    out["msr_repair_gbps"] = code.alpha * s * n / wall / 1e9
+    K = synth.Stream(synth.CONFIG_SEED + 1).subset(code.n, code.k)
+    Y = torch.cat([node(i) for i in K])
+    xo = torch.empty_like(x)
+    wall, ev = Timer(torch).run(lambda i: pm.pm_decode(code.h, K, Y.data_ptr(), s, xo.data_ptr(), s, s, stream),
+                                n, max(1, warmup // 4))
+    out["msr_decode_gbps"] = S * n / wall / 1e9
+    out["msr_decode_nodes"] = K
+    return out
+
+
+def cpu_baseline(synth, budget_s=12.0):
+    """The oracle (plain log/antilog C) on the host cores: the same encode on
+    a bounded sample -- the first `w` bytes of every sub-block of the
+    configuration-2 object -- doubled until it runs for a few seconds."""
+    import numpy as np
+    import oracle as O
+    threads = min(os.cpu_count() or 1, 16)
+    code = O.Code(O.MSR, 8, 14, 16, O.SPARSE)
+    X, s = synth.split_object(64 << 20, code.B, synth.CONFIG_SEED + 1)
+    w = 4096
+    while True:
+        sample = np.ascontiguousarray(X[:, :w])
+        t0 = time.perf_counter()
+        O.apply(code.enc, sample, nthreads=threads)
+        dt = time.perf_counter() - t0
+        if dt > budget_s / 4 or w >= s:
+            break
+        w = min(s, w * 2)
+    src = code.B * w
+    return {"value": src / dt / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": "first %d B of each of the 56 sub-blocks of the 64 MiB object (%d source bytes), "
+                      "sparse systematic k=8 encode, %.2f s" % (w, src, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the method shards with no exchange; see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1412_3022_amd import pm, synth
+    if not torch.cuda.is_available():
+        print("no ROCm GPU visible", file=sys.stderr)
+        sys.exit(1)
+    if args.calibrate_copy:
+        calibrate_copy(torch)
+        return
+    pm.lib()
+
+    S = 64 << 20
+    head_kw = dict(k=8, d=14, n=16, kind=pm.PM_MSR, construction=pm.PM_SPARSE)
+    code, head = encode_case(torch, pm, synth, head_kw, S, synth.CONFIG_SEED + 1, args.steps, args.warmup,
+                             sweep=args.sweep)
+    extra = {"headline_kernel_us": round(head["kernel_us"], 3), "headline_variant": head["variant"],
+             "headline_event_gbps": round(S / (head["kernel_us"] * 1e-6) / 1e9, 2)}
+    if not args.no_extra:
+        others = [
+            ("msr_vanilla_nonsys", dict(k=8, d=14, n=16, kind=pm.PM_MSR, construction=pm.PM_VANILLA,
+                                        systematic=False)),
+            ("msr_vanilla_sys", dict(k=8, d=14, n=16, kind=pm.PM_MSR, construction=pm.PM_VANILLA)),
+            ("rs_16_8", dict(k=8, d=8, n=16, kind=pm.PM_RS)),
+        ]
+        for name, kw in others:
+            _, r = encode_case(torch, pm, synth, kw, S, synth.CONFIG_SEED + 1, max(20, args.steps // 4),
+                               max(2, args.warmup // 4))
+            extra[name + "_encode_gbps"] = round(r["gbps"], 2)
+        extra.update({k: (round(v, 2) if isinstance(v, float) else v)
+                      for k, v in msr_repair_decode(torch, pm, synth, args.steps, args.warmup).items()})
+        extra.update({k: (round(v, 2) if isinstance(v, float) else v)
+                      for k, v in mbr_cases(torch, pm, synth, args.steps, args.warmup).items()})
+
+    achieved = head["alg_bytes_per_launch"] / (head["kernel_us"] * 1e-6) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": measured_traffic(),
+            "kernel": "pm_apply_kernel", "alg_bytes_per_launch": head["alg_bytes_per_launch"]}
+    line = {
+        "metric": "encode GB/s (source bytes) PM-MSR k=8 d=14 at 1 GPU",
+        "value": round(head["gbps"], 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["wall_s"] / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic (splitmix64 uniform bytes, seed 0x5EED0001)",
+        "config": {"workload": "PM-MSR sparse systematic encode k=8 d=14 n=16 GF(2^8), 64 MiB object "
+                               "as 56 x 1198400 B sub-blocks, plain single launch per object",
+                   "source_bytes_per_step": S, "buffer_sets": NBUF},
+        "roofline": roof,
+        "extra": extra,
+        "paper_context": {"sparse_sys_k8_MBps": 790, "vanilla_sys_k8_MBps": 210, "rs_k8_MBps": 1640,
+                          "cpu": "Xeon E5-2640 2.5 GHz, 1 core, 16 KB blocks"},
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(synth)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

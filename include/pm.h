@@ -150,10 +150,70 @@ pm_status pm_apply(const uint8_t *A, uint32_t rows, uint32_t cols, const uint8_t
 
 /* Kernel variant for one operation of a code (set by the autotuner or the
  * caller).  op: 0 encode, 1 repair helper, 2 repair newcomer, 3 decode,
- * 4 pm_apply (global).  rows_per_group in {4, 8, 16}, dwords_per_lane in
- * {2, 4}; 0, 0 restores the built-in cost model. */
+ * 4 pm_apply (global).  rows_per_group in {4, 8, 16}: output rows held in
+ * registers per work unit; dwords_per_lane in {2, 4} (8 or 16 bytes per lane
+ * per source block), plus 10 to stage the coefficient tables in LDS instead
+ * of reading them through the scalar cache (12, 14).  0, 0 restores the
+ * built-in cost model.  PM_EINVAL for other values. */
 pm_status pm_set_variant(pm_code *code, int op, uint32_t rows_per_group,
                          uint32_t dwords_per_lane);
+
+/* Autotuner for encode: times every kernel variant on the caller's buffers
+ * (X, out as for pm_encode; reps launches each, HIP events on `stream`),
+ * keeps the fastest for this code and reports it.  Synchronous: returns after
+ * the timing runs; out holds a valid encoding afterwards. */
+pm_status pm_autotune_encode(pm_code *code, const uint8_t *X, size_t x_ld, uint8_t *out,
+                             size_t out_ld, size_t block_bytes, uint32_t reps, pm_stream stream,
+                             uint32_t *best_rows_per_group, uint32_t *best_dwords_per_lane);
+
+/* ---- Batched launches (project addition beyond the paper) ----------------
+ * Many independent operations -- objects of different sizes and codes,
+ * encode, repair and decode mixed -- run as one persistent work-list launch
+ * per row-group size, with the waves of the whole GPU pulling (item, row
+ * group, byte tile) units from per-XCD queues.  The plan fixes every pointer
+ * and size; a run only enqueues. */
+typedef struct {
+    const pm_code *code;
+    int32_t op;            /* 0 encode, 1 repair helper, 2 repair newcomer, 3 decode */
+    uint32_t failed;       /* op 1, 2: the failed node */
+    const uint32_t *ids;   /* op 2: d helper ids; op 3: k node ids (host, read
+                              during pm_batch_plan only); NULL otherwise */
+    const uint8_t *in;     /* device region set, as for the single calls */
+    size_t in_ld;
+    uint8_t *out;
+    size_t out_ld;         /* ignored for op 1 (one output block) */
+    size_t block_bytes;
+} pm_batch_item;
+
+typedef struct pm_batch pm_batch;
+
+#define PM_BATCH_GRAPH 1u  /* capture the launches in a HIP graph on the first
+                              run and replay it afterwards */
+
+/* Resolve every item (building repair / decode matrices as needed), check
+ * its regions as the single calls do, and upload the work lists.  Blocks
+ * until the uploads land.  The items array is not kept. */
+pm_status pm_batch_plan(const pm_batch_item *items, size_t n, uint32_t flags, pm_batch **out);
+
+/* Tile width of the work lists: dwords_per_lane 2 or 4 (8 or 16 bytes per
+ * lane per block) for the size class with rows_per_group rows (0 = all). */
+pm_status pm_batch_set_variant(pm_batch *batch, uint32_t rows_per_group, uint32_t dwords_per_lane);
+
+/* Autotuner: times each tile width per size class (reps runs each, HIP
+ * events on `stream`), keeps the fastest and reports the last class's pick.
+ * Synchronous; overwrites the items' outputs with valid results. */
+pm_status pm_batch_autotune(pm_batch *batch, uint32_t reps, pm_stream stream,
+                            uint32_t *best_dwords_per_lane);
+
+/* Enqueue all items on `stream`.  Runs of one batch share its queue heads,
+ * so they must be ordered (one stream, or events between streams). */
+pm_status pm_batch_run(pm_batch *batch, pm_stream stream);
+
+/* Work units (item x row group x wave tile) and size classes of a plan. */
+pm_status pm_batch_info(const pm_batch *batch, uint64_t *units, uint32_t *size_classes);
+
+/* Free a plan; no run of it may still be in flight. */
+void pm_batch_destroy(pm_batch *batch);
 
 /* Message of the last failing HIP call on this thread ("" if none). */
 const char *pm_last_hip_error(void);

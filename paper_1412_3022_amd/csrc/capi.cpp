@@ -84,6 +84,21 @@ int ProgEntry::device_ptr(hipStream_t user, const uint32_t **out) {
     return ST_OK;
 }
 
+int ProgEntry::device_ptr_sync(const uint32_t **out) {
+    int st = device_ptr(nullptr, out);
+    if (st != ST_OK) return st;
+    int devid = 0;
+    hipError_t e = hipGetDevice(&devid);
+    if (e != hipSuccess) return hip_fail(e);
+    std::lock_guard<std::mutex> lk(mu);
+    DevCopy &dc = dev[devid];
+    if (!dc.done) {
+        if ((e = hipEventSynchronize(dc.ready)) != hipSuccess) return hip_fail(e);
+        dc.done = true;
+    }
+    return ST_OK;
+}
+
 // ---- variant choice ----------------------------------------------------------
 // VALU cost per lane dword of a program: each evaluated slot costs three
 // byte-permutes and 1.5 three-input XORs plus its share of table moves; each
@@ -220,6 +235,83 @@ int pick_rg_cached(Variant &v, const Mat &A) {
 
 }  // namespace
 
+namespace pmrc {
+
+// Matrix, program and region counts of one operation of a code; builds and
+// caches the per-failure-pattern matrices (the initialization phase).
+int resolve_op(pm_code *c, int op, uint32_t failed, const uint32_t *ids, Resolved *r) {
+    if (!c) return ST_EINVAL;
+    const CodeMats &m = c->m;
+    if ((op == OPK_HELPER || op == OPK_NEWCOMER) && failed >= static_cast<uint32_t>(m.n)) return ST_EINVAL;
+    std::vector<int> list;
+    if (op == OPK_NEWCOMER || op == OPK_DECODE) {
+        if (!ids) return ST_EINVAL;
+        const int cnt = op == OPK_NEWCOMER ? m.d : m.k;
+        list.assign(ids, ids + cnt);
+        std::vector<int> sorted = list;
+        std::sort(sorted.begin(), sorted.end());
+        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) return ST_EINVAL;
+        for (int v : list)
+            if (v < 0 || v >= m.n || (op == OPK_NEWCOMER && v == static_cast<int>(failed))) return ST_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(c->mu);
+    const Variant &var = c->var[op];
+    r->vec = var.vec ? var.vec : 4;
+    switch (op) {
+        case OPK_ENCODE: {
+            const int rg = pick_rg_cached(c->var[0], m.enc);
+            r->pe = get_prog(c->enc, std::make_tuple(rg), m.enc, {});
+            r->in_n = static_cast<size_t>(m.B);
+            r->out_n = static_cast<size_t>(m.enc.rows);
+            return ST_OK;
+        }
+        case OPK_HELPER: {
+            auto it = c->helper_mat.find(static_cast<int>(failed));
+            if (it == c->helper_mat.end())
+                it = c->helper_mat.emplace(static_cast<int>(failed), helper_row(m, static_cast<int>(failed))).first;
+            const int rg = var.rg ? var.rg : 4;
+            r->pe = get_prog(c->helper, std::make_pair(static_cast<int>(failed), rg), it->second, {});
+            r->in_n = static_cast<size_t>(m.kind == KIND_RS ? 1 : m.alpha);
+            r->out_n = 1;
+            return ST_OK;
+        }
+        case OPK_NEWCOMER: {
+            auto key = std::make_pair(static_cast<int>(failed), list);
+            auto it = c->newcomer_mat.find(key);
+            if (it == c->newcomer_mat.end()) {
+                Mat R;
+                int st = newcomer_matrix(m, static_cast<int>(failed), list, R);
+                if (st != ST_OK) return st;
+                it = c->newcomer_mat.emplace(key, std::move(R)).first;
+            }
+            const int rg = pick_rg_cached(c->var[2], it->second);
+            r->pe = get_prog(c->newcomer, std::make_tuple(static_cast<int>(failed), list, rg), it->second, {});
+            r->in_n = static_cast<size_t>(m.d);
+            r->out_n = static_cast<size_t>(it->second.rows);
+            return ST_OK;
+        }
+        case OPK_DECODE: {
+            auto it = c->decode_mat.find(list);
+            if (it == c->decode_mat.end()) {
+                Mat D;
+                std::vector<int> used;
+                int st = decode_matrix(m, list, D, used);
+                if (st != ST_OK) return st;
+                it = c->decode_mat.emplace(list, std::make_pair(std::move(D), std::move(used))).first;
+            }
+            const int rg = pick_rg_cached(c->var[3], it->second.first);
+            r->pe = get_prog(c->decode, std::make_pair(list, rg), it->second.first, it->second.second);
+            r->in_n = static_cast<size_t>(m.k) * static_cast<size_t>(m.alpha);
+            r->out_n = static_cast<size_t>(m.B);
+            return ST_OK;
+        }
+        default:
+            return ST_EINVAL;
+    }
+}
+
+}  // namespace pmrc
+
 extern "C" {
 
 const char *pm_status_string(pm_status st) {
@@ -309,7 +401,8 @@ pm_status pm_code_node_map(const pm_code *c, int32_t *map, size_t cap) {
 
 pm_status pm_set_variant(pm_code *c, int op, uint32_t rg, uint32_t vec) {
     const bool reset = rg == 0 && vec == 0;
-    if (!reset && ((rg != 4 && rg != 8 && rg != 16) || (vec != 2 && vec != 4))) return PM_EINVAL;
+    if (!reset && ((rg != 4 && rg != 8 && rg != 16) || (vec != 2 && vec != 4 && vec != 12 && vec != 14)))
+        return PM_EINVAL;
     if (op == 4) {
         set_apply_variant(static_cast<int>(rg), static_cast<int>(vec));
         return PM_OK;
@@ -323,108 +416,42 @@ pm_status pm_set_variant(pm_code *c, int op, uint32_t rg, uint32_t vec) {
 
 pm_status pm_encode(const pm_code *cc, const uint8_t *X, size_t x_ld, uint8_t *out, size_t out_ld,
                     size_t s, pm_stream stream) {
-    pm_code *c = const_cast<pm_code *>(cc);
-    if (!c || s == 0) return PM_EINVAL;
-    ProgEntry *pe;
-    int vec;
-    {
-        std::lock_guard<std::mutex> lk(c->mu);
-        const int rg = pick_rg_cached(c->var[0], c->m.enc);
-        vec = c->var[0].vec ? c->var[0].vec : 4;
-        pe = get_prog(c->enc, std::make_tuple(rg), c->m.enc, {});
-    }
-    return static_cast<pm_status>(launch_program(*pe, vec, X, x_ld, static_cast<size_t>(c->m.B), out, out_ld,
-                                                 static_cast<size_t>(c->m.enc.rows), s,
+    if (s == 0) return PM_EINVAL;
+    Resolved r;
+    int st = resolve_op(const_cast<pm_code *>(cc), OPK_ENCODE, 0, nullptr, &r);
+    if (st != ST_OK) return static_cast<pm_status>(st);
+    return static_cast<pm_status>(launch_program(*r.pe, r.vec, X, x_ld, r.in_n, out, out_ld, r.out_n, s,
                                                  reinterpret_cast<hipStream_t>(stream)));
 }
 
 pm_status pm_repair_helper(const pm_code *cc, uint32_t failed, const uint8_t *node, size_t node_ld,
                            uint8_t *out, size_t s, pm_stream stream) {
-    pm_code *c = const_cast<pm_code *>(cc);
-    if (!c || s == 0 || failed >= static_cast<uint32_t>(c->m.n)) return PM_EINVAL;
-    ProgEntry *pe;
-    int vec;
-    {
-        std::lock_guard<std::mutex> lk(c->mu);
-        auto it = c->helper_mat.find(static_cast<int>(failed));
-        if (it == c->helper_mat.end())
-            it = c->helper_mat.emplace(static_cast<int>(failed), helper_row(c->m, static_cast<int>(failed))).first;
-        const int rg = c->var[1].rg ? c->var[1].rg : 4;
-        vec = c->var[1].vec ? c->var[1].vec : 4;
-        pe = get_prog(c->helper, std::make_pair(static_cast<int>(failed), rg), it->second, {});
-    }
-    const size_t in_n = static_cast<size_t>(c->m.kind == KIND_RS ? 1 : c->m.alpha);
+    if (s == 0) return PM_EINVAL;
+    Resolved r;
+    int st = resolve_op(const_cast<pm_code *>(cc), OPK_HELPER, failed, nullptr, &r);
+    if (st != ST_OK) return static_cast<pm_status>(st);
     const size_t out_ld = (s + 15) / 16 * 16;   // one output block: ld only has to be valid
-    return static_cast<pm_status>(launch_program(*pe, vec, node, node_ld, in_n, out, out_ld, 1, s,
+    return static_cast<pm_status>(launch_program(*r.pe, r.vec, node, node_ld, r.in_n, out, out_ld, 1, s,
                                                  reinterpret_cast<hipStream_t>(stream)));
 }
 
 pm_status pm_repair_newcomer(const pm_code *cc, uint32_t failed, const uint32_t *helpers, const uint8_t *recv,
                              size_t recv_ld, uint8_t *out, size_t out_ld, size_t s, pm_stream stream) {
-    pm_code *c = const_cast<pm_code *>(cc);
-    if (!c || !helpers || s == 0 || failed >= static_cast<uint32_t>(c->m.n)) return PM_EINVAL;
-    const int d = c->m.d;
-    std::vector<int> H(helpers, helpers + d);
-    {
-        std::vector<int> sorted = H;
-        std::sort(sorted.begin(), sorted.end());
-        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) return PM_EINVAL;
-        for (int h : H)
-            if (h < 0 || h >= c->m.n || h == static_cast<int>(failed)) return PM_EINVAL;
-    }
-    ProgEntry *pe;
-    int vec;
-    int out_rows;
-    {
-        std::lock_guard<std::mutex> lk(c->mu);
-        auto key = std::make_pair(static_cast<int>(failed), H);
-        auto it = c->newcomer_mat.find(key);
-        if (it == c->newcomer_mat.end()) {
-            Mat R;
-            int st = newcomer_matrix(c->m, static_cast<int>(failed), H, R);
-            if (st != ST_OK) return static_cast<pm_status>(st);
-            it = c->newcomer_mat.emplace(key, std::move(R)).first;
-        }
-        const int rg = pick_rg_cached(c->var[2], it->second);
-        vec = c->var[2].vec ? c->var[2].vec : 4;
-        out_rows = it->second.rows;
-        pe = get_prog(c->newcomer, std::make_tuple(static_cast<int>(failed), H, rg), it->second, {});
-    }
-    return static_cast<pm_status>(launch_program(*pe, vec, recv, recv_ld, static_cast<size_t>(d), out, out_ld,
-                                                 static_cast<size_t>(out_rows), s,
+    if (s == 0) return PM_EINVAL;
+    Resolved r;
+    int st = resolve_op(const_cast<pm_code *>(cc), OPK_NEWCOMER, failed, helpers, &r);
+    if (st != ST_OK) return static_cast<pm_status>(st);
+    return static_cast<pm_status>(launch_program(*r.pe, r.vec, recv, recv_ld, r.in_n, out, out_ld, r.out_n, s,
                                                  reinterpret_cast<hipStream_t>(stream)));
 }
 
 pm_status pm_decode(const pm_code *cc, const uint32_t *nodes, const uint8_t *Y, size_t y_ld, uint8_t *X,
                     size_t x_ld, size_t s, pm_stream stream) {
-    pm_code *c = const_cast<pm_code *>(cc);
-    if (!c || !nodes || s == 0) return PM_EINVAL;
-    std::vector<int> K(nodes, nodes + c->m.k);
-    {
-        std::vector<int> sorted = K;
-        std::sort(sorted.begin(), sorted.end());
-        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) return PM_EINVAL;
-        for (int v : K)
-            if (v < 0 || v >= c->m.n) return PM_EINVAL;
-    }
-    ProgEntry *pe;
-    int vec;
-    {
-        std::lock_guard<std::mutex> lk(c->mu);
-        auto it = c->decode_mat.find(K);
-        if (it == c->decode_mat.end()) {
-            Mat D;
-            std::vector<int> used;
-            int st = decode_matrix(c->m, K, D, used);
-            if (st != ST_OK) return static_cast<pm_status>(st);
-            it = c->decode_mat.emplace(K, std::make_pair(std::move(D), std::move(used))).first;
-        }
-        const int rg = pick_rg_cached(c->var[3], it->second.first);
-        vec = c->var[3].vec ? c->var[3].vec : 4;
-        pe = get_prog(c->decode, std::make_pair(K, rg), it->second.first, it->second.second);
-    }
-    const size_t in_n = static_cast<size_t>(c->m.k) * static_cast<size_t>(c->m.alpha);
-    return static_cast<pm_status>(launch_program(*pe, vec, Y, y_ld, in_n, X, x_ld, static_cast<size_t>(c->m.B), s,
+    if (s == 0) return PM_EINVAL;
+    Resolved r;
+    int st = resolve_op(const_cast<pm_code *>(cc), OPK_DECODE, 0, nodes, &r);
+    if (st != ST_OK) return static_cast<pm_status>(st);
+    return static_cast<pm_status>(launch_program(*r.pe, r.vec, Y, y_ld, r.in_n, X, x_ld, r.out_n, s,
                                                  reinterpret_cast<hipStream_t>(stream)));
 }
 
@@ -437,6 +464,48 @@ pm_status pm_apply(const uint8_t *A, uint32_t rows, uint32_t cols, const uint8_t
     ProgEntry *pe = apply_program(M, &vec);
     return static_cast<pm_status>(launch_program(*pe, vec, in, in_ld, cols, out, out_ld, rows, s,
                                                  reinterpret_cast<hipStream_t>(stream)));
+}
+
+pm_status pm_autotune_encode(pm_code *c, const uint8_t *X, size_t x_ld, uint8_t *out, size_t out_ld, size_t s,
+                             uint32_t reps, pm_stream stream, uint32_t *best_rg, uint32_t *best_vec) {
+    if (!c || s == 0 || reps == 0) return PM_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    hipError_t e;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return static_cast<pm_status>(hip_fail(e));
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return static_cast<pm_status>(hip_fail(e));
+    }
+    float best = 1e30f;
+    int brg = 0, bvec = 0;
+    pm_status rc = PM_OK;
+    for (int rg : {4, 8, 16}) {
+        for (int vec : {2, 4, 12, 14}) {
+            pm_set_variant(c, 0, static_cast<uint32_t>(rg), static_cast<uint32_t>(vec));
+            rc = pm_encode(c, X, x_ld, out, out_ld, s, stream);   // warm-up (and upload)
+            if (rc != PM_OK) break;
+            (void)hipEventRecord(e0, st);
+            for (uint32_t i = 0; i < reps && rc == PM_OK; ++i) rc = pm_encode(c, X, x_ld, out, out_ld, s, stream);
+            (void)hipEventRecord(e1, st);
+            if (rc != PM_OK) break;
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) { rc = static_cast<pm_status>(hip_fail(e)); break; }
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) { best = ms; brg = rg; bvec = vec; }
+        }
+        if (rc != PM_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != PM_OK) {
+        pm_set_variant(c, 0, 0, 0);
+        return rc;
+    }
+    pm_set_variant(c, 0, static_cast<uint32_t>(brg), static_cast<uint32_t>(bvec));
+    if (best_rg) *best_rg = static_cast<uint32_t>(brg);
+    if (best_vec) *best_vec = static_cast<uint32_t>(bvec);
+    return PM_OK;
 }
 
 }  // extern "C"

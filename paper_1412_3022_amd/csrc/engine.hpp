@@ -24,6 +24,8 @@ struct PmkApply {
 extern "C" hipError_t pmk_apply(int rg, int vec, const PmkApply *h, hipStream_t st);
 extern "C" int pmk_tile_bytes(int vec);
 
+struct pm_code;
+
 namespace pmrc {
 
 extern thread_local std::string g_hip_msg;
@@ -44,6 +46,8 @@ struct ProgEntry {
     std::map<int, DevCopy> dev;
     ~ProgEntry();
     int device_ptr(hipStream_t user, const uint32_t **out);
+    // Same, but returns only once the copy has landed (for plans and graphs).
+    int device_ptr_sync(const uint32_t **out);
 };
 
 struct Variant {
@@ -58,5 +62,16 @@ int launch_program(ProgEntry &pe, int vec, const uint8_t *in, size_t in_ld, size
 
 ProgEntry *apply_program(const Mat &A, int *vec);
 void set_apply_variant(int rg, int vec);
+
+enum OpKind { OPK_ENCODE = 0, OPK_HELPER = 1, OPK_NEWCOMER = 2, OPK_DECODE = 3 };
+
+// Program and region counts of one operation of a code.  ids: d helper ids
+// (newcomer) or k node ids (decode); failed: the failed node (repair).
+struct Resolved {
+    ProgEntry *pe = nullptr;
+    size_t in_n = 0, out_n = 0;
+    int vec = 4;
+};
+int resolve_op(pm_code *c, int op, uint32_t failed, const uint32_t *ids, Resolved *r);
 
 }  // namespace pmrc

@@ -101,13 +101,14 @@ Program build_program(const Mat &A, int rg, const std::vector<int> &in_map) {
     P.ngroups = static_cast<int>(groups.size());
 
     // Layout.
-    std::vector<uint32_t> rec, rowids, colids, tabs;
+    std::vector<uint32_t> rec, rowids, colids, tab4, tab1;
     auto in_col = [&](int c) { return static_cast<uint32_t>(in_map.empty() ? c : in_map[c]); };
     for (const Grp &g : groups) {
         uint32_t row_off = static_cast<uint32_t>(rowids.size());
         for (int r : g.rows) rowids.push_back(static_cast<uint32_t>(r));
         uint32_t col_off = static_cast<uint32_t>(colids.size());
-        uint32_t tab_off = static_cast<uint32_t>(tabs.size());
+        uint32_t tab4_off = static_cast<uint32_t>(tab4.size());
+        uint32_t tab1_off = static_cast<uint32_t>(tab1.size());
         uint32_t ncols = 0;
         if (g.kind == GROUP_COPY) {
             for (int r : g.rows) {
@@ -129,32 +130,37 @@ Program build_program(const Mat &A, int rg, const std::vector<int> &in_map) {
                     uint32_t t[kTabWords];
                     uint8_t coef = r < static_cast<int>(g.rows.size()) ? A.at(g.rows[r], cols[ci]) : 0;
                     pack_tables(coef, t);
-                    tabs.insert(tabs.end(), t, t + kTabWords);
+                    tab4.insert(tab4.end(), t, t + 4);
+                    tab1.push_back(t[4]);
                 }
             }
             if (pad) {
                 colids.push_back(in_col(cols.back()));
-                tabs.insert(tabs.end(), static_cast<size_t>(rg) * kTabWords, 0u);
+                tab4.insert(tab4.end(), static_cast<size_t>(rg) * 4, 0u);
+                tab1.insert(tab1.end(), static_cast<size_t>(rg), 0u);
             }
             ncols = static_cast<uint32_t>(cols.size() + (pad ? 1 : 0));
             P.slots += static_cast<long>(ncols) * rg;
+            P.max_group_slots = std::max(P.max_group_slots, static_cast<long>(ncols) * rg);
             P.col_reads += ncols;
         }
         uint32_t r8[kGroupWords] = {g.kind, static_cast<uint32_t>(g.rows.size()), ncols, col_off,
-                                    tab_off, row_off, 0, 0};
+                                    tab4_off, row_off, tab1_off, 0};
         rec.insert(rec.end(), r8, r8 + kGroupWords);
     }
     // Absolute word offsets.
     const uint32_t base_rows = kHeaderWords + static_cast<uint32_t>(rec.size());
     const uint32_t base_cols = base_rows + static_cast<uint32_t>(rowids.size());
-    uint32_t base_tabs = base_cols + static_cast<uint32_t>(colids.size());
-    base_tabs = (base_tabs + 15u) & ~15u;  // 64-byte aligned tables
+    uint32_t base_tab4 = base_cols + static_cast<uint32_t>(colids.size());
+    base_tab4 = (base_tab4 + 15u) & ~15u;  // 64-byte aligned tables
+    uint32_t base_tab1 = base_tab4 + static_cast<uint32_t>(tab4.size());
     for (size_t g = 0; g < groups.size(); ++g) {
         rec[g * kGroupWords + 3] += base_cols;
-        rec[g * kGroupWords + 4] += base_tabs;
+        rec[g * kGroupWords + 4] += base_tab4;
         rec[g * kGroupWords + 5] += base_rows;
+        rec[g * kGroupWords + 6] += base_tab1;
     }
-    P.blob.assign(base_tabs + tabs.size(), 0u);
+    P.blob.assign(base_tab1 + tab1.size(), 0u);
     P.blob[0] = static_cast<uint32_t>(P.ngroups);
     P.blob[1] = static_cast<uint32_t>(rg);
     P.blob[2] = static_cast<uint32_t>(A.rows);
@@ -162,7 +168,8 @@ Program build_program(const Mat &A, int rg, const std::vector<int> &in_map) {
     std::copy(rec.begin(), rec.end(), P.blob.begin() + kHeaderWords);
     std::copy(rowids.begin(), rowids.end(), P.blob.begin() + base_rows);
     std::copy(colids.begin(), colids.end(), P.blob.begin() + base_cols);
-    std::copy(tabs.begin(), tabs.end(), P.blob.begin() + base_tabs);
+    std::copy(tab4.begin(), tab4.end(), P.blob.begin() + base_tab4);
+    std::copy(tab1.begin(), tab1.end(), P.blob.begin() + base_tab1);
     return P;
 }
 

@@ -2,6 +2,8 @@
 // kernel: output rows are packed into groups of at most RG rows that read the
 // same input columns, so the kernel can keep one accumulator per group row in
 // registers and loop over the group's columns with no per-coefficient branch.
+// Group record: kind, rows, columns, then word offsets of the column ids, of
+// the 4-word table part, of the row ids and of the 1-word table part.
 // Each (group, column, row) slot carries the split product tables of its
 // coefficient: c*{0..7} (low 3 bits), c*{0,8,..,56} (middle 3 bits) and
 // c*{0,64,128,192} (top 2 bits), packed so that a byte-permute lookup with the
@@ -30,6 +32,7 @@ struct Program {
     long slots = 0;              // (group column x RG) slots the kernel evaluates
     long copies = 0;             // unit rows served by copy
     long col_reads = 0;          // sum over groups of columns read (input re-reads)
+    long max_group_slots = 0;    // largest (columns x RG) of one group: its table footprint
     std::vector<uint32_t> blob;  // header | groups | row ids | column ids | tables
 };
 

@@ -38,6 +38,14 @@ class pm_params(ctypes.Structure):
                 ("systematic", ctypes.c_uint32), ("x", ctypes.POINTER(ctypes.c_uint8))]
 
 
+class pm_batch_item(ctypes.Structure):
+    _fields_ = [("code", ctypes.c_void_p), ("op", ctypes.c_int32), ("failed", ctypes.c_uint32),
+                ("ids", ctypes.POINTER(ctypes.c_uint32)), ("in_", ctypes.c_void_p), ("in_ld", ctypes.c_size_t),
+                ("out", ctypes.c_void_p), ("out_ld", ctypes.c_size_t), ("block_bytes", ctypes.c_size_t)]
+
+
+PM_BATCH_GRAPH = 1
+
 _L = None
 
 
@@ -62,11 +70,21 @@ def _lib():
         L.pm_decode.argtypes = [vp, u32p, vp, sz, vp, sz, sz, vp]
         L.pm_apply.argtypes = [vp, u32, u32, vp, sz, vp, sz, sz, vp]
         L.pm_set_variant.argtypes = [vp, i32, u32, u32]
+        L.pm_autotune_encode.argtypes = [vp, vp, sz, vp, sz, sz, u32, vp, u32p, u32p]
+        L.pm_batch_plan.argtypes = [ctypes.POINTER(pm_batch_item), sz, u32, ctypes.POINTER(vp)]
+        L.pm_batch_set_variant.argtypes = [vp, u32, u32]
+        L.pm_batch_autotune.argtypes = [vp, u32, vp, u32p]
+        L.pm_batch_run.argtypes = [vp, vp]
+        L.pm_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), u32p]
+        L.pm_batch_destroy.argtypes = [vp]
+        L.pm_batch_destroy.restype = None
         L.pm_last_hip_error.restype = ctypes.c_char_p
         L.pm_status_string.argtypes = [i32]
         L.pm_status_string.restype = ctypes.c_char_p
         for name in ("pm_code_create", "pm_code_dims", "pm_code_matrix", "pm_code_node_map", "pm_encode",
-                     "pm_repair_helper", "pm_repair_newcomer", "pm_decode", "pm_apply", "pm_set_variant"):
+                     "pm_repair_helper", "pm_repair_newcomer", "pm_decode", "pm_apply", "pm_set_variant",
+                     "pm_autotune_encode", "pm_batch_plan", "pm_batch_set_variant", "pm_batch_autotune",
+                     "pm_batch_run", "pm_batch_info"):
             getattr(L, name).restype = i32
         _L = L
     return _L
@@ -134,6 +152,13 @@ def pm_apply(A, in_ptr, in_ld, out_ptr, out_ld, block_bytes, stream=0):
 
 def pm_set_variant(h, op, rows_per_group, dwords_per_lane):
     return _lib().pm_set_variant(h, op, rows_per_group, dwords_per_lane)
+
+
+def pm_autotune_encode(h, x_ptr, x_ld, out_ptr, out_ld, block_bytes, reps=5, stream=0):
+    rg, vec = ctypes.c_uint32(), ctypes.c_uint32()
+    st = _lib().pm_autotune_encode(h, x_ptr, x_ld, out_ptr, out_ld, block_bytes, reps, stream or None,
+                                   ctypes.byref(rg), ctypes.byref(vec))
+    return st, rg.value, vec.value
 
 
 # ---- convenience wrapper over torch tensors -------------------------------
@@ -226,3 +251,62 @@ def apply(A, inp, out, block_bytes, stream=None):
     ip, ild = _regions(inp, A.shape[1])
     op, old = _regions(out, A.shape[0])
     _check(pm_apply(A, ip, ild, op, old, block_bytes, _stream_handle(stream)), "pm_apply")
+
+
+# ---- batched launches -------------------------------------------------------
+OP_NAMES = {"encode": 0, "helper": 1, "newcomer": 2, "decode": 3}
+
+
+class Batch:
+    """A plan of many operations run as persistent work-list launches.
+
+    items: list of dicts with keys code (Code), op ("encode" | "helper" |
+    "newcomer" | "decode"), inp and out (2-D uint8 device tensors),
+    block_bytes, and failed / ids for repair and decode."""
+
+    def __init__(self, items, graph=True):
+        arr = (pm_batch_item * max(1, len(items)))()
+        keep = []
+        for i, it in enumerate(items):
+            code = it["code"]
+            e = arr[i]
+            e.code = code.h
+            e.op = OP_NAMES[it["op"]] if isinstance(it["op"], str) else int(it["op"])
+            e.failed = int(it.get("failed", 0))
+            ids = it.get("ids")
+            if ids is not None:
+                a = _u32arr(ids)
+                keep.append(a)
+                e.ids = ctypes.cast(a, ctypes.POINTER(ctypes.c_uint32))
+            inp, out = it["inp"], it["out"]
+            e.in_, e.in_ld = inp.data_ptr(), inp.stride(0)
+            e.out, e.out_ld = out.data_ptr(), (out.stride(0) if out.dim() == 2 else 16)
+            e.block_bytes = int(it["block_bytes"])
+        h = ctypes.c_void_p()
+        _check(_lib().pm_batch_plan(arr, len(items), PM_BATCH_GRAPH if graph else 0, ctypes.byref(h)),
+               "pm_batch_plan")
+        self.h = h.value
+        self.codes = [it["code"] for it in items]   # keep codes alive
+
+    def __del__(self):
+        import sys
+        h, self.h = getattr(self, "h", None), None
+        if h and _L is not None and not sys.is_finalizing():
+            _L.pm_batch_destroy(h)
+
+    def info(self):
+        u, c = ctypes.c_uint64(), ctypes.c_uint32()
+        _check(_lib().pm_batch_info(self.h, ctypes.byref(u), ctypes.byref(c)), "pm_batch_info")
+        return u.value, c.value
+
+    def set_variant(self, dwords_per_lane, rows_per_group=0):
+        _check(_lib().pm_batch_set_variant(self.h, rows_per_group, dwords_per_lane), "pm_batch_set_variant")
+
+    def autotune(self, reps=3, stream=None):
+        v = ctypes.c_uint32()
+        _check(_lib().pm_batch_autotune(self.h, reps, _stream_handle(stream), ctypes.byref(v)),
+               "pm_batch_autotune")
+        return v.value
+
+    def run(self, stream=None):
+        _check(_lib().pm_batch_run(self.h, _stream_handle(stream)), "pm_batch_run")

@@ -1,0 +1,152 @@
+"""Batched work-list launches: every item equals the oracle and the same
+operation run alone; graph replays give the same bytes every time."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from gpu_util import device
+from paper_1412_3022_amd import pm, synth
+
+pytestmark = pytest.mark.gpu
+
+CODES = [
+    ("msr4", dict(k=4, d=6, n=8), (O.MSR, 4, 6, 8, O.SPARSE)),
+    ("msr8", dict(k=8, d=14, n=16), (O.MSR, 8, 14, 16, O.SPARSE)),
+    ("msr16", dict(k=16, d=30, n=32), (O.MSR, 16, 30, 32, O.SPARSE)),
+    ("mbr8", dict(k=8, d=14, n=16, kind=pm.PM_MBR), (O.MBR, 8, 14, 16, O.SPARSE)),
+    ("rs", dict(k=8, d=8, n=16, kind=pm.PM_RS), (O.RS, 8, 8, 16, O.SPARSE)),
+]
+
+
+def _mixed_items(seed, count, max_bytes):
+    """A seeded mix of encode / helper / newcomer / decode items over the
+    codes above, with ragged block sizes; returns (items, expected)."""
+    st = synth.Stream(seed)
+    codes = {name: (pm.Code(**kw), O.Code(*ok)) for name, kw, ok in CODES}
+    names = [c[0] for c in CODES]
+    dev = device()
+    items, expected = [], []
+    for i in range(count):
+        name = names[st.below(len(names))]
+        c, o = codes[name]
+        s = 1 + st.below(max_bytes)
+        X = synth.random_bytes(seed * 7919 + i, c.B * s).reshape(c.B, s)
+        P = o.encode(X, nthreads=8)
+        nodes = {j: o.node_blocks(j, X, P) for j in range(c.n)}
+        op = ["encode", "helper", "newcomer", "decode"][st.below(4)]
+        ld = (s + 15) // 16 * 16 + 16 * st.below(3)
+        if op == "encode":
+            inp, want, extra = X, P, {}
+        elif op == "helper":
+            f = st.below(c.n)
+            h = [j for j in range(c.n) if j != f][st.below(c.n - 1)]
+            inp = nodes[h][:1] if c.kind == pm.PM_RS else nodes[h]
+            want = O.apply(o.helper_row(f), inp)
+            extra = {"failed": f}
+        elif op == "newcomer":
+            f = st.below(c.n)
+            H = st.subset(c.n, c.d, exclude=[f])
+            inp = np.stack([O.apply(o.helper_row(f), nodes[h])[0] for h in H])
+            want = nodes[f]
+            extra = {"failed": f, "ids": H}
+        else:
+            K = st.subset(c.n, c.k)
+            inp = np.concatenate([nodes[j] for j in K])
+            want = X
+            extra = {"ids": K}
+        tin = torch.zeros((inp.shape[0], ld), dtype=torch.uint8, device=dev)
+        tin[:, :s] = torch.from_numpy(np.ascontiguousarray(inp)).to(dev)
+        tout = torch.full((want.shape[0], ld), 0x5A, dtype=torch.uint8, device=dev)
+        it = dict(code=c, op=op, inp=tin, out=tout, block_bytes=s, **extra)
+        items.append(it)
+        expected.append(want)
+    return items, expected, codes
+
+
+def _check(items, expected):
+    torch.cuda.synchronize()
+    for it, want in zip(items, expected):
+        s = it["block_bytes"]
+        got = it["out"].cpu().numpy()
+        assert np.array_equal(got[:, :s], want), (it["op"], s)
+        assert np.all(got[:, s:] == 0x5A)
+
+
+@pytest.mark.parametrize("vec", [2, 4])
+def test_mixed_batch_matches_oracle(vec):
+    print("batch vec=%d" % vec, flush=True)
+    items, expected, codes = _mixed_items(11, 60, 3000)
+    b = pm.Batch(items, graph=False)
+    b.set_variant(vec)
+    units, classes = b.info()
+    assert units > 0 and classes >= 2
+    b.run()
+    _check(items, expected)
+
+
+def test_graph_replays_match_every_time():
+    print("batch graph replays", flush=True)
+    items, expected, codes = _mixed_items(12, 40, 5000)
+    b = pm.Batch(items, graph=True)
+    for rep in range(4):
+        for it in items:
+            it["out"].fill_(0x5A)          # eager work between replays
+        torch.cuda.synchronize()
+        b.run()
+        _check(items, expected)
+
+
+def test_batch_equals_single_calls_after_autotune():
+    print("batch autotune", flush=True)
+    items, expected, codes = _mixed_items(13, 30, 6000)
+    b = pm.Batch(items, graph=True)
+    vec = b.autotune(reps=2)
+    assert vec in (2, 4)
+    for it in items:
+        it["out"].fill_(0x5A)
+    b.run()
+    _check(items, expected)
+    # the same operations as single calls
+    for it, want in zip(items, expected):
+        c, s = it["code"], it["block_bytes"]
+        out = torch.full_like(it["out"], 0x5A)
+        if it["op"] == "encode":
+            c.encode(it["inp"], out, s)
+        elif it["op"] == "helper":
+            c.repair_helper(it["failed"], it["inp"], out, s)
+        elif it["op"] == "newcomer":
+            c.repair_newcomer(it["failed"], it["ids"], it["inp"], out, s)
+        else:
+            c.decode(it["ids"], it["inp"], out, s)
+        torch.cuda.synchronize()
+        assert torch.equal(out, it["out"])
+
+
+def test_config4_shape_scaled_down():
+    """Configuration-4 shape at reduced total size: 256 objects, sizes
+    log-uniform 4 KiB - 256 KiB, codes MSR (4,6), (8,14), (16,30) with n = 2k,
+    all encoded in one batch; sampled outputs checked against the oracle."""
+    print("config4 scaled", flush=True)
+    st = synth.Stream(synth.CONFIG_SEED + 3)
+    kinds = [(4, 6), (8, 14), (16, 30)]
+    codes = {k: (pm.Code(k=k, d=d, n=2 * k), O.Code(O.MSR, k, d, 2 * k, O.SPARSE)) for k, d in kinds}
+    dev = device()
+    items, hosts = [], []
+    for i in range(256):
+        k, d = kinds[st.below(3)]
+        c, o = codes[k]
+        S = st.log_uniform(4 << 10, 256 << 10)
+        X, s = synth.split_object(S, c.B, synth.CONFIG_SEED + 3 + 1000 * (i + 1))
+        xin = torch.from_numpy(X).to(dev)
+        out = torch.empty((c.enc_rows, s), dtype=torch.uint8, device=dev)
+        items.append(dict(code=c, op="encode", inp=xin, out=out, block_bytes=s))
+        hosts.append((o, X, s))
+    b = pm.Batch(items, graph=True)
+    b.run()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(4)
+    for it, (o, X, s) in zip(items, hosts):
+        pos = np.unique(np.concatenate([rng.integers(0, s, 64), [0, s - 1]]))
+        got = it["out"].cpu().numpy()[:, pos]
+        assert np.array_equal(got, O.apply(o.enc, X[:, pos]))

@@ -15,7 +15,7 @@ from paper_1412_3022_amd import pm, synth
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = [(4, 2), (4, 4), (8, 2), (8, 4), (16, 2), (16, 4)]
+VARIANTS = [(rg, vec) for rg in (4, 8, 16) for vec in (2, 4, 12, 14)]
 
 
 def _rand(seed, rows, s):
