@@ -215,6 +215,87 @@ pm_status pm_batch_info(const pm_batch *batch, uint64_t *units, uint32_t *size_c
 /* Free a plan; no run of it may still be in flight. */
 void pm_batch_destroy(pm_batch *batch);
 
+/* ---- Served mode (project addition beyond the paper) ---------------------
+ * Continuous batching of requests under an HBM budget.  The server owns one
+ * device arena of hbm_budget_bytes; a request is admitted (in arrival order)
+ * once the arena can hold its result (and, for repair, its d helper blocks),
+ * then runs inside a micro-batch on one of `streams` streams.  Requests that
+ * arrive while earlier micro-batches run are admitted into the next free
+ * stream, so their work overlaps on the GPU.  A result stays in the arena
+ * until pm_server_release. */
+typedef enum { PM_REQ_ENCODE = 0, PM_REQ_REPAIR = 1, PM_REQ_DECODE = 2 } pm_request_op;
+
+typedef struct {
+    int32_t op;                          /* pm_request_op */
+    const pm_code *code;
+    uint32_t failed;                     /* repair: the failed node */
+    const uint32_t *ids;                 /* repair: d helper ids; decode: k node ids
+                                            (host, copied at submit) */
+    const uint8_t *in;                   /* encode: X (B blocks); decode: the k alpha
+                                            received blocks, node-major (device) */
+    size_t in_ld;
+    const uint8_t *const *helper_nodes;  /* repair: d device pointers, each to the
+                                            alpha blocks of one helper node (host
+                                            array, copied at submit) */
+    size_t node_ld;
+    size_t block_bytes;
+    uint64_t tag;                        /* returned in the completion */
+} pm_request;
+
+typedef struct {
+    uint64_t ticket, tag;
+    int32_t status;
+    uint8_t *out;          /* result blocks in the arena (device), valid until released */
+    size_t out_ld;
+    uint32_t out_blocks;   /* encode: enc_rows; repair: alpha; decode: B */
+    uint64_t t_submit_ns, t_admit_ns, t_done_ns;   /* steady clock */
+} pm_completion;
+
+typedef struct {
+    uint64_t hbm_budget_bytes;  /* arena size: admitted results + repair scratch */
+    uint32_t streams;           /* micro-batches in flight at once (1..16) */
+    uint32_t max_batch;         /* requests per micro-batch */
+    uint32_t queue_cap;         /* pending requests before submit returns PM_EBUSY */
+    uint32_t dwords_per_lane;   /* tile width of the work lists: 2 or 4 (0 = 2) */
+} pm_server_cfg;
+
+typedef struct {
+    uint64_t completed, batches, pending, arena_used, arena_high_water;
+    uint32_t max_concurrent_batches;   /* most micro-batches in flight at once */
+} pm_server_stat;
+
+typedef struct pm_server pm_server;
+
+/* Allocate the arena, streams and staging buffers; start the scheduler
+ * thread (on the calling thread's current device). */
+pm_status pm_server_create(const pm_server_cfg *cfg, pm_server **out);
+
+/* Queue a request (thread-safe).  Resolves its matrices (building a repair or
+ * decode matrix for a new failure pattern here), checks its regions and
+ * returns a ticket.  PM_EBUSY when queue_cap requests are pending; PM_ENOMEM
+ * when its result can never fit the arena.  Input buffers must stay valid
+ * until its completion is polled. */
+pm_status pm_server_submit(pm_server *srv, const pm_request *req, uint64_t *ticket);
+
+/* Move up to cap finished requests into out[]; *n_done = how many. */
+pm_status pm_server_poll(pm_server *srv, pm_completion *out, size_t cap, size_t *n_done);
+
+/* Give a finished request's arena space back. */
+pm_status pm_server_release(pm_server *srv, uint64_t ticket);
+
+pm_status pm_server_stats(pm_server *srv, pm_server_stat *st);
+
+/* Load driver: submit reqs[i] at arrival_ns[i] after the call starts (spin
+ * waiting, retrying while the queue is full), collect every completion into
+ * out[i], and release each result at once unless flags has PM_REPLAY_KEEP.
+ * Returns when all n requests have completed. */
+#define PM_REPLAY_KEEP 1u
+pm_status pm_server_replay(pm_server *srv, const pm_request *reqs, const uint64_t *arrival_ns,
+                           size_t n, uint32_t flags, pm_completion *out);
+
+/* Stop the scheduler after the micro-batches in flight finish; free all. */
+void pm_server_destroy(pm_server *srv);
+
 /* Message of the last failing HIP call on this thread ("" if none). */
 const char *pm_last_hip_error(void);
 const char *pm_status_string(pm_status st);

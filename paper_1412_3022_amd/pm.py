@@ -310,3 +310,181 @@ class Batch:
 
     def run(self, stream=None):
         _check(_lib().pm_batch_run(self.h, _stream_handle(stream)), "pm_batch_run")
+
+
+# ---- served mode ------------------------------------------------------------
+PM_REQ_ENCODE, PM_REQ_REPAIR, PM_REQ_DECODE = 0, 1, 2
+
+
+class pm_request(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("code", ctypes.c_void_p), ("failed", ctypes.c_uint32),
+                ("ids", ctypes.POINTER(ctypes.c_uint32)), ("in_", ctypes.c_void_p), ("in_ld", ctypes.c_size_t),
+                ("helper_nodes", ctypes.POINTER(ctypes.c_void_p)), ("node_ld", ctypes.c_size_t),
+                ("block_bytes", ctypes.c_size_t), ("tag", ctypes.c_uint64)]
+
+
+class pm_completion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("out", ctypes.c_void_p), ("out_ld", ctypes.c_size_t), ("out_blocks", ctypes.c_uint32),
+                ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64)]
+
+
+class pm_server_cfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("streams", ctypes.c_uint32),
+                ("max_batch", ctypes.c_uint32), ("queue_cap", ctypes.c_uint32),
+                ("dwords_per_lane", ctypes.c_uint32)]
+
+
+class pm_server_stat(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_uint64), ("batches", ctypes.c_uint64), ("pending", ctypes.c_uint64),
+                ("arena_used", ctypes.c_uint64), ("arena_high_water", ctypes.c_uint64),
+                ("max_concurrent_batches", ctypes.c_uint32)]
+
+
+_server_sigs_done = False
+
+
+def _server_sigs():
+    global _server_sigs_done
+    if _server_sigs_done:
+        return _lib()
+    L = _lib()
+    vp = ctypes.c_void_p
+    L.pm_server_create.argtypes = [ctypes.POINTER(pm_server_cfg), ctypes.POINTER(vp)]
+    L.pm_server_submit.argtypes = [vp, ctypes.POINTER(pm_request), ctypes.POINTER(ctypes.c_uint64)]
+    L.pm_server_poll.argtypes = [vp, ctypes.POINTER(pm_completion), ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+    L.pm_server_release.argtypes = [vp, ctypes.c_uint64]
+    L.pm_server_stats.argtypes = [vp, ctypes.POINTER(pm_server_stat)]
+    L.pm_server_replay.argtypes = [vp, ctypes.POINTER(pm_request), ctypes.POINTER(ctypes.c_uint64),
+                                   ctypes.c_size_t, ctypes.c_uint32, ctypes.POINTER(pm_completion)]
+    L.pm_server_destroy.argtypes = [vp]
+    L.pm_server_destroy.restype = None
+    for n in ("pm_server_create", "pm_server_submit", "pm_server_poll", "pm_server_release", "pm_server_stats",
+              "pm_server_replay"):
+        getattr(L, n).restype = ctypes.c_int
+    _server_sigs_done = True
+    return L
+
+
+class Server:
+    """Continuous-batching server over the engine (see pm_server_* in pm.h)."""
+
+    def __init__(self, hbm_budget_bytes, streams=4, max_batch=64, queue_cap=4096, dwords_per_lane=2):
+        L = _server_sigs()
+        cfg = pm_server_cfg(hbm_budget_bytes, streams, max_batch, queue_cap, dwords_per_lane)
+        h = ctypes.c_void_p()
+        _check(L.pm_server_create(ctypes.byref(cfg), ctypes.byref(h)), "pm_server_create")
+        self.h = h.value
+        self._keep = {}
+
+    def close(self):
+        h, self.h = getattr(self, "h", None), None
+        if h:
+            _lib().pm_server_destroy(h)
+
+    def __del__(self):
+        import sys
+        if not sys.is_finalizing():
+            self.close()
+
+    def _submit(self, req, keep):
+        t = ctypes.c_uint64()
+        st = _lib().pm_server_submit(self.h, ctypes.byref(req), ctypes.byref(t))
+        if st == PM_EBUSY:
+            return None
+        _check(st, "pm_server_submit")
+        self._keep[t.value] = keep
+        return t.value
+
+    def submit_encode(self, code, X, block_bytes, tag=0):
+        r = pm_request(PM_REQ_ENCODE, code.h, 0, None, X.data_ptr(), X.stride(0), None, 0, block_bytes, tag)
+        return self._submit(r, (code, X))
+
+    def submit_decode(self, code, nodes, Y, block_bytes, tag=0):
+        ids = _u32arr(nodes)
+        r = pm_request(PM_REQ_DECODE, code.h, 0, ctypes.cast(ids, ctypes.POINTER(ctypes.c_uint32)),
+                       Y.data_ptr(), Y.stride(0), None, 0, block_bytes, tag)
+        return self._submit(r, (code, Y))
+
+    def submit_repair(self, code, failed, helpers, helper_nodes, block_bytes, tag=0):
+        ids = _u32arr(helpers)
+        ptrs = (ctypes.c_void_p * len(helper_nodes))(*[t.data_ptr() for t in helper_nodes])
+        ld = helper_nodes[0].stride(0)
+        r = pm_request(PM_REQ_REPAIR, code.h, failed, ctypes.cast(ids, ctypes.POINTER(ctypes.c_uint32)),
+                       None, 0, ctypes.cast(ptrs, ctypes.POINTER(ctypes.c_void_p)), ld, block_bytes, tag)
+        return self._submit(r, (code, helper_nodes))
+
+    def poll(self, cap=1024):
+        arr = (pm_completion * cap)()
+        n = ctypes.c_size_t()
+        _check(_lib().pm_server_poll(self.h, arr, cap, ctypes.byref(n)), "pm_server_poll")
+        out = []
+        for i in range(n.value):
+            c = arr[i]
+            self._keep.pop(c.ticket, None)
+            out.append(dict(ticket=c.ticket, tag=c.tag, status=c.status, out=c.out, out_ld=c.out_ld,
+                            out_blocks=c.out_blocks, t_submit=c.t_submit_ns, t_admit=c.t_admit_ns,
+                            t_done=c.t_done_ns))
+        return out
+
+    def release(self, ticket):
+        _check(_lib().pm_server_release(self.h, ticket), "pm_server_release")
+
+    def replay(self, requests, arrival_ns, keep=False):
+        """Native load driver.  requests: list of dicts with op ("encode",
+        "repair", "decode"), code, block_bytes and the op's tensors (X;
+        helpers + helper_nodes + failed; nodes + Y).  Returns completions in
+        request order."""
+        n = len(requests)
+        arr = (pm_request * max(1, n))()
+        keep_alive = []
+        for i, q in enumerate(requests):
+            r = arr[i]
+            r.code, r.block_bytes, r.tag = q["code"].h, q["block_bytes"], i
+            if q["op"] == "encode":
+                r.op, r.in_, r.in_ld = PM_REQ_ENCODE, q["X"].data_ptr(), q["X"].stride(0)
+            elif q["op"] == "decode":
+                ids = _u32arr(q["nodes"])
+                keep_alive.append(ids)
+                r.op, r.ids = PM_REQ_DECODE, ctypes.cast(ids, ctypes.POINTER(ctypes.c_uint32))
+                r.in_, r.in_ld = q["Y"].data_ptr(), q["Y"].stride(0)
+            else:
+                ids = _u32arr(q["helpers"])
+                ptrs = (ctypes.c_void_p * len(q["helper_nodes"]))(*[t.data_ptr() for t in q["helper_nodes"]])
+                keep_alive += [ids, ptrs]
+                r.op, r.failed = PM_REQ_REPAIR, q["failed"]
+                r.ids = ctypes.cast(ids, ctypes.POINTER(ctypes.c_uint32))
+                r.helper_nodes = ctypes.cast(ptrs, ctypes.POINTER(ctypes.c_void_p))
+                r.node_ld = q["helper_nodes"][0].stride(0)
+        arrivals = (ctypes.c_uint64 * max(1, n))(*[int(t) for t in arrival_ns])
+        outs = (pm_completion * max(1, n))()
+        _check(_lib().pm_server_replay(self.h, arr, arrivals, n, 1 if keep else 0, outs), "pm_server_replay")
+        res = []
+        for i in range(n):
+            c = outs[i]
+            res.append(dict(ticket=c.ticket, tag=c.tag, status=c.status, out=c.out, out_ld=c.out_ld,
+                            out_blocks=c.out_blocks, t_submit=c.t_submit_ns, t_admit=c.t_admit_ns,
+                            t_done=c.t_done_ns))
+        return res
+
+    def stats(self):
+        s = pm_server_stat()
+        _check(_lib().pm_server_stats(self.h, ctypes.byref(s)), "pm_server_stats")
+        return dict(completed=s.completed, batches=s.batches, pending=s.pending, arena_used=s.arena_used,
+                    arena_high_water=s.arena_high_water, max_concurrent_batches=s.max_concurrent_batches)
+
+
+_hip = None
+
+
+def copy_device(dst_ptr, src_ptr, nbytes):
+    """Device-to-device copy through the HIP runtime (result read-back for
+    tests and the benchmark harness; not part of the engine's data path)."""
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _hip.hipMemcpy.restype = ctypes.c_int
+    st = _hip.hipMemcpy(dst_ptr, src_ptr, nbytes, 3)   # hipMemcpyDeviceToDevice
+    if st != 0:
+        raise RuntimeError("hipMemcpy failed: %d" % st)

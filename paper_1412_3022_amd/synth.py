@@ -84,3 +84,31 @@ def split_object(S: int, B: int, seed: int, align: int = 64):
 def block_bytes_for(S: int, B: int, align: int = 64) -> int:
     s = -(-S // B)
     return -(-s // align) * align
+
+
+def random_bytes_torch(seed: int, nbytes: int, device, chunk_words: int = 1 << 26):
+    """The same splitmix64 byte stream as random_bytes(), generated with torch
+    integer ops on `device` (int64 arithmetic wraps like uint64; logical right
+    shifts are arithmetic shifts masked to the low bits).  Returns a uint8
+    tensor of nbytes."""
+    import torch
+    nwords = (nbytes + 7) // 8
+    out = torch.empty(nwords * 8, dtype=torch.uint8, device=device)
+    words = out.view(torch.int64)
+
+    def s64(v):
+        v &= (1 << 64) - 1
+        return v - (1 << 64) if v >= 1 << 63 else v
+
+    gamma, m1, m2 = s64(0x9E3779B97F4A7C15), s64(0xBF58476D1CE4E5B9), s64(0x94D049BB133111EB)
+
+    def shr(z, k):
+        return (z >> k) & ((1 << (64 - k)) - 1)
+
+    for a in range(0, nwords, chunk_words):
+        b = min(nwords, a + chunk_words)
+        z = torch.arange(a + 1, b + 1, dtype=torch.int64, device=device) * gamma + s64(seed)
+        z = (z ^ shr(z, 30)) * m1
+        z = (z ^ shr(z, 27)) * m2
+        words[a:b] = z ^ shr(z, 31)
+    return out[:nbytes]

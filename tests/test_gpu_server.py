@@ -1,0 +1,124 @@
+"""Served mode: every result is the same byte for byte whether the request
+runs alone or inside the mix, micro-batches really overlap on the GPU, and
+admission never holds more than the HBM budget."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import device
+from paper_1412_3022_amd import pm, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _result(c, out_blocks, s):
+    t = torch.empty((c["out_blocks"], c["out_ld"]), dtype=torch.uint8, device=device())
+    pm.copy_device(t.data_ptr(), c["out"], t.numel())
+    return t[:, :s]
+
+
+def _alone(q):
+    """The same request as plain single calls."""
+    c, s = q["code"], q["block_bytes"]
+    dev = device()
+    if q["op"] == "encode":
+        out = torch.empty((c.enc_rows, s), dtype=torch.uint8, device=dev)
+        c.encode(q["X"], out, s)
+    elif q["op"] == "decode":
+        out = torch.empty((c.B, s), dtype=torch.uint8, device=dev)
+        c.decode(q["nodes"], q["Y"], out, s)
+    else:
+        recv = torch.empty((c.d, s), dtype=torch.uint8, device=dev)
+        for j, node in enumerate(q["helper_nodes"]):
+            c.repair_helper(q["failed"], node, recv[j:j + 1], s)
+        out = torch.empty((c.alpha, s), dtype=torch.uint8, device=dev)
+        c.repair_newcomer(q["failed"], q["helpers"], recv, out, s)
+    torch.cuda.synchronize()
+    return out
+
+
+def test_served_mix_equals_alone_and_overlaps():
+    print("server mix", flush=True)
+    wl = workloads.ServeWorkload(21, device(), 1 << 10, 256 << 10, resident_per_family=2)
+    reqs, arrivals, nbytes = wl.requests(300, rate_per_s=2e5)
+    budget = 32 << 20
+    srv = pm.Server(budget, streams=3, max_batch=8)
+    try:
+        comps = srv.replay(reqs, arrivals, keep=True)
+        torch.cuda.synchronize()
+        for q, c in zip(reqs, comps):
+            assert c["status"] == pm.PM_OK
+            s = q["block_bytes"]
+            got = _result(c, c["out_blocks"], s)
+            want = _alone(q)
+            assert torch.equal(got, want), (q["op"], s)
+            if q["op"] == "repair":
+                assert torch.equal(got, q["obj"]["nodes"][q["failed"]])
+            elif q["op"] == "decode":
+                assert torch.equal(got, q["obj"]["X"])
+            srv.release(c["ticket"])
+        st = srv.stats()
+        assert st["completed"] == len(reqs)
+        assert st["max_concurrent_batches"] >= 2, st
+        assert st["arena_high_water"] <= budget
+        assert st["arena_used"] == 0
+        # latencies are ordered timestamps
+        for c in comps:
+            assert c["t_submit"] <= c["t_admit"] <= c["t_done"]
+    finally:
+        srv.close()
+
+
+def test_budget_backpressure_completes_everything():
+    print("server budget", flush=True)
+    wl = workloads.ServeWorkload(22, device(), 64 << 10, 512 << 10, resident_per_family=1)
+    reqs, arrivals, _ = wl.requests(60, rate_per_s=1e6)
+    need = max(q["code"].enc_rows if q["op"] == "encode" else
+               (q["code"].B if q["op"] == "decode" else q["code"].alpha + q["code"].d)
+               for q in reqs) * max(q["block_bytes"] for q in reqs)
+    budget = need + (1 << 16)          # about one request at a time
+    srv = pm.Server(budget, streams=4, max_batch=4)
+    try:
+        comps = srv.replay(reqs, arrivals, keep=False)
+        st = srv.stats()
+        assert st["completed"] == len(reqs)
+        assert all(c["status"] == pm.PM_OK for c in comps)
+        assert st["arena_high_water"] <= budget
+    finally:
+        srv.close()
+
+
+def test_queue_full_and_oversized_requests():
+    print("server queue", flush=True)
+    dev = device()
+    c = pm.Code(k=4, d=6, n=8)
+    s = 64 << 10
+    X = torch.zeros((c.B, s), dtype=torch.uint8, device=dev)
+    srv = pm.Server(c.enc_rows * s + 4096, streams=2, max_batch=2, queue_cap=2)
+    try:
+        t0 = srv.submit_encode(c, X, s)
+        done = []
+        deadline = time.time() + 30
+        while not done and time.time() < deadline:
+            done = srv.poll()
+        assert done and done[0]["ticket"] == t0
+        # the first result is held: the next two wait for memory, the third bounces
+        assert srv.submit_encode(c, X, s) is not None
+        assert srv.submit_encode(c, X, s) is not None
+        assert srv.submit_encode(c, X, s) is None          # PM_EBUSY
+        srv.release(t0)
+        got = []
+        deadline = time.time() + 30
+        while len(got) < 2 and time.time() < deadline:
+            for r in srv.poll():
+                got.append(r)
+                srv.release(r["ticket"])
+        assert len(got) == 2
+        big = torch.zeros((c.B, 4 * s), dtype=torch.uint8, device=dev)
+        with pytest.raises(pm.PMError) as e:
+            srv.submit_encode(c, big, 4 * s)
+        assert e.value.status == pm.PM_ENOMEM
+    finally:
+        srv.close()
