@@ -116,8 +116,7 @@ def encode_case(torch, pm, synth, kw, S, seed, steps, warmup, nbuf=NBUF, tune=Tr
     stream = torch.cuda.current_stream().cuda_stream
     variant = None
     if sweep:
-        for rg in (4, 8, 16):
-            for vec in (2, 4, 12, 14):
+        for rg, vec in [(rg, vec) for rg in (4, 8, 16) for vec in (2, 4, 12, 14, 22, 24)] + [(8, 32)]:
                 code.set_variant(pm.OP_ENCODE, rg, vec)
                 def one(i):
                     j = i % nbuf

@@ -153,8 +153,17 @@ pm_status pm_apply(const uint8_t *A, uint32_t rows, uint32_t cols, const uint8_t
  * 4 pm_apply (global).  rows_per_group in {4, 8, 16}: output rows held in
  * registers per work unit; dwords_per_lane in {2, 4} (8 or 16 bytes per lane
  * per source block), plus 10 to stage the coefficient tables in LDS instead
- * of reading them through the scalar cache (12, 14).  0, 0 restores the
- * built-in cost model.  PM_EINVAL for other values. */
+ * of reading them through the scalar cache (12, 14), plus 20 for the
+ * software-pipelined kernel that loads every column of the next work unit
+ * while multiplying the current one (22, 24; row groups of up to 16
+ * columns, others fall back to the plain loop).  dwords_per_lane 32 (with
+ * rows_per_group 8): the bit-sliced kernel -- the matrix compiled at first
+ * use (hipRTC, a few seconds, cached per matrix and device) into a
+ * straight-line XOR network over bit planes (Section 4.1's bit-matrix
+ * view); blocks shorter than 2048 bytes and matrices whose network exceeds
+ * the size limit run the table kernel with 4 dwords per lane instead.  A
+ * hipRTC failure is reported as PM_EHIP.  0, 0 restores the built-in cost
+ * model.  PM_EINVAL for other values. */
 pm_status pm_set_variant(pm_code *code, int op, uint32_t rows_per_group,
                          uint32_t dwords_per_lane);
 

@@ -22,7 +22,7 @@ LIB = os.path.join(LIBDIR, "libpmrc.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
-HOST_SOURCES = ["gf256.cpp", "construct.cpp", "program.cpp", "capi.cpp", "batch.cpp", "server.cpp"]
+HOST_SOURCES = ["gf256.cpp", "construct.cpp", "program.cpp", "capi.cpp", "batch.cpp", "server.cpp", "bitslice.cpp"]
 HIP_SOURCES = ["kernels.hip"]
 
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__",
@@ -72,7 +72,7 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("build of the HIP engine failed")
     tmp = LIB + ".tmp%d" % os.getpid()
     link = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + [o for _, o in jobs] + \
-        ["-pthread"]
+        ["-pthread", "-L" + os.path.join(ROCM, "lib"), "-lhiprtc"]
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.check_call(link)

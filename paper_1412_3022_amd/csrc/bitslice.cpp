@@ -1,0 +1,363 @@
+// Bit-sliced region kernels specialized per matrix (compiled with hipRTC).
+//
+// Multiplying a byte by a constant c in GF(2^8) is linear over GF(2): bit i
+// of c*x is the XOR of the bits j of x for which bit i of c*2^j is set.  Once
+// 32 bytes of a lane are transposed into 8 bit planes (plane j = bit j of
+// every byte), c*x for all 32 bytes is a fixed XOR network over the planes,
+// and a whole row group is a fixed network over its columns' planes.  This is
+// the GPU counterpart of the paper's bit-matrix XOR schedules (Section 4.1,
+// the encode paragraph's note on bit matrices).
+//
+// The network is emitted as straight-line HIP source for one matrix,
+// compiled once with hipRTC and cached (per matrix and device).  Per source
+// column the generator forms the XOR combinations of planes 0-3 and of
+// planes 4-7 that the group's rows need (the "four Russians" table), so every
+// output plane costs one three-input XOR per column.  The 8x8 bit transposes
+// in and out cost 12 masked swaps each.  Rows of a group number at most 8
+// (64 plane accumulators); copy groups move bytes without transposing.
+//
+// Launch geometry: each lane owns 32 bytes of a wave tile (two 16-byte
+// pieces 1 KiB apart, so every load instruction is one contiguous KiB).
+// Work-groups are dealt to the 8 XCDs round-robin; on each XCD every slot
+// (work-group) is bound to one row group and the slots of a group stride over
+// that XCD's range of tiles.  All groups of a tile therefore run at once in
+// one L2 (their shared source columns are read from HBM once), while each
+// work-group executes only one group's code (the instruction cache holds it).
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <set>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "bitslice.hpp"
+#include "construct.hpp"
+#include "engine.hpp"
+#include "gf256.hpp"
+#include "program.hpp"
+
+namespace pmrc {
+namespace {
+
+constexpr int kGroupWords = 8;
+constexpr int kHeaderWords = 4;
+
+const char *kPrelude = R"(
+typedef unsigned int u32;
+typedef unsigned long long u64;
+typedef u32 u32x4 __attribute__((ext_vector_type(4)));
+#define X3(a, b, c) __builtin_amdgcn_bitop3_b32((a), (b), (c), 0x96)
+#define DS(a, b, sh, m) { u32 t_ = (((a) >> (sh)) ^ (b)) & (m); (b) ^= t_; (a) ^= t_ << (sh); }
+#define TR8(A0, A1, A2, A3, A4, A5, A6, A7) { \
+  DS(A0, A4, 4, 0x0F0F0F0Fu) DS(A1, A5, 4, 0x0F0F0F0Fu) DS(A2, A6, 4, 0x0F0F0F0Fu) DS(A3, A7, 4, 0x0F0F0F0Fu) \
+  DS(A0, A2, 2, 0x33333333u) DS(A1, A3, 2, 0x33333333u) DS(A4, A6, 2, 0x33333333u) DS(A5, A7, 2, 0x33333333u) \
+  DS(A0, A1, 1, 0x55555555u) DS(A2, A3, 1, 0x55555555u) DS(A4, A5, 1, 0x55555555u) DS(A6, A7, 1, 0x55555555u) }
+struct BsArgs { const unsigned char *in; u64 ld; unsigned char *out; u64 old; u64 s; u32 nfull, ntiles, P; };
+// Product in GF(2^8) by shift and add (used only for the last s mod 16 bytes).
+__device__ __forceinline__ u32 gm(u32 c, u32 x) {
+  u32 p = 0u;
+#pragma unroll 1
+  for (; c; c >>= 1) {
+    if (c & 1u) p ^= x;
+    x = (x << 1) ^ ((x & 0x80u) ? POLY : 0u);
+  }
+  return p;
+}
+)";
+
+struct Grp {
+    uint32_t kind;
+    std::vector<uint32_t> rows, cols;           // output rows; input blocks
+    std::vector<std::vector<uint8_t>> coef;     // [row][col]
+};
+
+std::vector<Grp> read_groups(const Program &p) {
+    std::vector<Grp> out;
+    const uint32_t *b = p.blob.data();
+    for (int g = 0; g < p.ngroups; ++g) {
+        const uint32_t *r = b + kHeaderWords + g * kGroupWords;
+        Grp G;
+        G.kind = r[0];
+        const uint32_t nrows = r[1], ncols = r[2];
+        for (uint32_t i = 0; i < nrows; ++i) G.rows.push_back(b[r[5] + i]);
+        if (G.kind == GROUP_COPY) {
+            for (uint32_t i = 0; i < nrows; ++i) G.cols.push_back(b[r[3] + i]);
+        } else {
+            for (uint32_t c = 0; c < ncols; ++c) G.cols.push_back(b[r[3] + c]);
+            G.coef.assign(nrows, std::vector<uint8_t>(ncols, 0));
+            for (uint32_t c = 0; c < ncols; ++c)
+                for (uint32_t i = 0; i < nrows; ++i)   // slot (c, i): word 0 byte 1 = coef * 1
+                    G.coef[i][c] = static_cast<uint8_t>((b[r[4] + (c * p.rg + i) * 4] >> 8) & 0xFF);
+        }
+        out.push_back(std::move(G));
+    }
+    return out;
+}
+
+int popc(unsigned m) { return __builtin_popcount(m); }
+
+// Straight-line code of one table group.
+void emit_table_group(std::ostringstream &o, int gi, const Grp &G) {
+    const int n = static_cast<int>(G.rows.size());
+    o << "__device__ __forceinline__ void g" << gi
+      << "(const unsigned char *in, u64 ld, unsigned char *out, u64 old, u64 off) {\n";
+    for (int r = 0; r < n; ++r) {
+        o << "  u32";
+        for (int i = 0; i < 8; ++i) o << (i ? "," : "") << " q" << r << "_" << i << " = 0u";
+        o << ";\n";
+    }
+    for (size_t ci = 0; ci < G.cols.size(); ++ci) {
+        // Skip padding columns whose coefficients are all zero.
+        bool any = false;
+        for (int r = 0; r < n; ++r) any |= G.coef[r][ci] != 0;
+        if (!any) continue;
+        o << "  {\n    const unsigned char *p = in + (u64)" << G.cols[ci] << "u * ld + off;\n"
+          << "    const u32x4 lo = *(const u32x4 *)p, hi = *(const u32x4 *)(p + 1024);\n"
+          << "    u32 P0 = lo.x, P1 = lo.y, P2 = lo.z, P3 = lo.w, P4 = hi.x, P5 = hi.y, P6 = hi.z, P7 = hi.w;\n"
+          << "    TR8(P0, P1, P2, P3, P4, P5, P6, P7)\n";
+        struct Eq { int r, i; unsigned lo, hi; };
+        std::vector<Eq> eqs;
+        std::set<std::pair<int, unsigned>> need;   // (half, mask)
+        for (int r = 0; r < n; ++r) {
+            const uint8_t a = G.coef[r][ci];
+            if (!a) continue;
+            uint8_t colbits[8];
+            for (int j = 0; j < 8; ++j) colbits[j] = gmul(a, static_cast<uint8_t>(1u << j));
+            for (int i = 0; i < 8; ++i) {
+                unsigned lo = 0, hi = 0;
+                for (int j = 0; j < 8; ++j)
+                    if ((colbits[j] >> i) & 1) {
+                        if (j < 4) lo |= 1u << j;
+                        else hi |= 1u << (j - 4);
+                    }
+                eqs.push_back({r, i, lo, hi});
+                if (lo) need.insert({0, lo});
+                if (hi) need.insert({1, hi});
+            }
+        }
+        auto name = [](int half, unsigned m) {
+            std::ostringstream s;
+            if (popc(m) == 1) s << "P" << (__builtin_ctz(m) + 4 * half);
+            else s << (half ? "H" : "L") << m;
+            return s.str();
+        };
+        std::set<std::pair<int, unsigned>> made;
+        // each combination = (combination without its lowest plane) ^ that plane
+        std::vector<std::pair<int, unsigned>> order(need.begin(), need.end());
+        std::sort(order.begin(), order.end(), [](auto a, auto b) {
+            return popc(a.second) != popc(b.second) ? popc(a.second) < popc(b.second) : a < b;
+        });
+        for (auto want : order) {
+            std::vector<unsigned> chain;
+            for (unsigned m = want.second; popc(m) > 1 && !made.count({want.first, m}); m &= m - 1) chain.push_back(m);
+            for (auto it = chain.rbegin(); it != chain.rend(); ++it) {
+                const unsigned m = *it, low = m & (~m + 1);
+                o << "    const u32 " << name(want.first, m) << " = " << name(want.first, m ^ low) << " ^ "
+                  << name(want.first, low) << ";\n";
+                made.insert({want.first, m});
+            }
+        }
+        for (const Eq &e : eqs) {
+            const std::string q = "q" + std::to_string(e.r) + "_" + std::to_string(e.i);
+            if (e.lo && e.hi) o << "    " << q << " = X3(" << q << ", " << name(0, e.lo) << ", " << name(1, e.hi) << ");\n";
+            else if (e.lo) o << "    " << q << " ^= " << name(0, e.lo) << ";\n";
+            else if (e.hi) o << "    " << q << " ^= " << name(1, e.hi) << ";\n";
+        }
+        o << "  }\n";
+    }
+    for (int r = 0; r < n; ++r) {
+        o << "  TR8(";
+        for (int i = 0; i < 8; ++i) o << (i ? ", " : "") << "q" << r << "_" << i;
+        o << ")\n  { unsigned char *d = out + (u64)" << G.rows[r] << "u * old + off;\n"
+          << "    *(u32x4 *)d = u32x4{q" << r << "_0, q" << r << "_1, q" << r << "_2, q" << r << "_3};\n"
+          << "    *(u32x4 *)(d + 1024) = u32x4{q" << r << "_4, q" << r << "_5, q" << r << "_6, q" << r << "_7}; }\n";
+    }
+    o << "}\n";
+}
+
+void emit_copy_group(std::ostringstream &o, int gi, const Grp &G) {
+    o << "__device__ __forceinline__ void g" << gi
+      << "(const unsigned char *in, u64 ld, unsigned char *out, u64 old, u64 off) {\n";
+    for (size_t i = 0; i < G.rows.size(); ++i)
+        o << "  { const unsigned char *p = in + (u64)" << G.cols[i] << "u * ld + off;\n"
+          << "    unsigned char *d = out + (u64)" << G.rows[i] << "u * old + off;\n"
+          << "    const u32x4 lo = *(const u32x4 *)p, hi = *(const u32x4 *)(p + 1024);\n"
+          << "    *(u32x4 *)d = lo; *(u32x4 *)(d + 1024) = hi; }\n";
+    o << "}\n";
+}
+
+// The last s mod 16 bytes of every row: one lane per byte position, each
+// output byte the sum over the group's columns of coefficient times input
+// byte, with the group's rows, columns and coefficients in constant tables.
+void emit_byte_tail(std::ostringstream &o, int gi, const Grp &G) {
+    const size_t nr = G.rows.size(), nc = G.kind == GROUP_COPY ? 1 : G.cols.size();
+    o << "__constant__ u32 tr" << gi << "[" << nr << "] = {";
+    for (size_t r = 0; r < nr; ++r) o << (r ? ", " : "") << G.rows[r] << "u";
+    o << "};\n__constant__ u32 tc" << gi << "[" << nr * nc << "] = {";
+    for (size_t r = 0; r < nr; ++r)
+        for (size_t c = 0; c < nc; ++c) {
+            // per (row, column): input block | coefficient << 24
+            const uint32_t col = G.kind == GROUP_COPY ? G.cols[r] : G.cols[c];
+            const uint32_t coef = G.kind == GROUP_COPY ? 1u : G.coef[r][c];
+            o << (r + c ? ", " : "") << (col | coef << 24) << "u";
+        }
+    o << "};\n__device__ __noinline__ void b" << gi
+      << "(const unsigned char *in, u64 ld, unsigned char *out, u64 old, u64 pos) {\n"
+      << "#pragma unroll 1\n  for (u32 r = 0; r < " << nr << "u; ++r) {\n    u32 acc = 0u;\n"
+      << "#pragma unroll 1\n    for (u32 c = 0; c < " << nc << "u; ++c) {\n"
+      << "      const u32 e = tc" << gi << "[r * " << nc << "u + c];\n"
+      << "      acc ^= gm(e >> 24, in[(u64)(e & 0xFFFFFFu) * ld + pos]);\n    }\n"
+      << "    out[(u64)tr" << gi << "[r] * old + pos] = (unsigned char)acc;\n  }\n}\n";
+}
+
+long estimate_ops(const std::vector<Grp> &gs) {
+    long ops = 0;
+    for (const Grp &G : gs) {
+        if (G.kind == GROUP_COPY) continue;
+        ops += static_cast<long>(G.cols.size()) * (60 + 24 + 8 * static_cast<long>(G.rows.size()));
+        ops += 60 * static_cast<long>(G.rows.size());
+    }
+    return ops;
+}
+
+std::string thread_log;
+
+}  // namespace
+
+std::unique_ptr<BsProgram> bs_generate(const Program &p8) {
+    std::vector<Grp> gs = read_groups(p8);
+    auto bp = std::make_unique<BsProgram>();
+    bp->ngroups = static_cast<int>(gs.size());
+    bp->est_ops = estimate_ops(gs);
+    std::ostringstream o;
+    // reduction polynomial of the field: x^8 = x * x^7
+    o << "#define POLY " << (0x100u | gmul(0x80, 2)) << "u\n" << kPrelude;
+    for (size_t g = 0; g < gs.size(); ++g) {
+        if (gs[g].kind == GROUP_COPY) emit_copy_group(o, static_cast<int>(g), gs[g]);
+        else emit_table_group(o, static_cast<int>(g), gs[g]);
+        emit_byte_tail(o, static_cast<int>(g), gs[g]);
+    }
+    const int G = bp->ngroups;
+    // Tiles 0 .. nfull-1 are the full 2048-byte tiles; when s16 (s rounded
+    // down to 16) is not a multiple of 2048, tile nfull is the window
+    // [s16 - 2048, s16), which overlaps tile nfull-1 and stores the same bytes
+    // it does.  The s - s16 bytes after s16 are done byte by byte by the
+    // lanes of the wave that takes the last tile.
+    o << "extern \"C\" __global__ __launch_bounds__(512) void pmbs(BsArgs a) {\n"
+      << "  const u32 wave = threadIdx.x / 64, lane = threadIdx.x % 64;\n"
+      << "  const u32 xcd = blockIdx.x % 8u, slot = blockIdx.x / 8u;\n"
+      << "  const u32 per = (a.ntiles + 7u) / 8u, t0 = xcd * per;\n"
+      << "  const u32 t1 = t0 + per < a.ntiles ? t0 + per : a.ntiles;\n"
+      << "  const u64 s16 = a.s & ~15ull;\n"
+      << "  const u32 G = " << G << "u;\n"
+      << "  // slots of one group stride over this XCD's tiles; with fewer slots\n"
+      << "  // than groups a slot takes groups slot, slot + P, ...\n"
+      << "  for (u32 g = slot % G; g < G; g += a.P) {\n"
+      << "    const u32 R = a.P >= G ? (a.P - 1u - g) / G + 1u : 1u;\n"
+      << "    const u32 r = a.P >= G ? slot / G : 0u;\n"
+      << "    for (u32 t = t0 + r * 8u + wave; t < t1; t += R * 8u) {\n"
+      << "      const u64 tile = t < a.nfull ? (u64)t * 2048u : s16 - 2048u;\n"
+      << "      switch (g) {\n";
+    for (int g = 0; g < G; ++g) o << "        case " << g << ": g" << g << "(a.in, a.ld, a.out, a.old, tile + lane * 16u); break;\n";
+    o << "      }\n"
+      << "      if (t == a.ntiles - 1u && s16 + lane < a.s) {\n"
+      << "        switch (g) {\n";
+    for (int g = 0; g < G; ++g) o << "          case " << g << ": b" << g << "(a.in, a.ld, a.out, a.old, s16 + lane); break;\n";
+    o << "        }\n      }\n    }\n    if (a.P >= G) break;\n  }\n}\n";
+    bp->source = o.str();
+    if (const char *dump = getenv("PMRC_BS_DUMP")) {   // debugging aid: keep the generated source
+        if (FILE *f = fopen(dump, "w")) {
+            fputs(bp->source.c_str(), f);
+            fclose(f);
+        }
+    }
+    return bp;
+}
+
+int bs_compile(BsProgram &bp) {
+    std::lock_guard<std::mutex> lk(bp.mu);
+    if (bp.compiled) return bp.compile_status;
+    bp.compiled = true;
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, bp.source.c_str(), "pm_bitslice.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS) {
+        bp.compile_status = ST_EHIP;
+        return bp.compile_status;
+    }
+    const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17"};
+    hiprtcResult r = hiprtcCompileProgram(prog, 3, opts);
+    if (r != HIPRTC_SUCCESS) {
+        size_t ls = 0;
+        hiprtcGetProgramLogSize(prog, &ls);
+        std::string log(ls, '\0');
+        if (ls) hiprtcGetProgramLog(prog, &log[0]);
+        g_hip_msg = "hipRTC: " + log.substr(0, 2000);
+        hiprtcDestroyProgram(&prog);
+        bp.compile_status = ST_EHIP;
+        return bp.compile_status;
+    }
+    size_t cs = 0;
+    hiprtcGetCodeSize(prog, &cs);
+    bp.code.resize(cs);
+    hiprtcGetCode(prog, bp.code.data());
+    hiprtcDestroyProgram(&prog);
+    bp.compile_status = ST_OK;
+    return ST_OK;
+}
+
+BsProgram::~BsProgram() {
+    for (auto &kv : dev)
+        if (kv.second.mod) (void)hipModuleUnload(kv.second.mod);
+}
+
+int bs_launch(BsProgram &bp, const uint8_t *in, uint64_t in_ld, uint8_t *out, uint64_t out_ld, uint64_t s,
+              hipStream_t st) {
+    int st_c = bs_compile(bp);
+    if (st_c != ST_OK) return st_c;
+    int devid = 0;
+    hipError_t e = hipGetDevice(&devid);
+    if (e != hipSuccess) return hip_fail(e);
+    BsModule *m;
+    {
+        std::lock_guard<std::mutex> lk(bp.mu);
+        m = &bp.dev[devid];
+        if (!m->fn) {
+            if ((e = hipModuleLoadData(&m->mod, bp.code.data())) != hipSuccess) return hip_fail(e);
+            if ((e = hipModuleGetFunction(&m->fn, m->mod, "pmbs")) != hipSuccess) return hip_fail(e);
+            int per_cu = 0, ncu = 0;
+            if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, m->fn, 512, 0) != hipSuccess ||
+                per_cu < 1)
+                per_cu = 1;
+            if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, devid) != hipSuccess || ncu < 8)
+                ncu = 256;
+            const int p0 = std::max(1, per_cu * ncu / 8);
+            m->P = bp.ngroups <= p0 ? (p0 / bp.ngroups) * bp.ngroups : p0;
+        }
+    }
+    // the window tile needs one full tile before it; shorter blocks are
+    // refused here and left to the table kernels by the caller
+    if (s < kBsTileBytes) return ST_EINVAL;
+    const uint64_t s16 = s & ~uint64_t(15), nfull = s16 / kBsTileBytes;
+    const uint64_t ntiles = nfull + (s16 % kBsTileBytes ? 1 : 0);
+    if (ntiles > 0xffffffffull) return ST_EINVAL;
+    struct {
+        const uint8_t *in;
+        uint64_t ld;
+        uint8_t *out;
+        uint64_t old;
+        uint64_t s;
+        uint32_t nfull, ntiles, P;
+    } args{in, in_ld, out, out_ld, s, static_cast<uint32_t>(nfull), static_cast<uint32_t>(ntiles),
+           static_cast<uint32_t>(m->P)};
+    size_t size = sizeof(args);
+    void *cfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &args, HIP_LAUNCH_PARAM_BUFFER_SIZE, &size, HIP_LAUNCH_PARAM_END};
+    e = hipModuleLaunchKernel(m->fn, static_cast<unsigned>(8 * m->P), 1, 1, 512, 1, 1, 0, st, nullptr, cfg);
+    if (e != hipSuccess) return hip_fail(e);
+    return ST_OK;
+}
+
+}  // namespace pmrc

@@ -99,6 +99,17 @@ int ProgEntry::device_ptr_sync(const uint32_t **out) {
     return ST_OK;
 }
 
+BsProgram *ProgEntry::bitslice() {
+    std::lock_guard<std::mutex> lk(mu);
+    if (!bs_tried) {
+        bs_tried = true;
+        Program p8 = build_program(A, 8, in_map);
+        std::unique_ptr<BsProgram> b = bs_generate(p8);
+        if (b->est_ops <= kBsMaxOps) bs = std::move(b);
+    }
+    return bs.get();
+}
+
 // ---- variant choice ----------------------------------------------------------
 // VALU cost per lane dword of a program: each evaluated slot costs three
 // byte-permutes and 1.5 three-input XORs plus its share of table moves; each
@@ -144,6 +155,13 @@ int launch_program(ProgEntry &pe, int vec, const uint8_t *in, size_t in_ld, size
     if ((st = check_regions(out, out_ld, out_n, s)) != ST_OK) return st;
     if (overlaps(in, in_ld, in_n, out, out_ld, out_n, s)) return ST_EINVAL;
     if (pe.prog.ngroups == 0) return ST_OK;
+    if (vec == kVecBitslice) {
+        // blocks shorter than one tile, and matrices too large for a
+        // specialized kernel, run on the table kernel
+        if (s >= kBsTileBytes)
+            if (BsProgram *bp = pe.bitslice()) return bs_launch(*bp, in, in_ld, out, out_ld, s, stream);
+        vec = 4;
+    }
     const uint32_t *dprog = nullptr;
     if ((st = pe.device_ptr(stream, &dprog)) != ST_OK) return st;
     PmkApply a{in, in_ld, out, out_ld, s, dprog, static_cast<uint32_t>(pe.prog.ngroups)};
@@ -173,6 +191,7 @@ ProgEntry *apply_program(const Mat &A, int *vec) {
     if (it != g_apply.end()) return it->second.get();
     auto pe = std::make_unique<ProgEntry>();
     pe->prog = build_program(A, rg);
+    pe->A = A;
     ProgEntry *raw = pe.get();
     g_apply.emplace(std::move(key), std::move(pe));
     return raw;
@@ -205,6 +224,8 @@ ProgEntry *get_prog(Map &map, const Key &key_prefix_rg, const Mat &A, const std:
     auto pe = std::make_unique<ProgEntry>();
     int rg = std::get<std::tuple_size<Key>::value - 1>(key_prefix_rg);
     pe->prog = build_program(A, rg, in_map);
+    pe->A = A;
+    pe->in_map = in_map;
     ProgEntry *raw = pe.get();
     map.emplace(key_prefix_rg, std::move(pe));
     return raw;
@@ -401,7 +422,9 @@ pm_status pm_code_node_map(const pm_code *c, int32_t *map, size_t cap) {
 
 pm_status pm_set_variant(pm_code *c, int op, uint32_t rg, uint32_t vec) {
     const bool reset = rg == 0 && vec == 0;
-    if (!reset && ((rg != 4 && rg != 8 && rg != 16) || (vec != 2 && vec != 4 && vec != 12 && vec != 14)))
+    if (!reset && ((rg != 4 && rg != 8 && rg != 16) ||
+                   (vec != 2 && vec != 4 && vec != 12 && vec != 14 && vec != 22 && vec != 24 &&
+                    vec != kVecBitslice) || (vec == kVecBitslice && rg != 8)))
         return PM_EINVAL;
     if (op == 4) {
         set_apply_variant(static_cast<int>(rg), static_cast<int>(vec));
@@ -481,7 +504,8 @@ pm_status pm_autotune_encode(pm_code *c, const uint8_t *X, size_t x_ld, uint8_t 
     int brg = 0, bvec = 0;
     pm_status rc = PM_OK;
     for (int rg : {4, 8, 16}) {
-        for (int vec : {2, 4, 12, 14}) {
+        for (int vec : {2, 4, 12, 14, 22, 24, kVecBitslice}) {
+            if (vec == kVecBitslice && rg != 8) continue;   // one specialization per matrix
             pm_set_variant(c, 0, static_cast<uint32_t>(rg), static_cast<uint32_t>(vec));
             rc = pm_encode(c, X, x_ld, out, out_ld, s, stream);   // warm-up (and upload)
             if (rc != PM_OK) break;

@@ -8,6 +8,7 @@
 #include <mutex>
 #include <string>
 
+#include "bitslice.hpp"
 #include "gf256.hpp"
 #include "program.hpp"
 
@@ -42,13 +43,22 @@ struct DevCopy {
 // the upload until it is known to be complete.
 struct ProgEntry {
     Program prog;
+    Mat A;                      // the matrix (for specialized kernels)
+    std::vector<int> in_map;
     std::mutex mu;
     std::map<int, DevCopy> dev;
+    bool bs_tried = false;
+    std::unique_ptr<BsProgram> bs;   // bit-sliced specialization, if eligible
     ~ProgEntry();
+    // The bit-sliced specialization, generated on first use; nullptr when
+    // the matrix is too large to specialize.
+    BsProgram *bitslice();
     int device_ptr(hipStream_t user, const uint32_t **out);
     // Same, but returns only once the copy has landed (for plans and graphs).
     int device_ptr_sync(const uint32_t **out);
 };
+
+constexpr int kVecBitslice = 32;   // variant code of the bit-sliced specialization
 
 struct Variant {
     int rg = 0;   // 0 = cost model

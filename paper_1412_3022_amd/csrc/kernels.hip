@@ -263,6 +263,115 @@ __global__ __launch_bounds__(kThreads) void pm_apply_scalar(ApplyArgs a) {
     }
 }
 
+// ---- software-pipelined kernel ----------------------------------------------
+// For row groups of at most MAXC columns: while a wave multiplies one unit,
+// the loads of every column of its next unit are already in flight (two
+// register buffers, used alternately), so each wave keeps MAXC * 64 * 4 * VEC
+// bytes of loads outstanding instead of one column pair.  The loads of a
+// unit are issued unconditionally (columns past the group's end re-read its
+// first column) so the compiler can wait on exactly the older unit's loads.
+// Units that do not fit (partial tiles, copy groups, wider groups) take the
+// plain path.
+template <int RG, int VEC, int MAXC>
+struct Pipe {
+    static constexpr uint64_t kTile = static_cast<uint64_t>(kThreads) * 4 * VEC;
+
+    // Issue all loads of unit u into x when it can take the fast path.
+    static __device__ __forceinline__ bool prefetch(const ApplyArgs &a, cptr prog, uint32_t u,
+                                                    uint32_t (&x)[MAXC][VEC]) {
+        const uint32_t tile = u / a.ngroups;
+        const uint32_t grp = u - tile * a.ngroups;
+        const Lane<VEC> ln(tile * kTile, a.s);
+        const cptr g = prog + kHeaderWords + grp * kGroupWords;
+        const uint32_t ncols = g[2];
+        if (!ln.full || g[0] != 0 || ncols > MAXC) return false;
+        const cptr cols = prog + g[3];
+        const uint8_t *inb = a.in + ln.off;
+        // One scalar fetch of MAXC column ids (the program pads the id list),
+        // then branch-free selects: every load issues back to back.
+        uint32_t cw[MAXC];
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) cw[c] = cols[c];
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) {
+            const uint32_t col = static_cast<uint32_t>(c) < ncols ? cw[c] : cw[0];
+            load_chunk<VEC, true>(inb + static_cast<uint64_t>(col) * a.in_ld, 4 * VEC, x[c]);
+        }
+        return true;
+    }
+
+    static __device__ __forceinline__ void compute(const ApplyArgs &a, cptr prog, uint32_t u,
+                                                   const uint32_t (&x)[MAXC][VEC]) {
+        const uint32_t tile = u / a.ngroups;
+        const uint32_t grp = u - tile * a.ngroups;
+        const Lane<VEC> ln(tile * kTile, a.s);
+        const cptr g = prog + kHeaderWords + grp * kGroupWords;
+        const uint32_t ncols = g[2];
+        const ScalarTables tabs{prog + g[4], prog + g[6]};
+        uint32_t acc[RG][VEC] = {};
+#pragma unroll
+        for (int c = 0; c < MAXC; c += 2) {
+            if (static_cast<uint32_t>(c) < ncols) {
+                Fields<VEC> f0, f1;
+                split<VEC>(x[c], f0);
+                split<VEC>(x[c + 1], f1);
+                tabs.template pair<RG, VEC>(acc, f0, f1, static_cast<uint32_t>(c));
+            }
+        }
+        store_rows<RG, VEC, true>(acc, prog + g[5], g[1], a.out, a.out_ld, ln.off, 4 * VEC);
+    }
+
+    // The plain path for a unit that cannot be pipelined.
+    static __device__ __forceinline__ void plain(const ApplyArgs &a, cptr prog, uint32_t u) {
+        const uint32_t tile = u / a.ngroups;
+        const uint32_t grp = u - tile * a.ngroups;
+        const Lane<VEC> ln(tile * kTile, a.s);
+        if (!ln.active) return;
+        const cptr g = prog + kHeaderWords + grp * kGroupWords;
+        const cptr cols = prog + g[3], rows = prog + g[5];
+        if (g[0] == 0) {
+            const ScalarTables tabs{prog + g[4], prog + g[6]};
+            uint32_t acc[RG][VEC] = {};
+            if (ln.full) {
+                run_columns<RG, VEC, true>(acc, tabs, cols, 0, g[2], a.in + ln.off, a.in_ld, 4 * VEC);
+                store_rows<RG, VEC, true>(acc, rows, g[1], a.out, a.out_ld, ln.off, 4 * VEC);
+            } else {
+                run_columns<RG, VEC, false>(acc, tabs, cols, 0, g[2], a.in + ln.off, a.in_ld, ln.avail);
+                store_rows<RG, VEC, false>(acc, rows, g[1], a.out, a.out_ld, ln.off, ln.avail);
+            }
+        } else if (ln.full) {
+            copy_rows<VEC, true>(cols, rows, g[1], a.in, a.in_ld, a.out, a.out_ld, ln.off, 4 * VEC);
+        } else {
+            copy_rows<VEC, false>(cols, rows, g[1], a.in, a.in_ld, a.out, a.out_ld, ln.off, ln.avail);
+        }
+    }
+};
+
+template <int RG, int VEC, int MAXC>
+__global__ __launch_bounds__(kThreads) void pm_apply_pipe(ApplyArgs a) {
+    using P = Pipe<RG, VEC, MAXC>;
+    const cptr prog = (cptr)(a.prog);
+    const UnitRange ur(a.nwork, a.per_xcd);
+    uint32_t xa[MAXC][VEC], xb[MAXC][VEC];
+    uint32_t u = ur.u;
+    if (u >= ur.end) return;
+    bool fa = P::prefetch(a, prog, u, xa), fb = false;
+    while (true) {
+        const uint32_t u2 = u + ur.step;
+        fb = u2 < ur.end && P::prefetch(a, prog, u2, xb);
+        if (fa) P::compute(a, prog, u, xa);
+        else P::plain(a, prog, u);
+        u = u2;
+        if (u >= ur.end) break;
+        const uint32_t u3 = u + ur.step;
+        fa = u3 < ur.end && P::prefetch(a, prog, u3, xa);
+        if (fb) P::compute(a, prog, u, xb);
+        else P::plain(a, prog, u);
+        u = u3;
+        if (u >= ur.end) break;
+    }
+}
+
 // ---- LDS-table kernel --------------------------------------------------------
 // Every wave of the work-group reaches every barrier: waves past the block
 // end skip only their loads, arithmetic and stores, and the unit sequence and
@@ -447,8 +556,9 @@ static uint32_t resident_groups(K kernel, int *ncu_out) {
     return static_cast<uint32_t>(blocks);
 }
 
-template <int RG, int VEC, bool LDS>
+template <int RG, int VEC, int KIND>   // KIND: 0 scalar, 1 LDS, 2 pipelined (<= 16 columns)
 static hipError_t launch_apply(const PmkApply &h, hipStream_t st) {
+    constexpr bool LDS = KIND == 1;
     constexpr uint64_t kTile = static_cast<uint64_t>(kThreads) * 4 * VEC;
     const uint64_t ntiles = (h.s + kTile - 1) / kTile;
     const uint64_t nwork = ntiles * h.ngroups;
@@ -456,15 +566,19 @@ static hipError_t launch_apply(const PmkApply &h, hipStream_t st) {
     if (nwork > 0x7fffff00ull) return hipErrorInvalidValue;
     int ncu = 0;
     uint32_t per_cu;
-    if constexpr (LDS) per_cu = resident_groups(pm_apply_lds<RG, VEC>, &ncu);
+    if constexpr (KIND == 1) per_cu = resident_groups(pm_apply_lds<RG, VEC>, &ncu);
+    else if constexpr (KIND == 2) per_cu = resident_groups(pm_apply_pipe<RG, VEC, 16>, &ncu);
     else per_cu = resident_groups(pm_apply_scalar<RG, VEC>, &ncu);
     const uint64_t resident = static_cast<uint64_t>(per_cu) * static_cast<uint64_t>(ncu);
     uint64_t grid = nwork < resident ? nwork : resident;
     grid = (grid + 7) / 8 * 8;
     ApplyArgs a{h.in, h.in_ld, h.out, h.out_ld, h.s, h.prog, h.ngroups,
                 static_cast<uint32_t>(nwork), static_cast<uint32_t>(grid / 8u), kLdsSlots};
-    if constexpr (LDS)
+    if constexpr (KIND == 1)
         hipLaunchKernelGGL((pm_apply_lds<RG, VEC>), dim3(static_cast<uint32_t>(grid)), dim3(kThreads), 0, st, a);
+    else if constexpr (KIND == 2)
+        hipLaunchKernelGGL((pm_apply_pipe<RG, VEC, 16>), dim3(static_cast<uint32_t>(grid)), dim3(kThreads), 0, st,
+                           a);
     else
         hipLaunchKernelGGL((pm_apply_scalar<RG, VEC>), dim3(static_cast<uint32_t>(grid)), dim3(kThreads), 0, st, a);
     return hipGetLastError();
@@ -511,21 +625,27 @@ extern "C" hipError_t pmk_batch(int rg, int vec, const PmkBatch *h, hipStream_t 
 extern "C" int pmk_tile_bytes(int vec) { return kThreads * 4 * (vec % 10); }
 
 // vec: dwords per lane (2 or 4) with scalar tables; 12 or 14 for the same
-// widths with LDS-staged tables.
+// widths with LDS-staged tables; 22 or 24 for the software-pipelined kernel.
 extern "C" hipError_t pmk_apply(int rg, int vec, const PmkApply *h, hipStream_t st) {
     switch (rg * 100 + vec) {
-        case 402: return launch_apply<4, 2, false>(*h, st);
-        case 404: return launch_apply<4, 4, false>(*h, st);
-        case 802: return launch_apply<8, 2, false>(*h, st);
-        case 804: return launch_apply<8, 4, false>(*h, st);
-        case 1602: return launch_apply<16, 2, false>(*h, st);
-        case 1604: return launch_apply<16, 4, false>(*h, st);
-        case 412: return launch_apply<4, 2, true>(*h, st);
-        case 414: return launch_apply<4, 4, true>(*h, st);
-        case 812: return launch_apply<8, 2, true>(*h, st);
-        case 814: return launch_apply<8, 4, true>(*h, st);
-        case 1612: return launch_apply<16, 2, true>(*h, st);
-        case 1614: return launch_apply<16, 4, true>(*h, st);
+        case 402: return launch_apply<4, 2, 0>(*h, st);
+        case 404: return launch_apply<4, 4, 0>(*h, st);
+        case 802: return launch_apply<8, 2, 0>(*h, st);
+        case 804: return launch_apply<8, 4, 0>(*h, st);
+        case 1602: return launch_apply<16, 2, 0>(*h, st);
+        case 1604: return launch_apply<16, 4, 0>(*h, st);
+        case 412: return launch_apply<4, 2, 1>(*h, st);
+        case 414: return launch_apply<4, 4, 1>(*h, st);
+        case 812: return launch_apply<8, 2, 1>(*h, st);
+        case 814: return launch_apply<8, 4, 1>(*h, st);
+        case 1612: return launch_apply<16, 2, 1>(*h, st);
+        case 1614: return launch_apply<16, 4, 1>(*h, st);
+        case 422: return launch_apply<4, 2, 2>(*h, st);
+        case 424: return launch_apply<4, 4, 2>(*h, st);
+        case 822: return launch_apply<8, 2, 2>(*h, st);
+        case 824: return launch_apply<8, 4, 2>(*h, st);
+        case 1622: return launch_apply<16, 2, 2>(*h, st);
+        case 1624: return launch_apply<16, 4, 2>(*h, st);
         default: return hipErrorInvalidValue;
     }
 }

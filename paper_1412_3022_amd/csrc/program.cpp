@@ -151,7 +151,8 @@ Program build_program(const Mat &A, int rg, const std::vector<int> &in_map) {
     // Absolute word offsets.
     const uint32_t base_rows = kHeaderWords + static_cast<uint32_t>(rec.size());
     const uint32_t base_cols = base_rows + static_cast<uint32_t>(rowids.size());
-    uint32_t base_tab4 = base_cols + static_cast<uint32_t>(colids.size());
+    // 16 spare words after the column ids: kernels may fetch a fixed 16 ids.
+    uint32_t base_tab4 = base_cols + static_cast<uint32_t>(colids.size()) + 16u;
     base_tab4 = (base_tab4 + 15u) & ~15u;  // 64-byte aligned tables
     uint32_t base_tab1 = base_tab4 + static_cast<uint32_t>(tab4.size());
     for (size_t g = 0; g < groups.size(); ++g) {

@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "_lib", "libpmrc.so")
@@ -195,7 +196,6 @@ class Code:
         self.d = k if kind == PM_RS else d
 
     def __del__(self):
-        import sys
         h, self.h = getattr(self, "h", None), None
         # At interpreter exit the HIP runtime may already be gone; the process
         # frees everything anyway.
@@ -289,7 +289,6 @@ class Batch:
         self.codes = [it["code"] for it in items]   # keep codes alive
 
     def __del__(self):
-        import sys
         h, self.h = getattr(self, "h", None), None
         if h and _L is not None and not sys.is_finalizing():
             _L.pm_batch_destroy(h)
@@ -383,7 +382,6 @@ class Server:
             _lib().pm_server_destroy(h)
 
     def __del__(self):
-        import sys
         if not sys.is_finalizing():
             self.close()
 

@@ -15,7 +15,7 @@ from paper_1412_3022_amd import pm, synth
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = [(rg, vec) for rg in (4, 8, 16) for vec in (2, 4, 12, 14)]
+VARIANTS = [(rg, vec) for rg in (4, 8, 16) for vec in (2, 4, 12, 14, 22, 24)] + [(8, 32)]
 
 
 def _rand(seed, rows, s):
@@ -23,7 +23,7 @@ def _rand(seed, rows, s):
 
 
 def _oracle_for(kw):
-    kind = {pm.PM_MSR: O.MSR, pm.PM_MBR: O.MBR, pm.PM_RS: O.RS}[kw["kind"]]
+    kind = {pm.PM_MSR: O.MSR, pm.PM_MBR: O.MBR, pm.PM_RS: O.RS}[kw.get("kind", pm.PM_MSR)]
     cons = O.VANILLA if kw.get("construction", pm.PM_SPARSE) == pm.PM_VANILLA else O.SPARSE
     x = np.array(kw["x"]) if kw.get("x") is not None else None
     return O.Code(kind, kw["k"], kw["d"], kw["n"], cons, kw.get("systematic", True), x=x)
@@ -267,3 +267,54 @@ def test_k16_sparse_encode_repair_decode():
         xo = out_regions(c.B, s)
         c.decode(K, to_regions(Y), xo, s)
         assert np.array_equal(read(xo, s), X)
+
+
+# ------------------------------------------------- bit-sliced specialization --
+BS_CODES = [
+    ("msr4", dict(k=4, d=6, n=8)),
+    ("msr8", dict(k=8, d=14, n=16)),
+    ("mbr8", dict(k=8, d=14, n=16, kind=pm.PM_MBR)),
+    ("rs", dict(k=8, d=8, n=16, kind=pm.PM_RS)),
+    ("msr3-vanilla-cfg1", dict(k=3, d=4, n=6, kind=pm.PM_MSR, construction=pm.PM_VANILLA, x=list(range(1, 7)))),
+]
+
+
+@pytest.mark.parametrize("name,kw", BS_CODES, ids=[c[0] for c in BS_CODES])
+# 100: below one tile (table kernel); 2048: one tile; 2053: byte tail only;
+# 2*2048+112: window tile, no byte tail; 4095, 3*2048+17, 40*2048+2047:
+# window tile and byte tail.
+@pytest.mark.parametrize("s", [100, 2048, 2053, 2 * 2048 + 112, 4095, 3 * 2048 + 17, 40 * 2048 + 2047])
+def test_bitslice_encode_matches_oracle(name, kw, s):
+    """The hipRTC-specialized bit-sliced kernel (full 2 KiB wave tiles, the
+    overlapping window tile and the byte tail) against the oracle byte for
+    byte, with guard bytes past s checked."""
+    print("bitslice encode %s s=%d" % (name, s), flush=True)
+    c = pm.Code(**kw)
+    o = _oracle_for(kw)
+    c.set_variant(pm.OP_ENCODE, 8, 32)
+    X = _rand(s + len(name), c.B, s)
+    assert np.array_equal(_gpu_encode(c, X, s), o.encode(X, nthreads=8))
+
+
+def test_bitslice_decode_and_newcomer_k8():
+    print("bitslice decode/newcomer", flush=True)
+    c = pm.Code(k=8, d=14, n=16)
+    o = O.Code(O.MSR, 8, 14, 16, O.SPARSE)
+    for op in (pm.OP_DECODE, pm.OP_NEWCOMER):
+        c.set_variant(op, 8, 32)
+    s = 5 * 2048 + 300
+    X = _rand(77, c.B, s)
+    P = o.encode(X, nthreads=8)
+    nodes = _nodes(c, X, P)
+    st = synth.Stream(88)
+    for _ in range(3):
+        K = st.subset(c.n, c.k)
+        xo = out_regions(c.B, s)
+        c.decode(K, to_regions(np.concatenate([nodes[i] for i in K])), xo, s)
+        assert np.array_equal(read(xo, s), X)
+        f = st.below(c.n)
+        H = st.subset(c.n, c.d, exclude=[f])
+        recv = np.stack([O.apply(o.helper_row(f), nodes[h])[0] for h in H])
+        rout = out_regions(c.alpha, s)
+        c.repair_newcomer(f, H, to_regions(recv), rout, s)
+        assert np.array_equal(read(rout, s), nodes[f])
