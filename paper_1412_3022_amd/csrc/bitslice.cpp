@@ -18,15 +18,21 @@
 //
 // Launch geometry: each lane owns 32 bytes of a wave tile (two 16-byte
 // pieces 1 KiB apart, so every load instruction is one contiguous KiB).
-// Work-groups are dealt to the 8 XCDs round-robin; on each XCD every slot
-// (work-group) is bound to one row group and the slots of a group stride over
-// that XCD's range of tiles.  All groups of a tile therefore run at once in
-// one L2 (their shared source columns are read from HBM once), while each
-// work-group executes only one group's code (the instruction cache holds it).
+// Work-groups of 4 waves are dealt to the 8 XCDs round-robin; on each XCD
+// every slot (work-group) is bound to one row group and the slots of a group
+// stride over that XCD's range of tiles.  All groups of a tile therefore run
+// at about the same time in one L2 (shared source columns are mostly read
+// from HBM once), while each work-group executes only one group's code (the
+// instruction cache holds it).  A wave loads the two columns after the one
+// it multiplies (the k=8 encode then needs 125 VGPRs: 4 waves per SIMD), and
+// the outputs leave with streaming (nontemporal) stores.
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
 #include <algorithm>
+#include <condition_variable>
+#include <deque>
+#include <thread>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -45,6 +51,8 @@ namespace pmrc {
 namespace {
 
 constexpr int kGroupWords = 8;
+constexpr size_t kPrefetch = 2;   // columns loaded ahead of the one being multiplied
+constexpr int kWaves = 4;         // waves per work-group
 constexpr int kHeaderWords = 4;
 
 const char *kPrelude = R"(
@@ -52,6 +60,8 @@ typedef unsigned int u32;
 typedef unsigned long long u64;
 typedef u32 u32x4 __attribute__((ext_vector_type(4)));
 #define X3(a, b, c) __builtin_amdgcn_bitop3_b32((a), (b), (c), 0x96)
+// outputs are written once and not read back by the kernel: streaming stores
+__device__ __forceinline__ void ST(unsigned char *d, u32x4 v) { __builtin_nontemporal_store(v, (u32x4 *)d); }
 #define DS(a, b, sh, m) { u32 t_ = (((a) >> (sh)) ^ (b)) & (m); (b) ^= t_; (a) ^= t_ << (sh); }
 #define TR8(A0, A1, A2, A3, A4, A5, A6, A7) { \
   DS(A0, A4, 4, 0x0F0F0F0Fu) DS(A1, A5, 4, 0x0F0F0F0Fu) DS(A2, A6, 4, 0x0F0F0F0Fu) DS(A3, A7, 4, 0x0F0F0F0Fu) \
@@ -111,13 +121,24 @@ void emit_table_group(std::ostringstream &o, int gi, const Grp &G) {
         for (int i = 0; i < 8; ++i) o << (i ? "," : "") << " q" << r << "_" << i << " = 0u";
         o << ";\n";
     }
+    // Columns with a nonzero coefficient (padding columns are skipped).  The
+    // loads of column j + kPrefetch are issued before column j is multiplied,
+    // so every wave keeps several columns in flight.
+    std::vector<size_t> used;
     for (size_t ci = 0; ci < G.cols.size(); ++ci) {
-        // Skip padding columns whose coefficients are all zero.
         bool any = false;
         for (int r = 0; r < n; ++r) any |= G.coef[r][ci] != 0;
-        if (!any) continue;
-        o << "  {\n    const unsigned char *p = in + (u64)" << G.cols[ci] << "u * ld + off;\n"
-          << "    const u32x4 lo = *(const u32x4 *)p, hi = *(const u32x4 *)(p + 1024);\n"
+        if (any) used.push_back(ci);
+    }
+    auto load = [&](size_t j) {
+        o << "  const u32x4 x" << j << "l = *(const u32x4 *)(in + (u64)" << G.cols[used[j]] << "u * ld + off), x" << j
+          << "h = *(const u32x4 *)(in + (u64)" << G.cols[used[j]] << "u * ld + off + 1024);\n";
+    };
+    for (size_t j = 0; j < used.size() && j < kPrefetch; ++j) load(j);
+    for (size_t j = 0; j < used.size(); ++j) {
+        const size_t ci = used[j];
+        if (j + kPrefetch < used.size()) load(j + kPrefetch);
+        o << "  {\n    const u32x4 lo = x" << j << "l, hi = x" << j << "h;\n"
           << "    u32 P0 = lo.x, P1 = lo.y, P2 = lo.z, P3 = lo.w, P4 = hi.x, P5 = hi.y, P6 = hi.z, P7 = hi.w;\n"
           << "    TR8(P0, P1, P2, P3, P4, P5, P6, P7)\n";
         struct Eq { int r, i; unsigned lo, hi; };
@@ -174,8 +195,8 @@ void emit_table_group(std::ostringstream &o, int gi, const Grp &G) {
         o << "  TR8(";
         for (int i = 0; i < 8; ++i) o << (i ? ", " : "") << "q" << r << "_" << i;
         o << ")\n  { unsigned char *d = out + (u64)" << G.rows[r] << "u * old + off;\n"
-          << "    *(u32x4 *)d = u32x4{q" << r << "_0, q" << r << "_1, q" << r << "_2, q" << r << "_3};\n"
-          << "    *(u32x4 *)(d + 1024) = u32x4{q" << r << "_4, q" << r << "_5, q" << r << "_6, q" << r << "_7}; }\n";
+          << "    ST(d, u32x4{q" << r << "_0, q" << r << "_1, q" << r << "_2, q" << r << "_3});\n"
+          << "    ST(d + 1024, u32x4{q" << r << "_4, q" << r << "_5, q" << r << "_6, q" << r << "_7}); }\n";
     }
     o << "}\n";
 }
@@ -187,7 +208,7 @@ void emit_copy_group(std::ostringstream &o, int gi, const Grp &G) {
         o << "  { const unsigned char *p = in + (u64)" << G.cols[i] << "u * ld + off;\n"
           << "    unsigned char *d = out + (u64)" << G.rows[i] << "u * old + off;\n"
           << "    const u32x4 lo = *(const u32x4 *)p, hi = *(const u32x4 *)(p + 1024);\n"
-          << "    *(u32x4 *)d = lo; *(u32x4 *)(d + 1024) = hi; }\n";
+          << "    ST(d, lo); ST(d + 1024, hi); }\n";
     o << "}\n";
 }
 
@@ -248,7 +269,7 @@ std::unique_ptr<BsProgram> bs_generate(const Program &p8) {
     // [s16 - 2048, s16), which overlaps tile nfull-1 and stores the same bytes
     // it does.  The s - s16 bytes after s16 are done byte by byte by the
     // lanes of the wave that takes the last tile.
-    o << "extern \"C\" __global__ __launch_bounds__(512) void pmbs(BsArgs a) {\n"
+    o << "extern \"C\" __global__ __launch_bounds__(" << 64 * kWaves << ") void pmbs(BsArgs a) {\n"
       << "  const u32 wave = threadIdx.x / 64, lane = threadIdx.x % 64;\n"
       << "  const u32 xcd = blockIdx.x % 8u, slot = blockIdx.x / 8u;\n"
       << "  const u32 per = (a.ntiles + 7u) / 8u, t0 = xcd * per;\n"
@@ -260,7 +281,7 @@ std::unique_ptr<BsProgram> bs_generate(const Program &p8) {
       << "  for (u32 g = slot % G; g < G; g += a.P) {\n"
       << "    const u32 R = a.P >= G ? (a.P - 1u - g) / G + 1u : 1u;\n"
       << "    const u32 r = a.P >= G ? slot / G : 0u;\n"
-      << "    for (u32 t = t0 + r * 8u + wave; t < t1; t += R * 8u) {\n"
+      << "    for (u32 t = t0 + r * " << kWaves << "u + wave; t < t1; t += R * " << kWaves << "u) {\n"
       << "      const u64 tile = t < a.nfull ? (u64)t * 2048u : s16 - 2048u;\n"
       << "      switch (g) {\n";
     for (int g = 0; g < G; ++g) o << "        case " << g << ": g" << g << "(a.in, a.ld, a.out, a.old, tile + lane * 16u); break;\n";
@@ -279,15 +300,21 @@ std::unique_ptr<BsProgram> bs_generate(const Program &p8) {
     return bp;
 }
 
+static int bs_compile_locked(BsProgram &bp);
+
 int bs_compile(BsProgram &bp) {
     std::lock_guard<std::mutex> lk(bp.mu);
     if (bp.compiled) return bp.compile_status;
     bp.compiled = true;
+    bp.compile_status = bs_compile_locked(bp);
+    bp.state.store(bp.compile_status == ST_OK ? BS_READY : BS_FAILED, std::memory_order_release);
+    return bp.compile_status;
+}
+
+static int bs_compile_locked(BsProgram &bp) {
     hiprtcProgram prog;
-    if (hiprtcCreateProgram(&prog, bp.source.c_str(), "pm_bitslice.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS) {
-        bp.compile_status = ST_EHIP;
-        return bp.compile_status;
-    }
+    if (hiprtcCreateProgram(&prog, bp.source.c_str(), "pm_bitslice.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
+        return ST_EHIP;
     const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17"};
     hiprtcResult r = hiprtcCompileProgram(prog, 3, opts);
     if (r != HIPRTC_SUCCESS) {
@@ -297,16 +324,68 @@ int bs_compile(BsProgram &bp) {
         if (ls) hiprtcGetProgramLog(prog, &log[0]);
         g_hip_msg = "hipRTC: " + log.substr(0, 2000);
         hiprtcDestroyProgram(&prog);
-        bp.compile_status = ST_EHIP;
-        return bp.compile_status;
+        return ST_EHIP;
     }
     size_t cs = 0;
     hiprtcGetCodeSize(prog, &cs);
     bp.code.resize(cs);
     hiprtcGetCode(prog, bp.code.data());
     hiprtcDestroyProgram(&prog);
-    bp.compile_status = ST_OK;
     return ST_OK;
+}
+
+// One compile thread per process.  Its queue holds references, so programs
+// dropped by their owners meanwhile stay alive until compiled.  At exit the
+// thread is stopped and joined (an in-flight hipRTC run is waited for); it
+// makes no HIP runtime calls, only hipRTC ones.
+namespace {
+class Compiler {
+    std::mutex mu_;
+    std::condition_variable cv_;
+    std::deque<std::shared_ptr<BsProgram>> q_;
+    bool stop_ = false;
+    std::thread th_;
+
+    void run() {
+        for (;;) {
+            std::shared_ptr<BsProgram> p;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return stop_ || !q_.empty(); });
+                if (stop_) return;
+                p = std::move(q_.front());
+                q_.pop_front();
+            }
+            (void)bs_compile(*p);
+        }
+    }
+
+  public:
+    void submit(const std::shared_ptr<BsProgram> &p) {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (stop_) return;
+        if (!th_.joinable()) th_ = std::thread(&Compiler::run, this);
+        q_.push_back(p);
+        cv_.notify_one();
+    }
+    ~Compiler() {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stop_ = true;
+            // programs still queued are left allocated: dropping a last
+            // reference here would unload modules from a static destructor
+            if (!q_.empty()) new std::deque<std::shared_ptr<BsProgram>>(std::move(q_));
+        }
+        cv_.notify_all();
+        if (th_.joinable()) th_.join();
+    }
+};
+Compiler g_compiler;
+}  // namespace
+
+void bs_compile_async(const std::shared_ptr<BsProgram> &bp) {
+    int expect = BS_NONE;
+    if (bp && bp->state.compare_exchange_strong(expect, BS_QUEUED)) g_compiler.submit(bp);
 }
 
 BsProgram::~BsProgram() {
@@ -329,7 +408,7 @@ int bs_launch(BsProgram &bp, const uint8_t *in, uint64_t in_ld, uint8_t *out, ui
             if ((e = hipModuleLoadData(&m->mod, bp.code.data())) != hipSuccess) return hip_fail(e);
             if ((e = hipModuleGetFunction(&m->fn, m->mod, "pmbs")) != hipSuccess) return hip_fail(e);
             int per_cu = 0, ncu = 0;
-            if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, m->fn, 512, 0) != hipSuccess ||
+            if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, m->fn, 64 * kWaves, 0) != hipSuccess ||
                 per_cu < 1)
                 per_cu = 1;
             if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, devid) != hipSuccess || ncu < 8)
@@ -355,7 +434,7 @@ int bs_launch(BsProgram &bp, const uint8_t *in, uint64_t in_ld, uint8_t *out, ui
            static_cast<uint32_t>(m->P)};
     size_t size = sizeof(args);
     void *cfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &args, HIP_LAUNCH_PARAM_BUFFER_SIZE, &size, HIP_LAUNCH_PARAM_END};
-    e = hipModuleLaunchKernel(m->fn, static_cast<unsigned>(8 * m->P), 1, 1, 512, 1, 1, 0, st, nullptr, cfg);
+    e = hipModuleLaunchKernel(m->fn, static_cast<unsigned>(8 * m->P), 1, 1, 64 * kWaves, 1, 1, 0, st, nullptr, cfg);
     if (e != hipSuccess) return hip_fail(e);
     return ST_OK;
 }

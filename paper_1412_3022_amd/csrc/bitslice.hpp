@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -18,6 +19,9 @@ struct BsModule {
     int P = 0;   // work-group slots per XCD
 };
 
+// Compile state of a BsProgram, readable without its mutex.
+enum BsState { BS_NONE = 0, BS_QUEUED = 1, BS_READY = 2, BS_FAILED = 3 };
+
 struct BsProgram {
     std::string source;
     int ngroups = 0;
@@ -25,6 +29,7 @@ struct BsProgram {
     std::mutex mu;
     bool compiled = false;
     int compile_status = 0;
+    std::atomic<int> state{BS_NONE};
     std::vector<char> code;   // gfx950 code object
     std::map<int, BsModule> dev;
     ~BsProgram();
@@ -37,7 +42,12 @@ constexpr uint64_t kBsTileBytes = 2048;   // bytes per wave tile
 
 // Generate the source for a program built with 8 rows per group.
 std::unique_ptr<BsProgram> bs_generate(const Program &p8);
+// Compile now (blocks for the hipRTC run; a no-op once compiled).
 int bs_compile(BsProgram &bp);
+// Queue the compile on the library's compile thread unless it is queued or
+// done already; the caller keeps using the table kernel until state is
+// BS_READY.  The thread holds a reference, so the owner may drop its own.
+void bs_compile_async(const std::shared_ptr<BsProgram> &bp);
 // Run the kernel over bytes [0, s) of every block, s >= kBsTileBytes (else
 // ST_EINVAL).  Bases 16-byte aligned, ld multiples of 16 (as checked by the
 // entry points).

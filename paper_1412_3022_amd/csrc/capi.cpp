@@ -99,7 +99,7 @@ int ProgEntry::device_ptr_sync(const uint32_t **out) {
     return ST_OK;
 }
 
-BsProgram *ProgEntry::bitslice() {
+std::shared_ptr<BsProgram> ProgEntry::bitslice() {
     std::lock_guard<std::mutex> lk(mu);
     if (!bs_tried) {
         bs_tried = true;
@@ -107,7 +107,7 @@ BsProgram *ProgEntry::bitslice() {
         std::unique_ptr<BsProgram> b = bs_generate(p8);
         if (b->est_ops <= kBsMaxOps) bs = std::move(b);
     }
-    return bs.get();
+    return bs;
 }
 
 // ---- variant choice ----------------------------------------------------------
@@ -159,8 +159,16 @@ int launch_program(ProgEntry &pe, int vec, const uint8_t *in, size_t in_ld, size
         // blocks shorter than one tile, and matrices too large for a
         // specialized kernel, run on the table kernel
         if (s >= kBsTileBytes)
-            if (BsProgram *bp = pe.bitslice()) return bs_launch(*bp, in, in_ld, out, out_ld, s, stream);
+            if (std::shared_ptr<BsProgram> bp = pe.bitslice()) return bs_launch(*bp, in, in_ld, out, out_ld, s, stream);
         vec = 4;
+    } else if (vec == kVecAuto) {
+        if (s >= kBsTileBytes)
+            if (std::shared_ptr<BsProgram> bp = pe.bitslice()) {
+                if (bp->state.load(std::memory_order_acquire) == BS_READY)
+                    return bs_launch(*bp, in, in_ld, out, out_ld, s, stream);
+                bs_compile_async(bp);
+            }
+        vec = kVecTable;
     }
     const uint32_t *dprog = nullptr;
     if ((st = pe.device_ptr(stream, &dprog)) != ST_OK) return st;
@@ -185,7 +193,7 @@ void set_apply_variant(int rg, int vec) {
 ProgEntry *apply_program(const Mat &A, int *vec) {
     std::lock_guard<std::mutex> lk(g_apply_mu);
     const int rg = g_apply_var.rg ? g_apply_var.rg : Variant::pick_rg(A);
-    *vec = g_apply_var.vec ? g_apply_var.vec : 4;
+    *vec = g_apply_var.vec;
     auto key = std::make_tuple(A.rows, A.cols, A.v, rg);
     auto it = g_apply.find(key);
     if (it != g_apply.end()) return it->second.get();
@@ -277,7 +285,7 @@ int resolve_op(pm_code *c, int op, uint32_t failed, const uint32_t *ids, Resolve
     }
     std::lock_guard<std::mutex> lk(c->mu);
     const Variant &var = c->var[op];
-    r->vec = var.vec ? var.vec : 4;
+    r->vec = var.vec;
     switch (op) {
         case OPK_ENCODE: {
             const int rg = pick_rg_cached(c->var[0], m.enc);
@@ -434,6 +442,24 @@ pm_status pm_set_variant(pm_code *c, int op, uint32_t rg, uint32_t vec) {
     std::lock_guard<std::mutex> lk(c->mu);
     c->var[op].rg = static_cast<int>(rg);
     c->var[op].vec = reset ? 0 : static_cast<int>(vec);
+    return PM_OK;
+}
+
+pm_status pm_prepare(pm_code *c, int op, uint32_t failed, const uint32_t *ids, int wait, int *specialized) {
+    if (specialized) *specialized = 0;
+    if (!c || op < 0 || op > 3) return PM_EINVAL;
+    Resolved r;
+    int st = resolve_op(c, op, failed, ids, &r);
+    if (st != ST_OK) return static_cast<pm_status>(st);
+    if (r.vec != kVecAuto && r.vec != kVecBitslice) return PM_OK;   // an explicit table variant
+    std::shared_ptr<BsProgram> bp = r.pe->bitslice();
+    if (!bp) return PM_OK;
+    if (wait) {
+        if ((st = bs_compile(*bp)) != ST_OK) return static_cast<pm_status>(st);
+    } else {
+        bs_compile_async(bp);
+    }
+    if (specialized) *specialized = bp->state.load(std::memory_order_acquire) == BS_READY;
     return PM_OK;
 }
 

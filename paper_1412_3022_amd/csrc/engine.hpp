@@ -48,21 +48,26 @@ struct ProgEntry {
     std::mutex mu;
     std::map<int, DevCopy> dev;
     bool bs_tried = false;
-    std::unique_ptr<BsProgram> bs;   // bit-sliced specialization, if eligible
+    std::shared_ptr<BsProgram> bs;   // bit-sliced specialization, if eligible
     ~ProgEntry();
-    // The bit-sliced specialization, generated on first use; nullptr when
-    // the matrix is too large to specialize.
-    BsProgram *bitslice();
+    // The bit-sliced specialization, generated (not compiled) on first use;
+    // nullptr when the matrix is too large to specialize.
+    std::shared_ptr<BsProgram> bitslice();
     int device_ptr(hipStream_t user, const uint32_t **out);
     // Same, but returns only once the copy has landed (for plans and graphs).
     int device_ptr_sync(const uint32_t **out);
 };
 
 constexpr int kVecBitslice = 32;   // variant code of the bit-sliced specialization
+// Default variant: the bit-sliced kernel once its background compile is done
+// (blocks of at least one tile), the table kernel with kVecTable dwords per
+// lane until then.
+constexpr int kVecAuto = 0;
+constexpr int kVecTable = 2;
 
 struct Variant {
     int rg = 0;   // 0 = cost model
-    int vec = 0;  // 0 = default (4)
+    int vec = 0;  // kVecAuto or an explicit variant code
     static int pick_rg(const Mat &A);
 };
 
@@ -80,7 +85,7 @@ enum OpKind { OPK_ENCODE = 0, OPK_HELPER = 1, OPK_NEWCOMER = 2, OPK_DECODE = 3 }
 struct Resolved {
     ProgEntry *pe = nullptr;
     size_t in_n = 0, out_n = 0;
-    int vec = 4;
+    int vec = kVecAuto;
 };
 int resolve_op(pm_code *c, int op, uint32_t failed, const uint32_t *ids, Resolved *r);
 

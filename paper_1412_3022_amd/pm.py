@@ -72,6 +72,7 @@ def _lib():
         L.pm_apply.argtypes = [vp, u32, u32, vp, sz, vp, sz, sz, vp]
         L.pm_set_variant.argtypes = [vp, i32, u32, u32]
         L.pm_autotune_encode.argtypes = [vp, vp, sz, vp, sz, sz, u32, vp, u32p, u32p]
+        L.pm_prepare.argtypes = [vp, i32, u32, u32p, i32, ctypes.POINTER(ctypes.c_int)]
         L.pm_batch_plan.argtypes = [ctypes.POINTER(pm_batch_item), sz, u32, ctypes.POINTER(vp)]
         L.pm_batch_set_variant.argtypes = [vp, u32, u32]
         L.pm_batch_autotune.argtypes = [vp, u32, vp, u32p]
@@ -155,6 +156,14 @@ def pm_set_variant(h, op, rows_per_group, dwords_per_lane):
     return _lib().pm_set_variant(h, op, rows_per_group, dwords_per_lane)
 
 
+def pm_prepare(h, op, failed=0, ids=None, wait=True):
+    """Init phase of one operation; returns (status, specialized)."""
+    spec = ctypes.c_int()
+    st = _lib().pm_prepare(h, op, failed, _u32arr(ids) if ids is not None else None, 1 if wait else 0,
+                           ctypes.byref(spec))
+    return st, spec.value
+
+
 def pm_autotune_encode(h, x_ptr, x_ld, out_ptr, out_ld, block_bytes, reps=5, stream=0):
     rg, vec = ctypes.c_uint32(), ctypes.c_uint32()
     st = _lib().pm_autotune_encode(h, x_ptr, x_ld, out_ptr, out_ld, block_bytes, reps, stream or None,
@@ -218,6 +227,13 @@ class Code:
 
     def set_variant(self, op, rows_per_group, dwords_per_lane):
         _check(pm_set_variant(self.h, op, rows_per_group, dwords_per_lane), "pm_set_variant")
+
+    def prepare(self, op, failed=0, ids=None, wait=True):
+        """Build the operation's matrix and its bit-sliced kernel (compiled now
+        if wait, else in the background); True when that kernel is ready."""
+        st, spec = pm_prepare(self.h, op, failed, ids, wait)
+        _check(st, "pm_prepare")
+        return bool(spec)
 
     def encode(self, X, out, block_bytes, stream=None):
         xp, xld = _regions(X, self.B)

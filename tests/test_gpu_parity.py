@@ -318,3 +318,26 @@ def test_bitslice_decode_and_newcomer_k8():
         rout = out_regions(c.alpha, s)
         c.repair_newcomer(f, H, to_regions(recv), rout, s)
         assert np.array_equal(read(rout, s), nodes[f])
+
+
+def test_default_variant_before_and_after_specialization():
+    """Under the default variant an operation runs the table kernel until its
+    bit-sliced kernel is compiled (pm_prepare with wait forces that), then the
+    bit-sliced kernel: both results equal the oracle's."""
+    print("default variant: table then bit-sliced", flush=True)
+    c = pm.Code(k=8, d=14, n=16)
+    o = O.Code(O.MSR, 8, 14, 16, O.SPARSE)
+    s = 9 * 2048 + 77
+    X = _rand(4242, c.B, s)
+    P = o.encode(X, nthreads=8)
+    nodes = _nodes(c, X, P)
+    K = [2, 3, 5, 8, 9, 10, 12, 14]
+    Y = to_regions(np.concatenate([nodes[i] for i in K]))
+    for prepared in (False, True):
+        if prepared:
+            assert c.prepare(pm.OP_DECODE, ids=K) is True
+            assert c.prepare(pm.OP_ENCODE) is True
+        xo = out_regions(c.B, s)
+        c.decode(K, Y, xo, s)
+        assert np.array_equal(read(xo, s), X)
+        assert np.array_equal(_gpu_encode(c, X, s), P)

@@ -113,3 +113,48 @@ def test_data_call_argument_errors_need_no_gpu():
 def test_status_strings():
     for st in range(-6, 1):
         assert pm.status_string(st)
+
+
+# ---------------------------------------------- init phase / specialization --
+def test_prepare_compiles_bitsliced_kernels_without_gpu():
+    """pm_prepare builds an operation's matrix and compiles its bit-sliced
+    kernel with hipRTC, which needs no GPU; the kernel then counts as ready."""
+    c = pm.Code(k=4, d=6, n=8)
+    assert c.prepare(pm.OP_ENCODE) is True
+    assert c.prepare(pm.OP_HELPER, failed=5) is True
+    assert c.prepare(pm.OP_NEWCOMER, failed=5, ids=[0, 1, 2, 3, 4, 6]) is True
+    assert c.prepare(pm.OP_DECODE, ids=[1, 4, 6, 7]) is True
+
+
+def test_prepare_background_compile_becomes_ready():
+    import time
+    c = pm.Code(k=3, d=4, n=6)
+    st, spec = pm.pm_prepare(c.h, pm.OP_DECODE, 0, [0, 2, 5], wait=False)
+    assert st == pm.PM_OK
+    t0 = time.time()
+    while not spec and time.time() - t0 < 120:
+        time.sleep(0.05)
+        st, spec = pm.pm_prepare(c.h, pm.OP_DECODE, 0, [0, 2, 5], wait=False)
+        assert st == pm.PM_OK
+    assert spec == 1
+
+
+def test_prepare_reports_table_kernel_cases():
+    # an explicit table variant never switches to the specialized kernel
+    c = pm.Code(k=4, d=6, n=8)
+    c.set_variant(pm.OP_ENCODE, 8, 2)
+    assert c.prepare(pm.OP_ENCODE) is False
+    # the k=16 encode network is over the size limit: table kernel
+    assert pm.Code(k=16, d=30, n=32).prepare(pm.OP_ENCODE) is False
+
+
+@pytest.mark.parametrize("op,failed,ids", [
+    (pm.OP_DECODE, 0, [1, 1, 2, 3]),        # repeated node
+    (pm.OP_NEWCOMER, 5, [0, 1, 2, 3, 4, 5]),  # the failed node as its own helper
+    (pm.OP_HELPER, 8, None),               # no such node
+    (7, 0, None),                          # no such operation
+])
+def test_prepare_argument_errors(op, failed, ids):
+    c = pm.Code(k=4, d=6, n=8)
+    st, spec = pm.pm_prepare(c.h, op, failed, ids, wait=True)
+    assert st == pm.PM_EINVAL and spec == 0
