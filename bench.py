@@ -31,7 +31,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 NBUF = 8
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_msr_k8_sparse_encode_64MiB.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_1412_3022_amd", "csrc", "kernels.hip")
+CSRC = os.path.join(ROOT, "paper_1412_3022_amd", "csrc")
+# the source a kernel's code comes from: the bit-sliced kernel is generated at
+# run time by bitslice.cpp, the table kernels are compiled from kernels.hip
+BITSLICE_SRC = os.path.join(CSRC, "bitslice.cpp")
+TABLE_SRC = os.path.join(CSRC, "kernels.hip")
 
 
 def parse():
@@ -60,14 +64,27 @@ def calibrate_copy(torch, reps=10):
     print(json.dumps({"calibrate_copy_bytes": n, "reps": reps}), flush=True)
 
 
-def kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
+def kernel_name(variant):
+    """Name of the kernel a (rows per group, dwords per lane) variant runs, as
+    rocprofv3 reports it, and the source file its code comes from."""
+    rg, vec = variant
+    if vec == 32:
+        return "pmbs", BITSLICE_SRC
+    if vec > 20:
+        return "pm_apply_pipe<%d, %d, 16>" % (rg, vec - 20), TABLE_SRC
+    if vec > 10:
+        return "pm_apply_lds<%d, %d>" % (rg, vec - 10), TABLE_SRC
+    return "pm_apply_scalar<%d, %d>" % (rg, vec), TABLE_SRC
+
+
+def source_hash(path):
+    with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(kernel, src):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source."""
+    was taken on this kernel built from the current source."""
     if not os.path.exists(PROFILE_TRAFFIC):
         return None
     vals = {}
@@ -76,7 +93,7 @@ def measured_traffic():
             if "=" in line and not line.startswith("#"):
                 k, v = line.split("=", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("kernel_sha256_16") != kernel_hash():
+    if vals.get("kernel") != kernel or vals.get("source_sha256_16") != source_hash(src):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -146,6 +163,18 @@ def encode_case(torch, pm, synth, kw, S, seed, steps, warmup, nbuf=NBUF, tune=Tr
     return code, res
 
 
+def prepare_all(code, pm, f, H, K):
+    """Init phase of the timed operations (matrices, inverses and their
+    bit-sliced kernels), kept out of the data-phase timing as the paper's
+    evaluation does; returns its wall time in seconds."""
+    t0 = time.perf_counter()
+    code.prepare(pm.OP_ENCODE)
+    code.prepare(pm.OP_HELPER, failed=f)
+    code.prepare(pm.OP_NEWCOMER, failed=f, ids=H)
+    code.prepare(pm.OP_DECODE, ids=K)
+    return time.perf_counter() - t0
+
+
 def mbr_cases(torch, pm, synth, steps, warmup):
     """Configuration 3: PM-MBR (8,14,16), 64 MiB: encode, repair of node 8 from
     14 helpers (helper projections + newcomer solve), decode from a seeded
@@ -164,12 +193,14 @@ def mbr_cases(torch, pm, synth, steps, warmup):
 
     out = {}
     stream = torch.cuda.current_stream().cuda_stream
+    f = 8
+    H = [i for i in range(code.n) if i != f][:code.d]
+    K = synth.Stream(synth.CONFIG_SEED + 2).subset(code.n, code.k)
+    out["mbr_init_s"] = prepare_all(code, pm, f, H, K)
     P2 = torch.empty_like(P)
     wall, ev = Timer(torch).run(lambda i: pm.pm_encode(code.h, x.data_ptr(), s, P2.data_ptr(), s, s, stream),
                                 steps, warmup)
     out["mbr_encode_gbps"] = S * steps / wall / 1e9
-    f = 8
-    H = [i for i in range(code.n) if i != f][:code.d]
     nodes = [node(h) for h in H]
     recv = torch.empty((code.d, s), dtype=torch.uint8, device=dev)
     rout = torch.empty((code.alpha, s), dtype=torch.uint8, device=dev)
@@ -181,7 +212,6 @@ def mbr_cases(torch, pm, synth, steps, warmup):
 
     wall, ev = Timer(torch).run(repair, max(1, steps // 4), max(1, warmup // 4))
     out["mbr_repair_gbps"] = code.alpha * s * max(1, steps // 4) / wall / 1e9   # repaired bytes
-    K = synth.Stream(synth.CONFIG_SEED + 2).subset(code.n, code.k)
     Y = torch.cat([node(i) for i in K])
     xo = torch.empty_like(x)
     wall, ev = Timer(torch).run(lambda i: pm.pm_decode(code.h, K, Y.data_ptr(), s, xo.data_ptr(), s, s, stream),
@@ -210,6 +240,8 @@ def msr_repair_decode(torch, pm, synth, steps, warmup):
     out = {}
     f = 8
     H = [i for i in range(code.n) if i != f][:code.d]
+    K = synth.Stream(synth.CONFIG_SEED + 1).subset(code.n, code.k)
+    out["msr_init_s"] = prepare_all(code, pm, f, H, K)
     nodes = [node(h) for h in H]
     recv = torch.empty((code.d, s), dtype=torch.uint8, device=dev)
     rout = torch.empty((code.alpha, s), dtype=torch.uint8, device=dev)
@@ -222,7 +254,6 @@ def msr_repair_decode(torch, pm, synth, steps, warmup):
     n = max(1, steps // 4)
     wall, ev = Timer(torch).run(repair, n, max(1, warmup // 4))
     out["msr_repair_gbps"] = code.alpha * s * n / wall / 1e9
-    K = synth.Stream(synth.CONFIG_SEED + 1).subset(code.n, code.k)
     Y = torch.cat([node(i) for i in K])
     xo = torch.empty_like(x)
     wall, ev = Timer(torch).run(lambda i: pm.pm_decode(code.h, K, Y.data_ptr(), s, xo.data_ptr(), s, s, stream),
@@ -406,9 +437,10 @@ def main():
         served = served_case(torch, pm, synth)
 
     achieved = head["alg_bytes_per_launch"] / (head["kernel_us"] * 1e-6) / 1e9
+    kname, ksrc = kernel_name(head["variant"])
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": measured_traffic(),
-            "kernel": "pm_apply_kernel", "alg_bytes_per_launch": head["alg_bytes_per_launch"]}
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": measured_traffic(kname, ksrc),
+            "kernel": kname, "alg_bytes_per_launch": head["alg_bytes_per_launch"]}
     line = {
         "metric": "encode GB/s (source bytes) PM-MSR k=8 d=14 at 1 GPU; batched vs plain; serve p50/p99",
         "value": round(head["gbps"], 2),

@@ -163,11 +163,11 @@ pm_status pm_apply(const uint8_t *A, uint32_t rows, uint32_t cols, const uint8_t
  * view); blocks shorter than 2048 bytes and matrices whose network exceeds
  * the size limit run the table kernel with 4 dwords per lane instead.  A
  * hipRTC failure is reported as PM_EHIP.  0, 0 restores the default: the
- * table kernel (cost-model rows per group, 2 dwords per lane) until the
- * bit-sliced kernel of the operation's matrix has been compiled on the
- * library's background compile thread (started by the first call, or by
- * pm_prepare), the bit-sliced kernel from then on.  Both give the same
- * bytes.  PM_EINVAL for other values. */
+ * bit-sliced kernel when the operation's matrix has one compiled (by
+ * pm_prepare, pm_autotune_encode or a call under variant 32) and the block
+ * is at least 2048 bytes, else the table kernel with the cost-model rows
+ * per group and 2 dwords per lane.  The default never compiles by itself.
+ * Every variant gives the same bytes.  PM_EINVAL for other values. */
 pm_status pm_set_variant(pm_code *code, int op, uint32_t rows_per_group,
                          uint32_t dwords_per_lane);
 
@@ -175,14 +175,13 @@ pm_status pm_set_variant(pm_code *code, int op, uint32_t rows_per_group,
  * paper's evaluation separates them (Section 4): builds the operation's
  * matrix (op 0 encode, 1 repair helper, 2 repair newcomer, 3 decode; failed
  * and ids as for those calls, ids on the host) and, under the default or the
- * bit-sliced variant, its bit-sliced kernel -- compiled now when wait != 0
- * (seconds; hipRTC, no GPU needed), else queued on the background compile
- * thread.  *specialized (may be NULL) = 1 when the bit-sliced kernel is
- * ready for this operation, 0 when the table kernel will run (matrix over
- * the size limit, explicit table variant, or compile still queued).
- * PM_EINVAL for bad ids, PM_EHIP if hipRTC fails. */
-pm_status pm_prepare(pm_code *code, int op, uint32_t failed, const uint32_t *ids, int wait,
-                     int *specialized);
+ * bit-sliced variant, generates its bit-sliced kernel and compiles it with
+ * hipRTC (seconds; no GPU needed; a no-op when already compiled).
+ * *specialized (may be NULL) = 1 when the bit-sliced kernel is ready for
+ * this operation, 0 when the table kernel will run (matrix over the size
+ * limit, or an explicit table variant).  PM_EINVAL for bad ids, PM_EHIP if
+ * hipRTC fails. */
+pm_status pm_prepare(pm_code *code, int op, uint32_t failed, const uint32_t *ids, int *specialized);
 
 /* Autotuner for encode: times every kernel variant on the caller's buffers
  * (X, out as for pm_encode; reps launches each, HIP events on `stream`),

@@ -30,9 +30,6 @@
 #include <hip/hiprtc.h>
 
 #include <algorithm>
-#include <condition_variable>
-#include <deque>
-#include <thread>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -332,60 +329,6 @@ static int bs_compile_locked(BsProgram &bp) {
     hiprtcGetCode(prog, bp.code.data());
     hiprtcDestroyProgram(&prog);
     return ST_OK;
-}
-
-// One compile thread per process.  Its queue holds references, so programs
-// dropped by their owners meanwhile stay alive until compiled.  At exit the
-// thread is stopped and joined (an in-flight hipRTC run is waited for); it
-// makes no HIP runtime calls, only hipRTC ones.
-namespace {
-class Compiler {
-    std::mutex mu_;
-    std::condition_variable cv_;
-    std::deque<std::shared_ptr<BsProgram>> q_;
-    bool stop_ = false;
-    std::thread th_;
-
-    void run() {
-        for (;;) {
-            std::shared_ptr<BsProgram> p;
-            {
-                std::unique_lock<std::mutex> lk(mu_);
-                cv_.wait(lk, [&] { return stop_ || !q_.empty(); });
-                if (stop_) return;
-                p = std::move(q_.front());
-                q_.pop_front();
-            }
-            (void)bs_compile(*p);
-        }
-    }
-
-  public:
-    void submit(const std::shared_ptr<BsProgram> &p) {
-        std::lock_guard<std::mutex> lk(mu_);
-        if (stop_) return;
-        if (!th_.joinable()) th_ = std::thread(&Compiler::run, this);
-        q_.push_back(p);
-        cv_.notify_one();
-    }
-    ~Compiler() {
-        {
-            std::lock_guard<std::mutex> lk(mu_);
-            stop_ = true;
-            // programs still queued are left allocated: dropping a last
-            // reference here would unload modules from a static destructor
-            if (!q_.empty()) new std::deque<std::shared_ptr<BsProgram>>(std::move(q_));
-        }
-        cv_.notify_all();
-        if (th_.joinable()) th_.join();
-    }
-};
-Compiler g_compiler;
-}  // namespace
-
-void bs_compile_async(const std::shared_ptr<BsProgram> &bp) {
-    int expect = BS_NONE;
-    if (bp && bp->state.compare_exchange_strong(expect, BS_QUEUED)) g_compiler.submit(bp);
 }
 
 BsProgram::~BsProgram() {

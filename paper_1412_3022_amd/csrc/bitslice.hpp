@@ -20,7 +20,7 @@ struct BsModule {
 };
 
 // Compile state of a BsProgram, readable without its mutex.
-enum BsState { BS_NONE = 0, BS_QUEUED = 1, BS_READY = 2, BS_FAILED = 3 };
+enum BsState { BS_NONE = 0, BS_READY = 2, BS_FAILED = 3 };
 
 struct BsProgram {
     std::string source;
@@ -42,12 +42,9 @@ constexpr uint64_t kBsTileBytes = 2048;   // bytes per wave tile
 
 // Generate the source for a program built with 8 rows per group.
 std::unique_ptr<BsProgram> bs_generate(const Program &p8);
-// Compile now (blocks for the hipRTC run; a no-op once compiled).
+// Compile now (blocks for the hipRTC run; a no-op once compiled).  Nothing
+// compiles in the background: no compile can be in flight at process exit.
 int bs_compile(BsProgram &bp);
-// Queue the compile on the library's compile thread unless it is queued or
-// done already; the caller keeps using the table kernel until state is
-// BS_READY.  The thread holds a reference, so the owner may drop its own.
-void bs_compile_async(const std::shared_ptr<BsProgram> &bp);
 // Run the kernel over bytes [0, s) of every block, s >= kBsTileBytes (else
 // ST_EINVAL).  Bases 16-byte aligned, ld multiples of 16 (as checked by the
 // entry points).

@@ -110,6 +110,12 @@ std::shared_ptr<BsProgram> ProgEntry::bitslice() {
     return bs;
 }
 
+std::shared_ptr<BsProgram> ProgEntry::bitslice_if_compiled() {
+    std::lock_guard<std::mutex> lk(mu);
+    if (bs && bs->state.load(std::memory_order_acquire) == BS_READY) return bs;
+    return nullptr;
+}
+
 // ---- variant choice ----------------------------------------------------------
 // VALU cost per lane dword of a program: each evaluated slot costs three
 // byte-permutes and 1.5 three-input XORs plus its share of table moves; each
@@ -163,11 +169,8 @@ int launch_program(ProgEntry &pe, int vec, const uint8_t *in, size_t in_ld, size
         vec = 4;
     } else if (vec == kVecAuto) {
         if (s >= kBsTileBytes)
-            if (std::shared_ptr<BsProgram> bp = pe.bitslice()) {
-                if (bp->state.load(std::memory_order_acquire) == BS_READY)
-                    return bs_launch(*bp, in, in_ld, out, out_ld, s, stream);
-                bs_compile_async(bp);
-            }
+            if (std::shared_ptr<BsProgram> bp = pe.bitslice_if_compiled())
+                return bs_launch(*bp, in, in_ld, out, out_ld, s, stream);
         vec = kVecTable;
     }
     const uint32_t *dprog = nullptr;
@@ -445,7 +448,7 @@ pm_status pm_set_variant(pm_code *c, int op, uint32_t rg, uint32_t vec) {
     return PM_OK;
 }
 
-pm_status pm_prepare(pm_code *c, int op, uint32_t failed, const uint32_t *ids, int wait, int *specialized) {
+pm_status pm_prepare(pm_code *c, int op, uint32_t failed, const uint32_t *ids, int *specialized) {
     if (specialized) *specialized = 0;
     if (!c || op < 0 || op > 3) return PM_EINVAL;
     Resolved r;
@@ -454,12 +457,8 @@ pm_status pm_prepare(pm_code *c, int op, uint32_t failed, const uint32_t *ids, i
     if (r.vec != kVecAuto && r.vec != kVecBitslice) return PM_OK;   // an explicit table variant
     std::shared_ptr<BsProgram> bp = r.pe->bitslice();
     if (!bp) return PM_OK;
-    if (wait) {
-        if ((st = bs_compile(*bp)) != ST_OK) return static_cast<pm_status>(st);
-    } else {
-        bs_compile_async(bp);
-    }
-    if (specialized) *specialized = bp->state.load(std::memory_order_acquire) == BS_READY;
+    if ((st = bs_compile(*bp)) != ST_OK) return static_cast<pm_status>(st);
+    if (specialized) *specialized = 1;
     return PM_OK;
 }
 

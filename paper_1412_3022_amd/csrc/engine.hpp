@@ -53,15 +53,19 @@ struct ProgEntry {
     // The bit-sliced specialization, generated (not compiled) on first use;
     // nullptr when the matrix is too large to specialize.
     std::shared_ptr<BsProgram> bitslice();
+    // The specialization if it has been generated and compiled, else nullptr
+    // (never generates or compiles).
+    std::shared_ptr<BsProgram> bitslice_if_compiled();
     int device_ptr(hipStream_t user, const uint32_t **out);
     // Same, but returns only once the copy has landed (for plans and graphs).
     int device_ptr_sync(const uint32_t **out);
 };
 
 constexpr int kVecBitslice = 32;   // variant code of the bit-sliced specialization
-// Default variant: the bit-sliced kernel once its background compile is done
-// (blocks of at least one tile), the table kernel with kVecTable dwords per
-// lane until then.
+// Default variant: the bit-sliced kernel when the matrix's kernel has been
+// compiled (by pm_prepare, the autotuner or an explicit bit-sliced call) and
+// the block is at least one tile long, else the table kernel with kVecTable
+// dwords per lane.
 constexpr int kVecAuto = 0;
 constexpr int kVecTable = 2;
 

@@ -72,7 +72,7 @@ def _lib():
         L.pm_apply.argtypes = [vp, u32, u32, vp, sz, vp, sz, sz, vp]
         L.pm_set_variant.argtypes = [vp, i32, u32, u32]
         L.pm_autotune_encode.argtypes = [vp, vp, sz, vp, sz, sz, u32, vp, u32p, u32p]
-        L.pm_prepare.argtypes = [vp, i32, u32, u32p, i32, ctypes.POINTER(ctypes.c_int)]
+        L.pm_prepare.argtypes = [vp, i32, u32, u32p, ctypes.POINTER(ctypes.c_int)]
         L.pm_batch_plan.argtypes = [ctypes.POINTER(pm_batch_item), sz, u32, ctypes.POINTER(vp)]
         L.pm_batch_set_variant.argtypes = [vp, u32, u32]
         L.pm_batch_autotune.argtypes = [vp, u32, vp, u32p]
@@ -156,11 +156,10 @@ def pm_set_variant(h, op, rows_per_group, dwords_per_lane):
     return _lib().pm_set_variant(h, op, rows_per_group, dwords_per_lane)
 
 
-def pm_prepare(h, op, failed=0, ids=None, wait=True):
+def pm_prepare(h, op, failed=0, ids=None):
     """Init phase of one operation; returns (status, specialized)."""
     spec = ctypes.c_int()
-    st = _lib().pm_prepare(h, op, failed, _u32arr(ids) if ids is not None else None, 1 if wait else 0,
-                           ctypes.byref(spec))
+    st = _lib().pm_prepare(h, op, failed, _u32arr(ids) if ids is not None else None, ctypes.byref(spec))
     return st, spec.value
 
 
@@ -228,10 +227,10 @@ class Code:
     def set_variant(self, op, rows_per_group, dwords_per_lane):
         _check(pm_set_variant(self.h, op, rows_per_group, dwords_per_lane), "pm_set_variant")
 
-    def prepare(self, op, failed=0, ids=None, wait=True):
-        """Build the operation's matrix and its bit-sliced kernel (compiled now
-        if wait, else in the background); True when that kernel is ready."""
-        st, spec = pm_prepare(self.h, op, failed, ids, wait)
+    def prepare(self, op, failed=0, ids=None):
+        """Build the operation's matrix and compile its bit-sliced kernel;
+        True when that kernel is ready (False: the table kernel runs)."""
+        st, spec = pm_prepare(self.h, op, failed, ids)
         _check(st, "pm_prepare")
         return bool(spec)
 

@@ -126,17 +126,21 @@ def test_prepare_compiles_bitsliced_kernels_without_gpu():
     assert c.prepare(pm.OP_DECODE, ids=[1, 4, 6, 7]) is True
 
 
-def test_prepare_background_compile_becomes_ready():
-    import time
+def test_default_variant_never_compiles_by_itself():
+    """A data call under the default variant must not start a compile: with
+    no GPU it fails with PM_EHIP after building the program, and the
+    operation still reports no specialized kernel until pm_prepare."""
     c = pm.Code(k=3, d=4, n=6)
-    st, spec = pm.pm_prepare(c.h, pm.OP_DECODE, 0, [0, 2, 5], wait=False)
-    assert st == pm.PM_OK
-    t0 = time.time()
-    while not spec and time.time() - t0 < 120:
-        time.sleep(0.05)
-        st, spec = pm.pm_prepare(c.h, pm.OP_DECODE, 0, [0, 2, 5], wait=False)
-        assert st == pm.PM_OK
-    assert spec == 1
+    s = 4096
+    st = pm.pm_decode(c.h, [0, 2, 5], 1 << 20, s, (1 << 20) + 64 * s, s, s, None)
+    assert st == pm.PM_EHIP
+    L = pm.lib()
+    spec = ctypes.c_int(-1)
+    ids = (ctypes.c_uint32 * 3)(0, 2, 5)
+    c.set_variant(pm.OP_DECODE, 4, 2)           # explicit table variant: prepare compiles nothing
+    assert L.pm_prepare(c.h, pm.OP_DECODE, 0, ids, ctypes.byref(spec)) == pm.PM_OK and spec.value == 0
+    c.set_variant(pm.OP_DECODE, 0, 0)
+    assert L.pm_prepare(c.h, pm.OP_DECODE, 0, ids, ctypes.byref(spec)) == pm.PM_OK and spec.value == 1
 
 
 def test_prepare_reports_table_kernel_cases():
@@ -156,5 +160,5 @@ def test_prepare_reports_table_kernel_cases():
 ])
 def test_prepare_argument_errors(op, failed, ids):
     c = pm.Code(k=4, d=6, n=8)
-    st, spec = pm.pm_prepare(c.h, op, failed, ids, wait=True)
+    st, spec = pm.pm_prepare(c.h, op, failed, ids)
     assert st == pm.PM_EINVAL and spec == 0
