@@ -176,12 +176,15 @@ pm_status pm_set_variant(pm_code *code, int op, uint32_t rows_per_group,
  * matrix (op 0 encode, 1 repair helper, 2 repair newcomer, 3 decode; failed
  * and ids as for those calls, ids on the host) and, under the default or the
  * bit-sliced variant, generates its bit-sliced kernel and compiles it with
- * hipRTC (seconds; no GPU needed; a no-op when already compiled).
- * *specialized (may be NULL) = 1 when the bit-sliced kernel is ready for
- * this operation, 0 when the table kernel will run (matrix over the size
- * limit, or an explicit table variant).  PM_EINVAL for bad ids, PM_EHIP if
- * hipRTC fails. */
-pm_status pm_prepare(pm_code *code, int op, uint32_t failed, const uint32_t *ids, int *specialized);
+ * hipRTC (seconds; no GPU needed; a no-op when already compiled).  With
+ * PM_PREPARE_BATCHED in flags it also compiles the kernel's multi-set form,
+ * which batches and the server use for this operation.  *specialized (may
+ * be NULL) = 1 when the bit-sliced kernel is ready for this operation, 0
+ * when the table kernel will run (matrix over the size limit, or an explicit
+ * table variant).  PM_EINVAL for bad ids or flags, PM_EHIP if hipRTC fails. */
+#define PM_PREPARE_BATCHED 1u
+pm_status pm_prepare(pm_code *code, int op, uint32_t failed, const uint32_t *ids, uint32_t flags,
+                     int *specialized);
 
 /* Autotuner for encode: times every kernel variant on the caller's buffers
  * (X, out as for pm_encode; reps launches each, HIP events on `stream`),
@@ -195,8 +198,11 @@ pm_status pm_autotune_encode(pm_code *code, const uint8_t *X, size_t x_ld, uint8
  * Many independent operations -- objects of different sizes and codes,
  * encode, repair and decode mixed -- run as one persistent work-list launch
  * per row-group size, with the waves of the whole GPU pulling (item, row
- * group, byte tile) units from per-XCD queues.  The plan fixes every pointer
- * and size; a run only enqueues. */
+ * group, byte tile) units from per-XCD queues.  Items of at least 2048 bytes
+ * whose matrix has a compiled multi-set bit-sliced kernel (pm_prepare with
+ * PM_PREPARE_BATCHED, or PM_BATCH_SPECIALIZE below) run instead as one
+ * launch of that kernel per matrix.  The plan fixes every pointer and size;
+ * a run only enqueues. */
 typedef struct {
     const pm_code *code;
     int32_t op;            /* 0 encode, 1 repair helper, 2 repair newcomer, 3 decode */
@@ -214,6 +220,10 @@ typedef struct pm_batch pm_batch;
 
 #define PM_BATCH_GRAPH 1u  /* capture the launches in a HIP graph on the first
                               run and replay it afterwards */
+#define PM_BATCH_SPECIALIZE 2u  /* compile, during the plan, the multi-set
+                                   bit-sliced kernel of every matrix that has
+                                   an item of >= 2048 bytes (seconds per new
+                                   matrix, about 30 s for the k = 16 encode) */
 
 /* Resolve every item (building repair / decode matrices as needed), check
  * its regions as the single calls do, and upload the work lists.  Blocks
@@ -234,7 +244,8 @@ pm_status pm_batch_autotune(pm_batch *batch, uint32_t reps, pm_stream stream,
  * so they must be ordered (one stream, or events between streams). */
 pm_status pm_batch_run(pm_batch *batch, pm_stream stream);
 
-/* Work units (item x row group x wave tile) and size classes of a plan. */
+/* Work units (item x row group x wave tile) and launches of a plan (table
+ * size classes plus bit-sliced matrices). */
 pm_status pm_batch_info(const pm_batch *batch, uint64_t *units, uint32_t *size_classes);
 
 /* Free a plan; no run of it may still be in flight. */
@@ -247,7 +258,11 @@ void pm_batch_destroy(pm_batch *batch);
  * then runs inside a micro-batch on one of `streams` streams.  Requests that
  * arrive while earlier micro-batches run are admitted into the next free
  * stream, so their work overlaps on the GPU.  A result stays in the arena
- * until pm_server_release. */
+ * until pm_server_release.  Operations of at least 2048 bytes whose matrix
+ * has a compiled multi-set bit-sliced kernel (pm_prepare with
+ * PM_PREPARE_BATCHED, before submitting) run on it, one launch per matrix
+ * per micro-batch phase; the rest on the table work lists.  The server never
+ * compiles by itself. */
 typedef enum { PM_REQ_ENCODE = 0, PM_REQ_REPAIR = 1, PM_REQ_DECODE = 2 } pm_request_op;
 
 typedef struct {

@@ -54,10 +54,20 @@ struct SizeClass {
     uint32_t nitems = 0, nunits = 0;
 };
 
+// Items whose matrix has a compiled multi-set bit-sliced kernel: one launch
+// of that kernel over all of them.
+struct BsClass {
+    std::shared_ptr<BsProgram> bp;
+    std::vector<BsItem> items;
+    BsItem *d_items = nullptr;
+    uint32_t ntiles = 0;
+};
+
 }  // namespace
 
 struct pm_batch {
     std::vector<SizeClass> classes;
+    std::vector<BsClass> bs_classes;
     uint32_t *d_counters = nullptr;   // 8 queue heads per class, 64 B apart
     uint32_t flags = 0;
     hipGraph_t graph = nullptr;
@@ -66,6 +76,8 @@ struct pm_batch {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         for (auto &c : classes)
+            if (c.d_items) (void)hipFree(c.d_items);
+        for (auto &c : bs_classes)
             if (c.d_items) (void)hipFree(c.d_items);
         if (d_counters) (void)hipFree(d_counters);
     }
@@ -114,7 +126,31 @@ int build_class(SizeClass &c, int vec) {
     return ST_OK;
 }
 
+// Number the tiles of a bit-sliced class back to back and upload it.
+int build_bs_class(BsClass &c) {
+    uint64_t tile = 0;
+    for (BsItem &it : c.items) {
+        it.tile0 = static_cast<uint32_t>(tile);
+        tile += it.ntiles;
+        if (tile > 0xffffff00ull) return ST_EINVAL;
+    }
+    c.ntiles = static_cast<uint32_t>(tile);
+    const size_t bytes = c.items.size() * sizeof(BsItem);
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&c.d_items), bytes);
+    if (e != hipSuccess) {
+        c.d_items = nullptr;
+        return hip_fail(e);
+    }
+    if ((e = hipMemcpy(c.d_items, c.items.data(), bytes, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(e);
+    // compile (if needed) and load the module now, not inside a graph capture
+    return bs_load(*c.bp, BS_MULTI);
+}
+
 int launch_all(pm_batch *b, hipStream_t st) {
+    for (BsClass &c : b->bs_classes) {
+        int rc = bs_launch_items(*c.bp, c.d_items, static_cast<uint32_t>(c.items.size()), c.ntiles, st);
+        if (rc != ST_OK) return rc;
+    }
     for (size_t i = 0; i < b->classes.size(); ++i) {
         SizeClass &c = b->classes[i];
         if (!c.nunits) continue;
@@ -143,6 +179,7 @@ pm_status pm_batch_plan(const pm_batch_item *items, size_t n, uint32_t flags, pm
     std::unique_ptr<pm_batch> b(new pm_batch());
     b->flags = flags;
     std::map<int, size_t> by_rg;
+    std::map<BsProgram *, size_t> by_bs;
     for (size_t i = 0; i < n; ++i) {
         const pm_batch_item &it = items[i];
         if (!it.code || it.block_bytes == 0 || it.op < 0 || it.op > 3) return PM_EINVAL;
@@ -155,6 +192,26 @@ pm_status pm_batch_plan(const pm_batch_item *items, size_t n, uint32_t flags, pm
             return static_cast<pm_status>(st);
         if (overlap(it.in, it.in_ld, r.in_n, it.out, out_ld, r.out_n, it.block_bytes)) return PM_EINVAL;
         if (r.pe->prog.ngroups == 0) continue;
+        if (it.block_bytes >= kBsTileBytes && (r.vec == kVecAuto || r.vec == kVecBitslice)) {
+            std::shared_ptr<BsProgram> bp;
+            if (flags & PM_BATCH_SPECIALIZE) {
+                if ((bp = r.pe->bitslice()) && (st = bs_compile(*bp, BS_MULTI)) != ST_OK)
+                    return static_cast<pm_status>(st);
+            } else {
+                bp = r.pe->bitslice_if_compiled(BS_MULTI);
+            }
+            if (bp) {
+                auto cls = by_bs.find(bp.get());
+                if (cls == by_bs.end()) {
+                    cls = by_bs.emplace(bp.get(), b->bs_classes.size()).first;
+                    b->bs_classes.emplace_back();
+                    b->bs_classes.back().bp = bp;
+                }
+                b->bs_classes[cls->second].items.push_back(
+                    bs_item(it.in, it.in_ld, it.out, out_ld, it.block_bytes, 0));
+                continue;
+            }
+        }
         const uint32_t *dprog = nullptr;
         if ((st = r.pe->device_ptr_sync(&dprog)) != ST_OK) return static_cast<pm_status>(st);
         auto cls = by_rg.find(r.pe->prog.rg);
@@ -168,6 +225,10 @@ pm_status pm_batch_plan(const pm_batch_item *items, size_t n, uint32_t flags, pm
     }
     for (SizeClass &c : b->classes) {
         int st = build_class(c, 2);
+        if (st != ST_OK) return static_cast<pm_status>(st);
+    }
+    for (BsClass &c : b->bs_classes) {
+        int st = build_bs_class(c);
         if (st != ST_OK) return static_cast<pm_status>(st);
     }
     const size_t cbytes = std::max<size_t>(1, b->classes.size()) * 8 * 16 * sizeof(uint32_t);
@@ -272,8 +333,9 @@ pm_status pm_batch_info(const pm_batch *b, uint64_t *units, uint32_t *size_class
     if (!b) return PM_EINVAL;
     uint64_t u = 0;
     for (const SizeClass &c : b->classes) u += c.nunits;
+    for (const BsClass &c : b->bs_classes) u += static_cast<uint64_t>(c.ntiles) * c.bp->ngroups;
     if (units) *units = u;
-    if (size_classes) *size_classes = static_cast<uint32_t>(b->classes.size());
+    if (size_classes) *size_classes = static_cast<uint32_t>(b->classes.size() + b->bs_classes.size());
     return PM_OK;
 }
 

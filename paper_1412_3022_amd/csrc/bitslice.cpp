@@ -49,6 +49,12 @@ namespace {
 
 constexpr int kGroupWords = 8;
 constexpr size_t kPrefetch = 2;   // columns loaded ahead of the one being multiplied
+// First statement of every group function: an empty asm that makes the two
+// strides opaque for each call.  Without it the compiler hoists every
+// group's column bases (in + column * ld) out of the tile loop, and the
+// hundreds of 64-bit scalars that produces spill into VGPR lanes (k = 16
+// encode: 903 SGPR spills and 176 VGPRs, against none and 151 with it).
+const char *kOpaqueStrides = "  asm volatile(\"\" : \"+s\"(ld), \"+s\"(old));\n";
 constexpr int kWaves = 4;         // waves per work-group
 constexpr int kHeaderWords = 4;
 
@@ -64,7 +70,28 @@ __device__ __forceinline__ void ST(unsigned char *d, u32x4 v) { __builtin_nontem
   DS(A0, A4, 4, 0x0F0F0F0Fu) DS(A1, A5, 4, 0x0F0F0F0Fu) DS(A2, A6, 4, 0x0F0F0F0Fu) DS(A3, A7, 4, 0x0F0F0F0Fu) \
   DS(A0, A2, 2, 0x33333333u) DS(A1, A3, 2, 0x33333333u) DS(A4, A6, 2, 0x33333333u) DS(A5, A7, 2, 0x33333333u) \
   DS(A0, A1, 1, 0x55555555u) DS(A2, A3, 1, 0x55555555u) DS(A4, A5, 1, 0x55555555u) DS(A6, A7, 1, 0x55555555u) }
+// One region set: tile0 = its first tile in the launch's tile numbering.
+struct BsItem { const unsigned char *in; u64 ld; unsigned char *out; u64 old; u64 s; u32 nfull, ntiles, tile0, pad; };
+// Arguments of the single-set kernel.
 struct BsArgs { const unsigned char *in; u64 ld; unsigned char *out; u64 old; u64 s; u32 nfull, ntiles, P; };
+// Arguments of the multi-set kernel: `items` in device memory, sorted by tile0.
+struct BsMultiArgs { const BsItem *items; u32 nitems, ntiles, P, pad; };
+// A wave-uniform 64-bit value, made a scalar for the compiler.  The builtin
+// returns int: each half goes through u32 so the low half is not
+// sign-extended into the high one.
+__device__ __forceinline__ u64 rfl64(u64 x) {
+  const u32 hi = (u32)__builtin_amdgcn_readfirstlane((u32)(x >> 32));
+  const u32 lo = (u32)__builtin_amdgcn_readfirstlane((u32)x);
+  return ((u64)hi << 32) | (u64)lo;
+}
+// Index of the item that holds tile t, searched in [lo, hi).
+__device__ __forceinline__ u32 find_item(const BsItem *items, u32 lo, u32 hi, u32 t) {
+  while (hi - lo > 1u) {
+    const u32 mid = (lo + hi) / 2u;
+    if (items[mid].tile0 <= t) lo = mid; else hi = mid;
+  }
+  return lo;
+}
 // Product in GF(2^8) by shift and add (used only for the last s mod 16 bytes).
 __device__ __forceinline__ u32 gm(u32 c, u32 x) {
   u32 p = 0u;
@@ -112,7 +139,7 @@ int popc(unsigned m) { return __builtin_popcount(m); }
 void emit_table_group(std::ostringstream &o, int gi, const Grp &G) {
     const int n = static_cast<int>(G.rows.size());
     o << "__device__ __forceinline__ void g" << gi
-      << "(const unsigned char *in, u64 ld, unsigned char *out, u64 old, u64 off) {\n";
+      << "(const unsigned char *in, u64 ld, unsigned char *out, u64 old, u64 off) {\n" << kOpaqueStrides;
     for (int r = 0; r < n; ++r) {
         o << "  u32";
         for (int i = 0; i < 8; ++i) o << (i ? "," : "") << " q" << r << "_" << i << " = 0u";
@@ -200,7 +227,7 @@ void emit_table_group(std::ostringstream &o, int gi, const Grp &G) {
 
 void emit_copy_group(std::ostringstream &o, int gi, const Grp &G) {
     o << "__device__ __forceinline__ void g" << gi
-      << "(const unsigned char *in, u64 ld, unsigned char *out, u64 old, u64 off) {\n";
+      << "(const unsigned char *in, u64 ld, unsigned char *out, u64 old, u64 off) {\n" << kOpaqueStrides;
     for (size_t i = 0; i < G.rows.size(); ++i)
         o << "  { const unsigned char *p = in + (u64)" << G.cols[i] << "u * ld + off;\n"
           << "    unsigned char *d = out + (u64)" << G.rows[i] << "u * old + off;\n"
@@ -261,56 +288,118 @@ std::unique_ptr<BsProgram> bs_generate(const Program &p8) {
         emit_byte_tail(o, static_cast<int>(g), gs[g]);
     }
     const int G = bp->ngroups;
-    // Tiles 0 .. nfull-1 are the full 2048-byte tiles; when s16 (s rounded
-    // down to 16) is not a multiple of 2048, tile nfull is the window
-    // [s16 - 2048, s16), which overlaps tile nfull-1 and stores the same bytes
-    // it does.  The s - s16 bytes after s16 are done byte by byte by the
-    // lanes of the wave that takes the last tile.
-    o << "extern \"C\" __global__ __launch_bounds__(" << 64 * kWaves << ") void pmbs(BsArgs a) {\n"
-      << "  const u32 wave = threadIdx.x / 64, lane = threadIdx.x % 64;\n"
-      << "  const u32 xcd = blockIdx.x % 8u, slot = blockIdx.x / 8u;\n"
-      << "  const u32 per = (a.ntiles + 7u) / 8u, t0 = xcd * per;\n"
-      << "  const u32 t1 = t0 + per < a.ntiles ? t0 + per : a.ntiles;\n"
-      << "  const u64 s16 = a.s & ~15ull;\n"
-      << "  const u32 G = " << G << "u;\n"
-      << "  // slots of one group stride over this XCD's tiles; with fewer slots\n"
-      << "  // than groups a slot takes groups slot, slot + P, ...\n"
-      << "  for (u32 g = slot % G; g < G; g += a.P) {\n"
-      << "    const u32 R = a.P >= G ? (a.P - 1u - g) / G + 1u : 1u;\n"
-      << "    const u32 r = a.P >= G ? slot / G : 0u;\n"
-      << "    for (u32 t = t0 + r * " << kWaves << "u + wave; t < t1; t += R * " << kWaves << "u) {\n"
-      << "      const u64 tile = t < a.nfull ? (u64)t * 2048u : s16 - 2048u;\n"
-      << "      switch (g) {\n";
-    for (int g = 0; g < G; ++g) o << "        case " << g << ": g" << g << "(a.in, a.ld, a.out, a.old, tile + lane * 16u); break;\n";
-    o << "      }\n"
-      << "      if (t == a.ntiles - 1u && s16 + lane < a.s) {\n"
-      << "        switch (g) {\n";
-    for (int g = 0; g < G; ++g) o << "          case " << g << ": b" << g << "(a.in, a.ld, a.out, a.old, s16 + lane); break;\n";
-    o << "        }\n      }\n    }\n    if (a.P >= G) break;\n  }\n}\n";
-    bp->source = o.str();
-    if (const char *dump = getenv("PMRC_BS_DUMP")) {   // debugging aid: keep the generated source
-        if (FILE *f = fopen(dump, "w")) {
-            fputs(bp->source.c_str(), f);
-            fclose(f);
+    const std::string body = o.str();
+    // Tiles 0 .. nfull-1 of a region set are the full 2048-byte tiles; when
+    // s16 (s rounded down to 16) is not a multiple of 2048, tile nfull is the
+    // window [s16 - 2048, s16), which overlaps tile nfull-1 and stores the
+    // same bytes it does.  The s - s16 bytes after s16 are done byte by byte
+    // by the lanes of the wave that takes the last tile.
+    auto group_calls = [&](std::ostringstream &k, const char *pre, const char *ind) {
+        k << ind << "switch (g) {\n";
+        for (int g = 0; g < G; ++g)
+            k << ind << "  case " << g << ": g" << g << "(" << pre << "in, " << pre << "ld, " << pre << "out, " << pre
+              << "old, tile + lane * 16u); break;\n";
+        k << ind << "}\n" << ind << "if (lt == " << pre << "ntiles - 1u && s16 + lane < " << pre << "s) {\n"
+          << ind << "  switch (g) {\n";
+        for (int g = 0; g < G; ++g)
+            k << ind << "    case " << g << ": b" << g << "(" << pre << "in, " << pre << "ld, " << pre << "out, " << pre
+              << "old, s16 + lane); break;\n";
+        k << ind << "  }\n" << ind << "}\n";
+    };
+    auto head = [&](std::ostringstream &k, const char *name, const char *args) {
+        k << "extern \"C\" __global__ __launch_bounds__(" << 64 * kWaves << ") void " << name << "(" << args
+          << " a) {\n"
+          << "  const u32 wave = threadIdx.x / 64, lane = threadIdx.x % 64;\n"
+          << "  const u32 xcd = blockIdx.x % 8u, slot = blockIdx.x / 8u;\n"
+          << "  const u32 per = (a.ntiles + 7u) / 8u, t0 = xcd * per;\n"
+          << "  const u32 t1 = t0 + per < a.ntiles ? t0 + per : a.ntiles;\n"
+          << "  const u32 G = " << G << "u;\n"
+          << "  // slots of one group stride over this XCD's tiles; with fewer slots\n"
+          << "  // than groups a slot takes groups slot, slot + P, ...\n"
+          << "  for (u32 g = slot % G; g < G; g += a.P) {\n"
+          << "    const u32 R = a.P >= G ? (a.P - 1u - g) / G + 1u : 1u;\n"
+          << "    const u32 r = a.P >= G ? slot / G : 0u;\n";
+    };
+    {
+        std::ostringstream k;
+        head(k, "pmbs", "BsArgs");
+        k << "    const u64 s16 = a.s & ~15ull;\n"
+          << "    for (u32 t = t0 + r * " << kWaves << "u + wave; t < t1; t += R * " << kWaves << "u) {\n"
+          << "      const u32 lt = t;\n"
+          << "      const u64 tile = t < a.nfull ? (u64)t * 2048u : s16 - 2048u;\n";
+        group_calls(k, "a.", "      ");
+        k << "    }\n    if (a.P >= G) break;\n  }\n}\n";
+        bp->k[BS_SINGLE].source = body + k.str();
+    }
+    {
+        // The tiles of all sets are numbered back to back; a wave walks its
+        // tiles in rising order and finds each one's set by a search bounded
+        // by its stride (every set has at least one tile).
+        std::ostringstream k;
+        head(k, "pmbs_multi", "BsMultiArgs");
+        k << "    const u32 step = R * " << kWaves << "u;\n"
+          << "    u32 it = 0u, prev = 0u;\n"
+          << "    bool first = true;\n"
+          << "    for (u32 t = t0 + r * " << kWaves << "u + wave; t < t1; t += step) {\n"
+          << "      const u32 lim = first ? a.nitems : (it + (t - prev) + 1u < a.nitems ? it + (t - prev) + 1u : a.nitems);\n"
+          << "      it = find_item(a.items, first ? 0u : it, lim, t);\n"
+          << "      first = false;\n"
+          << "      prev = t;\n"
+          << "      BsItem I = a.items[it];\n"
+          << "      // the set is the same for the whole wave\n"
+          << "      I.in = (const unsigned char *)rfl64((u64)I.in);\n"
+          << "      I.out = (unsigned char *)rfl64((u64)I.out);\n"
+          << "      I.ld = rfl64(I.ld);\n"
+          << "      I.old = rfl64(I.old);\n"
+          << "      I.s = rfl64(I.s);\n"
+          << "      const u32 lt = t - I.tile0;\n"
+          << "      const u64 s16 = I.s & ~15ull;\n"
+          << "      const u64 tile = lt < I.nfull ? (u64)lt * 2048u : s16 - 2048u;\n";
+        group_calls(k, "I.", "      ");
+        k << "    }\n    if (a.P >= G) break;\n  }\n}\n";
+        bp->k[BS_MULTI].source = body + k.str();
+    }
+    if (const char *dump = getenv("PMRC_BS_DUMP")) {   // debugging aid: keep the generated sources
+        for (int kind = 0; kind < 2; ++kind) {
+            const std::string path = std::string(dump) + (kind == BS_MULTI ? ".multi" : "");
+            if (FILE *f = fopen(path.c_str(), "w")) {
+                fputs(bp->k[kind].source.c_str(), f);
+                fclose(f);
+            }
         }
     }
     return bp;
 }
 
-static int bs_compile_locked(BsProgram &bp);
+static int bs_compile_locked(BsKernel &bk);
 
-int bs_compile(BsProgram &bp) {
+int bs_compile(BsProgram &bp, BsKind kind) {
     std::lock_guard<std::mutex> lk(bp.mu);
-    if (bp.compiled) return bp.compile_status;
-    bp.compiled = true;
-    bp.compile_status = bs_compile_locked(bp);
-    bp.state.store(bp.compile_status == ST_OK ? BS_READY : BS_FAILED, std::memory_order_release);
-    return bp.compile_status;
+    BsKernel &bk = bp.k[kind];
+    if (bk.compiled) return bk.compile_status;
+    bk.compiled = true;
+    bk.compile_status = bs_compile_locked(bk);
+    bk.state.store(bk.compile_status == ST_OK ? BS_READY : BS_FAILED, std::memory_order_release);
+    return bk.compile_status;
 }
 
-static int bs_compile_locked(BsProgram &bp) {
+// Code objects by generated source, for the life of the process: the same
+// matrix met again (another code object with the same parameters, or a
+// failure pattern seen before) reuses its code instead of running hipRTC.
+static std::mutex g_code_mu;
+static std::map<std::string, std::vector<char>> &g_code_cache = *new std::map<std::string, std::vector<char>>();
+
+static int bs_compile_locked(BsKernel &bk) {
+    {
+        std::lock_guard<std::mutex> lk(g_code_mu);
+        auto it = g_code_cache.find(bk.source);
+        if (it != g_code_cache.end()) {
+            bk.code = it->second;
+            return ST_OK;
+        }
+    }
     hiprtcProgram prog;
-    if (hiprtcCreateProgram(&prog, bp.source.c_str(), "pm_bitslice.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
+    if (hiprtcCreateProgram(&prog, bk.source.c_str(), "pm_bitslice.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
         return ST_EHIP;
     const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17"};
     hiprtcResult r = hiprtcCompileProgram(prog, 3, opts);
@@ -325,61 +414,106 @@ static int bs_compile_locked(BsProgram &bp) {
     }
     size_t cs = 0;
     hiprtcGetCodeSize(prog, &cs);
-    bp.code.resize(cs);
-    hiprtcGetCode(prog, bp.code.data());
+    bk.code.resize(cs);
+    hiprtcGetCode(prog, bk.code.data());
     hiprtcDestroyProgram(&prog);
+    std::lock_guard<std::mutex> lk(g_code_mu);
+    g_code_cache.emplace(bk.source, bk.code);
     return ST_OK;
 }
 
 BsProgram::~BsProgram() {
-    for (auto &kv : dev)
-        if (kv.second.mod) (void)hipModuleUnload(kv.second.mod);
+    for (BsKernel &bk : k)
+        for (auto &kv : bk.dev)
+            if (kv.second.mod) (void)hipModuleUnload(kv.second.mod);
 }
 
-int bs_launch(BsProgram &bp, const uint8_t *in, uint64_t in_ld, uint8_t *out, uint64_t out_ld, uint64_t s,
-              hipStream_t st) {
-    int st_c = bs_compile(bp);
+// The module of a compiled kernel on the current device (loaded on first
+// use there), with its work-group slots per XCD.
+static int bs_module(BsProgram &bp, BsKind kind, BsModule **out) {
+    int st_c = bs_compile(bp, kind);
     if (st_c != ST_OK) return st_c;
     int devid = 0;
     hipError_t e = hipGetDevice(&devid);
     if (e != hipSuccess) return hip_fail(e);
-    BsModule *m;
-    {
-        std::lock_guard<std::mutex> lk(bp.mu);
-        m = &bp.dev[devid];
-        if (!m->fn) {
-            if ((e = hipModuleLoadData(&m->mod, bp.code.data())) != hipSuccess) return hip_fail(e);
-            if ((e = hipModuleGetFunction(&m->fn, m->mod, "pmbs")) != hipSuccess) return hip_fail(e);
-            int per_cu = 0, ncu = 0;
-            if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, m->fn, 64 * kWaves, 0) != hipSuccess ||
-                per_cu < 1)
-                per_cu = 1;
-            if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, devid) != hipSuccess || ncu < 8)
-                ncu = 256;
-            const int p0 = std::max(1, per_cu * ncu / 8);
-            m->P = bp.ngroups <= p0 ? (p0 / bp.ngroups) * bp.ngroups : p0;
+    std::lock_guard<std::mutex> lk(bp.mu);
+    BsKernel &bk = bp.k[kind];
+    BsModule *m = &bk.dev[devid];
+    if (!m->fn) {
+        if (!m->mod && (e = hipModuleLoadData(&m->mod, bk.code.data())) != hipSuccess) {
+            m->mod = nullptr;
+            return hip_fail(e);
         }
+        hipFunction_t fn = nullptr;
+        if ((e = hipModuleGetFunction(&fn, m->mod, kind == BS_MULTI ? "pmbs_multi" : "pmbs")) != hipSuccess)
+            return hip_fail(e);
+        int per_cu = 0, ncu = 0;
+        if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * kWaves, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, devid) != hipSuccess || ncu < 8)
+            ncu = 256;
+        const int p0 = std::max(1, per_cu * ncu / 8);
+        m->P = bp.ngroups <= p0 ? (p0 / bp.ngroups) * bp.ngroups : p0;
+        m->fn = fn;
     }
+    *out = m;
+    return ST_OK;
+}
+
+BsItem bs_item(const uint8_t *in, uint64_t in_ld, uint8_t *out, uint64_t out_ld, uint64_t s, uint32_t tile0) {
+    const uint64_t s16 = s & ~uint64_t(15), nfull = s16 / kBsTileBytes;
+    return BsItem{in, in_ld, out, out_ld, s, static_cast<uint32_t>(nfull),
+                  static_cast<uint32_t>(nfull + (s16 % kBsTileBytes ? 1 : 0)), tile0, 0};
+}
+
+int bs_load(BsProgram &bp, BsKind kind) {
+    BsModule *m;
+    return bs_module(bp, kind, &m);
+}
+
+// The kernel's one (struct) parameter goes through kernelParams, whose
+// values the runtime copies at the launch call, also when the stream is
+// being captured into a graph (a pointer to a caller's buffer passed in
+// `extra` would have to outlive the graph).
+template <class Args>
+static int bs_go(BsModule *m, Args &args, hipStream_t st) {
+    void *params[] = {&args};
+    hipError_t e = hipModuleLaunchKernel(m->fn, static_cast<unsigned>(8 * m->P), 1, 1, 64 * kWaves, 1, 1, 0, st,
+                                         params, nullptr);
+    return e == hipSuccess ? ST_OK : hip_fail(e);
+}
+
+int bs_launch(BsProgram &bp, const uint8_t *in, uint64_t in_ld, uint8_t *out, uint64_t out_ld, uint64_t s,
+              hipStream_t st) {
     // the window tile needs one full tile before it; shorter blocks are
     // refused here and left to the table kernels by the caller
     if (s < kBsTileBytes) return ST_EINVAL;
-    const uint64_t s16 = s & ~uint64_t(15), nfull = s16 / kBsTileBytes;
-    const uint64_t ntiles = nfull + (s16 % kBsTileBytes ? 1 : 0);
-    if (ntiles > 0xffffffffull) return ST_EINVAL;
+    if (s / kBsTileBytes + 1 > 0xffffffffull) return ST_EINVAL;
+    BsModule *m;
+    int rc = bs_module(bp, BS_SINGLE, &m);
+    if (rc != ST_OK) return rc;
+    const BsItem it = bs_item(in, in_ld, out, out_ld, s, 0);
     struct {
         const uint8_t *in;
         uint64_t ld;
         uint8_t *out;
-        uint64_t old;
-        uint64_t s;
+        uint64_t old, s;
         uint32_t nfull, ntiles, P;
-    } args{in, in_ld, out, out_ld, s, static_cast<uint32_t>(nfull), static_cast<uint32_t>(ntiles),
-           static_cast<uint32_t>(m->P)};
-    size_t size = sizeof(args);
-    void *cfg[] = {HIP_LAUNCH_PARAM_BUFFER_POINTER, &args, HIP_LAUNCH_PARAM_BUFFER_SIZE, &size, HIP_LAUNCH_PARAM_END};
-    e = hipModuleLaunchKernel(m->fn, static_cast<unsigned>(8 * m->P), 1, 1, 64 * kWaves, 1, 1, 0, st, nullptr, cfg);
-    if (e != hipSuccess) return hip_fail(e);
-    return ST_OK;
+    } args{in, in_ld, out, out_ld, s, it.nfull, it.ntiles, static_cast<uint32_t>(m->P)};
+    return bs_go(m, args, st);
+}
+
+int bs_launch_items(BsProgram &bp, const BsItem *d_items, uint32_t nitems, uint32_t ntiles, hipStream_t st) {
+    if (nitems == 0 || ntiles == 0) return ST_OK;
+    BsModule *m;
+    int rc = bs_module(bp, BS_MULTI, &m);
+    if (rc != ST_OK) return rc;
+    struct {
+        const BsItem *items;
+        uint32_t nitems, ntiles, P, pad;
+    } args{d_items, nitems, ntiles, static_cast<uint32_t>(m->P), 0};
+    return bs_go(m, args, st);
 }
 
 }  // namespace pmrc

@@ -110,9 +110,9 @@ std::shared_ptr<BsProgram> ProgEntry::bitslice() {
     return bs;
 }
 
-std::shared_ptr<BsProgram> ProgEntry::bitslice_if_compiled() {
+std::shared_ptr<BsProgram> ProgEntry::bitslice_if_compiled(int kind) {
     std::lock_guard<std::mutex> lk(mu);
-    if (bs && bs->state.load(std::memory_order_acquire) == BS_READY) return bs;
+    if (bs && bs_ready(*bs, static_cast<BsKind>(kind))) return bs;
     return nullptr;
 }
 
@@ -169,7 +169,7 @@ int launch_program(ProgEntry &pe, int vec, const uint8_t *in, size_t in_ld, size
         vec = 4;
     } else if (vec == kVecAuto) {
         if (s >= kBsTileBytes)
-            if (std::shared_ptr<BsProgram> bp = pe.bitslice_if_compiled())
+            if (std::shared_ptr<BsProgram> bp = pe.bitslice_if_compiled(BS_SINGLE))
                 return bs_launch(*bp, in, in_ld, out, out_ld, s, stream);
         vec = kVecTable;
     }
@@ -448,16 +448,17 @@ pm_status pm_set_variant(pm_code *c, int op, uint32_t rg, uint32_t vec) {
     return PM_OK;
 }
 
-pm_status pm_prepare(pm_code *c, int op, uint32_t failed, const uint32_t *ids, int *specialized) {
+pm_status pm_prepare(pm_code *c, int op, uint32_t failed, const uint32_t *ids, uint32_t flags, int *specialized) {
     if (specialized) *specialized = 0;
-    if (!c || op < 0 || op > 3) return PM_EINVAL;
+    if (!c || op < 0 || op > 3 || (flags & ~static_cast<uint32_t>(PM_PREPARE_BATCHED))) return PM_EINVAL;
     Resolved r;
     int st = resolve_op(c, op, failed, ids, &r);
     if (st != ST_OK) return static_cast<pm_status>(st);
     if (r.vec != kVecAuto && r.vec != kVecBitslice) return PM_OK;   // an explicit table variant
     std::shared_ptr<BsProgram> bp = r.pe->bitslice();
     if (!bp) return PM_OK;
-    if ((st = bs_compile(*bp)) != ST_OK) return static_cast<pm_status>(st);
+    if ((st = bs_compile(*bp, BS_SINGLE)) != ST_OK) return static_cast<pm_status>(st);
+    if ((flags & PM_PREPARE_BATCHED) && (st = bs_compile(*bp, BS_MULTI)) != ST_OK) return static_cast<pm_status>(st);
     if (specialized) *specialized = 1;
     return PM_OK;
 }

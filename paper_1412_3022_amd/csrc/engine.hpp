@@ -53,9 +53,9 @@ struct ProgEntry {
     // The bit-sliced specialization, generated (not compiled) on first use;
     // nullptr when the matrix is too large to specialize.
     std::shared_ptr<BsProgram> bitslice();
-    // The specialization if it has been generated and compiled, else nullptr
-    // (never generates or compiles).
-    std::shared_ptr<BsProgram> bitslice_if_compiled();
+    // The specialization if its kernel of this BsKind has been compiled, else
+    // nullptr (never generates or compiles).
+    std::shared_ptr<BsProgram> bitslice_if_compiled(int kind);
     int device_ptr(hipStream_t user, const uint32_t **out);
     // Same, but returns only once the copy has landed (for plans and graphs).
     int device_ptr_sync(const uint32_t **out);

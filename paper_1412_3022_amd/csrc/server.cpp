@@ -122,6 +122,8 @@ struct Slot {
     hipEvent_t done = nullptr;
     HostItem *h_items = nullptr;   // pinned staging of the work lists
     void *d_items = nullptr;
+    BsItem *h_bs = nullptr;        // pinned staging of the bit-sliced item lists
+    BsItem *d_bs = nullptr;
     uint32_t *d_counters = nullptr;
     std::vector<Req *> reqs;
     bool busy = false;
@@ -160,6 +162,8 @@ struct pm_server {
             if (s.stream) (void)hipStreamDestroy(s.stream);
             if (s.h_items) (void)hipHostFree(s.h_items);
             if (s.d_items) (void)hipFree(s.d_items);
+            if (s.h_bs) (void)hipHostFree(s.h_bs);
+            if (s.d_bs) (void)hipFree(s.d_bs);
             if (s.d_counters) (void)hipFree(s.d_counters);
         }
         if (arena_base) (void)hipFree(arena_base);
@@ -187,12 +191,22 @@ struct pm_server {
     // them and launch.
     int launch(Slot &sl) {
         std::vector<HostItem> lists[kPhases][kClasses];
+        // items whose matrix has a compiled multi-set bit-sliced kernel, per
+        // phase and matrix
+        std::map<BsProgram *, std::pair<std::shared_ptr<BsProgram>, std::vector<BsItem>>> bs_lists[kPhases];
         const int vec = static_cast<int>(cfg.dwords_per_lane ? cfg.dwords_per_lane : 2);
         const uint64_t wave_bytes = static_cast<uint64_t>(pmk_wave_bytes(vec));
         auto add = [&](int phase, const Resolved &rs, const uint8_t *in, uint64_t in_ld, uint8_t *out,
                        uint64_t out_ld, uint64_t s) {
             const Program &p = rs.pe->prog;
             if (p.ngroups == 0) return;
+            if (s >= kBsTileBytes && (rs.vec == kVecAuto || rs.vec == kVecBitslice))
+                if (std::shared_ptr<BsProgram> bp = rs.pe->bitslice_if_compiled(BS_MULTI)) {
+                    auto &e = bs_lists[phase][bp.get()];
+                    e.first = bp;
+                    e.second.push_back(bs_item(in, in_ld, out, out_ld, s, 0));
+                    return;
+                }
             const uint32_t *dprog = nullptr;
             if (rs.pe->device_ptr_sync(&dprog) != ST_OK) return;
             const uint64_t ntiles = (s + wave_bytes - 1) / wave_bytes;
@@ -229,11 +243,40 @@ struct pm_server {
                 std::copy(lists[ph][c].begin(), lists[ph][c].end(), sl.h_items + pos);
                 pos += static_cast<uint32_t>(lists[ph][c].size());
             }
+        // Stage the bit-sliced lists back to back, tiles numbered per matrix.
+        struct BsLaunch {
+            BsProgram *bp;
+            uint32_t start, n, ntiles;
+        };
+        std::vector<BsLaunch> bs_launches[kPhases];
+        uint32_t bpos = 0;
+        for (int ph = 0; ph < kPhases; ++ph)
+            for (auto &kv : bs_lists[ph]) {
+                std::vector<BsItem> &v = kv.second.second;
+                if (bpos + v.size() > item_cap) return ST_EINVAL;
+                uint64_t tile = 0;
+                for (BsItem &it : v) {
+                    it.tile0 = static_cast<uint32_t>(tile);
+                    tile += it.ntiles;
+                }
+                if (tile > 0xffffff00ull) return ST_EINVAL;
+                std::copy(v.begin(), v.end(), sl.h_bs + bpos);
+                bs_launches[ph].push_back(BsLaunch{kv.first, bpos, static_cast<uint32_t>(v.size()),
+                                                   static_cast<uint32_t>(tile)});
+                bpos += static_cast<uint32_t>(v.size());
+            }
         hipError_t e;
         if (pos && (e = hipMemcpyAsync(sl.d_items, sl.h_items, pos * sizeof(HostItem), hipMemcpyHostToDevice,
                                        sl.stream)) != hipSuccess)
             return hip_fail(e);
-        for (int ph = 0; ph < kPhases; ++ph)
+        if (bpos && (e = hipMemcpyAsync(sl.d_bs, sl.h_bs, bpos * sizeof(BsItem), hipMemcpyHostToDevice,
+                                        sl.stream)) != hipSuccess)
+            return hip_fail(e);
+        for (int ph = 0; ph < kPhases; ++ph) {
+            for (const BsLaunch &l : bs_launches[ph]) {
+                int rc = bs_launch_items(*l.bp, sl.d_bs + l.start, l.n, l.ntiles, sl.stream);
+                if (rc != ST_OK) return rc;
+            }
             for (int c = 0; c < kClasses; ++c) {
                 if (!units[ph][c]) continue;
                 PmkBatch h{static_cast<HostItem *>(sl.d_items) + start[ph][c],
@@ -241,6 +284,7 @@ struct pm_server {
                            sl.d_counters + (ph * kClasses + c) * 8 * 16};
                 if ((e = pmk_batch(rg_of(c), vec, &h, sl.stream)) != hipSuccess) return hip_fail(e);
             }
+        }
         if ((e = hipEventRecord(sl.done, sl.stream)) != hipSuccess) return hip_fail(e);
         return ST_OK;
     }
@@ -353,6 +397,9 @@ pm_status pm_server_create(const pm_server_cfg *cfg, pm_server **out) {
             (e = hipHostMalloc(reinterpret_cast<void **>(&sl.h_items), s->item_cap * sizeof(HostItem), 0)) !=
                 hipSuccess ||
             (e = hipMalloc(&sl.d_items, s->item_cap * sizeof(HostItem))) != hipSuccess ||
+            (e = hipHostMalloc(reinterpret_cast<void **>(&sl.h_bs), s->item_cap * sizeof(BsItem), 0)) !=
+                hipSuccess ||
+            (e = hipMalloc(reinterpret_cast<void **>(&sl.d_bs), s->item_cap * sizeof(BsItem))) != hipSuccess ||
             (e = hipMalloc(reinterpret_cast<void **>(&sl.d_counters),
                            kPhases * kClasses * 8 * 16 * sizeof(uint32_t))) != hipSuccess)
             return static_cast<pm_status>(hip_fail(e));

@@ -46,6 +46,7 @@ class pm_batch_item(ctypes.Structure):
 
 
 PM_BATCH_GRAPH = 1
+PM_BATCH_SPECIALIZE = 2
 
 _L = None
 
@@ -72,7 +73,7 @@ def _lib():
         L.pm_apply.argtypes = [vp, u32, u32, vp, sz, vp, sz, sz, vp]
         L.pm_set_variant.argtypes = [vp, i32, u32, u32]
         L.pm_autotune_encode.argtypes = [vp, vp, sz, vp, sz, sz, u32, vp, u32p, u32p]
-        L.pm_prepare.argtypes = [vp, i32, u32, u32p, ctypes.POINTER(ctypes.c_int)]
+        L.pm_prepare.argtypes = [vp, i32, u32, u32p, u32, ctypes.POINTER(ctypes.c_int)]
         L.pm_batch_plan.argtypes = [ctypes.POINTER(pm_batch_item), sz, u32, ctypes.POINTER(vp)]
         L.pm_batch_set_variant.argtypes = [vp, u32, u32]
         L.pm_batch_autotune.argtypes = [vp, u32, vp, u32p]
@@ -156,10 +157,13 @@ def pm_set_variant(h, op, rows_per_group, dwords_per_lane):
     return _lib().pm_set_variant(h, op, rows_per_group, dwords_per_lane)
 
 
-def pm_prepare(h, op, failed=0, ids=None):
+PM_PREPARE_BATCHED = 1
+
+
+def pm_prepare(h, op, failed=0, ids=None, flags=0):
     """Init phase of one operation; returns (status, specialized)."""
     spec = ctypes.c_int()
-    st = _lib().pm_prepare(h, op, failed, _u32arr(ids) if ids is not None else None, ctypes.byref(spec))
+    st = _lib().pm_prepare(h, op, failed, _u32arr(ids) if ids is not None else None, flags, ctypes.byref(spec))
     return st, spec.value
 
 
@@ -227,10 +231,11 @@ class Code:
     def set_variant(self, op, rows_per_group, dwords_per_lane):
         _check(pm_set_variant(self.h, op, rows_per_group, dwords_per_lane), "pm_set_variant")
 
-    def prepare(self, op, failed=0, ids=None):
-        """Build the operation's matrix and compile its bit-sliced kernel;
-        True when that kernel is ready (False: the table kernel runs)."""
-        st, spec = pm_prepare(self.h, op, failed, ids)
+    def prepare(self, op, failed=0, ids=None, batched=False):
+        """Build the operation's matrix and compile its bit-sliced kernel (and,
+        if batched, the multi-set form batches and the server use); True when
+        that kernel is ready (False: the table kernel runs)."""
+        st, spec = pm_prepare(self.h, op, failed, ids, PM_PREPARE_BATCHED if batched else 0)
         _check(st, "pm_prepare")
         return bool(spec)
 
@@ -279,7 +284,7 @@ class Batch:
     "newcomer" | "decode"), inp and out (2-D uint8 device tensors),
     block_bytes, and failed / ids for repair and decode."""
 
-    def __init__(self, items, graph=True):
+    def __init__(self, items, graph=True, specialize=False):
         arr = (pm_batch_item * max(1, len(items)))()
         keep = []
         for i, it in enumerate(items):
@@ -298,8 +303,8 @@ class Batch:
             e.out, e.out_ld = out.data_ptr(), (out.stride(0) if out.dim() == 2 else 16)
             e.block_bytes = int(it["block_bytes"])
         h = ctypes.c_void_p()
-        _check(_lib().pm_batch_plan(arr, len(items), PM_BATCH_GRAPH if graph else 0, ctypes.byref(h)),
-               "pm_batch_plan")
+        flags = (PM_BATCH_GRAPH if graph else 0) | (PM_BATCH_SPECIALIZE if specialize else 0)
+        _check(_lib().pm_batch_plan(arr, len(items), flags, ctypes.byref(h)), "pm_batch_plan")
         self.h = h.value
         self.codes = [it["code"] for it in items]   # keep codes alive
 

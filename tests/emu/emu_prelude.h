@@ -1,0 +1,24 @@
+// Host stand-ins that let a generated bit-sliced kernel source compile as
+// plain C++ (clang, for the ext_vector_type loads): the kernels share nothing
+// between threads (no LDS, no barriers; cross-lane reads only of wave-uniform
+// values), so running every (block, thread) in turn gives the GPU's bytes.
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+struct EmuDim { unsigned x; };
+static EmuDim threadIdx, blockIdx;
+#define __device__
+#define __global__
+#define __constant__ static const
+#define __launch_bounds__(x)
+#define __noinline__ __attribute__((noinline))
+#define __forceinline__ inline
+// The kernels use truth table 0x96 only: a ^ b ^ c.
+#define __builtin_amdgcn_bitop3_b32(a, b, c, imm) ((a) ^ (b) ^ (c))
+// Like the builtin, returns int (a caller that widens it without going
+// through an unsigned type sign-extends, as on the GPU).
+#define __builtin_amdgcn_readfirstlane(x) ((int)(x))
+#define __builtin_nontemporal_store(v, p) (*(p) = (v))

@@ -150,3 +150,112 @@ def test_config4_shape_scaled_down():
         pos = np.unique(np.concatenate([rng.integers(0, s, 64), [0, s - 1]]))
         got = it["out"].cpu().numpy()[:, pos]
         assert np.array_equal(got, O.apply(o.enc, X[:, pos]))
+
+
+def _fixed_pattern_items(seed, count, max_bytes, fams):
+    """Items over a few fixed matrices per code (encode, one repair pattern,
+    one decode pattern), ragged sizes from 1 byte to max_bytes, so that a
+    specialized plan compiles few kernels but runs many region sets."""
+    st = synth.Stream(seed)
+    dev = device()
+    items, expected = [], []
+    for i in range(count):
+        c, o, f, H, K = fams[st.below(len(fams))]
+        s = 1 + st.below(max_bytes) if st.below(4) else 2048 + st.below(16)
+        X = synth.random_bytes(seed * 7919 + i, c.B * s).reshape(c.B, s)
+        P = o.encode(X, nthreads=8)
+        nodes = {j: o.node_blocks(j, X, P) for j in range(c.n)}
+        op = ["encode", "helper", "newcomer", "decode"][st.below(4)]
+        ld = (s + 15) // 16 * 16 + 16 * st.below(3)
+        if op == "encode":
+            inp, want, extra = X, P, {}
+        elif op == "helper":
+            inp = nodes[H[0]]
+            want = O.apply(o.helper_row(f), inp)
+            extra = {"failed": f}
+        elif op == "newcomer":
+            inp = np.stack([O.apply(o.helper_row(f), nodes[h])[0] for h in H])
+            want = nodes[f]
+            extra = {"failed": f, "ids": H}
+        else:
+            inp = np.concatenate([nodes[j] for j in K])
+            want = X
+            extra = {"ids": K}
+        tin = torch.zeros((inp.shape[0], ld), dtype=torch.uint8, device=dev)
+        tin[:, :s] = torch.from_numpy(np.ascontiguousarray(inp)).to(dev)
+        tout = torch.full((want.shape[0], ld), 0x5A, dtype=torch.uint8, device=dev)
+        items.append(dict(code=c, op=op, inp=tin, out=tout, block_bytes=s, **extra))
+        expected.append(want)
+    return items, expected
+
+
+def _fams():
+    fams = []
+    for kw, ok, f, H, K in [
+        (dict(k=4, d=6, n=8), (O.MSR, 4, 6, 8, O.SPARSE), 5, [0, 1, 2, 3, 4, 6], [1, 4, 6, 7]),
+        (dict(k=8, d=14, n=16), (O.MSR, 8, 14, 16, O.SPARSE), 9, [0, 1, 2, 3, 4, 5, 6, 7, 8, 10, 11, 12, 13, 14],
+         [0, 3, 5, 8, 9, 11, 13, 15]),
+    ]:
+        fams.append((pm.Code(**kw), O.Code(*ok), f, H, K))
+    return fams
+
+
+def test_specialized_batch_matches_oracle():
+    """PM_BATCH_SPECIALIZE: items of >= 2048 bytes run on the multi-set
+    bit-sliced kernels (one launch per matrix), shorter ones on the table work
+    lists; every item equals the oracle, run after run."""
+    print("specialized batch, plain launches", flush=True)
+    items, expected = _fixed_pattern_items(21, 48, 12000, _fams())
+    assert any(it["block_bytes"] >= 2048 for it in items) and any(it["block_bytes"] < 2048 for it in items)
+    plain = pm.Batch(items, graph=False)
+    b = pm.Batch(items, graph=False, specialize=True)
+    assert b.info()[1] > plain.info()[1]      # bit-sliced launches were added
+    for rep in range(2):
+        for it in items:
+            it["out"].fill_(0x5A)
+        torch.cuda.synchronize()
+        b.run()
+        _check(items, expected)
+
+
+def test_specialized_batch_graph_replays():
+    """The same specialized plan captured in a HIP graph: every replay gives
+    the oracle's bytes."""
+    print("specialized batch, graph replays", flush=True)
+    items, expected = _fixed_pattern_items(22, 40, 12000, _fams())
+    b = pm.Batch(items, graph=True, specialize=True)
+    for rep in range(3):
+        for it in items:
+            it["out"].fill_(0x5A)
+        torch.cuda.synchronize()
+        b.run()
+        _check(items, expected)
+
+
+def test_specialized_k16_encode_single_and_batched():
+    """The k = 16 encode network (30 row groups of 8 x 30): its single-set
+    kernel through pm_prepare and its multi-set kernel through a specialized
+    batch, both against the oracle."""
+    print("k16 specialized encode", flush=True)
+    c = pm.Code(k=16, d=30, n=32)
+    o = O.Code(O.MSR, 16, 30, 32, O.SPARSE)
+    assert c.prepare(pm.OP_ENCODE) is True
+    dev = device()
+    items, expected = [], []
+    for i, s in enumerate([2048, 2049, 5000, 3 * 2048 + 16, 20000]):
+        X = synth.random_bytes(3100 + i, c.B * s).reshape(c.B, s)
+        want = o.encode(X, nthreads=8)
+        ld = (s + 15) // 16 * 16
+        tin = torch.zeros((c.B, ld), dtype=torch.uint8, device=dev)
+        tin[:, :s] = torch.from_numpy(X).to(dev)
+        tout = torch.full((c.enc_rows, ld), 0x5A, dtype=torch.uint8, device=dev)
+        items.append(dict(code=c, op="encode", inp=tin, out=tout, block_bytes=s))
+        expected.append(want)
+        single = torch.full_like(tout, 0x5A)
+        c.encode(tin, single, s)
+        torch.cuda.synchronize()
+        got = single.cpu().numpy()
+        assert np.array_equal(got[:, :s], want) and np.all(got[:, s:] == 0x5A)
+    b = pm.Batch(items, graph=False, specialize=True)
+    b.run()
+    _check(items, expected)

@@ -122,3 +122,37 @@ def test_queue_full_and_oversized_requests():
         assert e.value.status == pm.PM_ENOMEM
     finally:
         srv.close()
+
+
+def test_served_mix_with_specialized_kernels():
+    """With the encode, repair and decode matrices of two families prepared
+    for batched use, their requests of >= 2048 bytes run on the multi-set
+    bit-sliced kernels inside the micro-batches; every result still equals
+    the same request run alone and the object it came from."""
+    print("server mix specialized", flush=True)
+    wl = workloads.ServeWorkload(33, device(), 1 << 10, 256 << 10, resident_per_family=2)
+    for name in ("msr4", "msr8"):
+        c = wl.codes[name]
+        assert c.prepare(pm.OP_ENCODE, batched=True)
+        for obj in wl.resident[name]:
+            c.prepare(pm.OP_HELPER, failed=obj["failed"], batched=True)
+            c.prepare(pm.OP_NEWCOMER, failed=obj["failed"], ids=obj["helpers"], batched=True)
+            c.prepare(pm.OP_DECODE, ids=obj["K"], batched=True)
+    reqs, arrivals, nbytes = wl.requests(200, rate_per_s=2e5)
+    srv = pm.Server(64 << 20, streams=3, max_batch=8)
+    try:
+        comps = srv.replay(reqs, arrivals, keep=True)
+        torch.cuda.synchronize()
+        for q, c in zip(reqs, comps):
+            assert c["status"] == pm.PM_OK
+            s = q["block_bytes"]
+            got = _result(c, c["out_blocks"], s)
+            assert torch.equal(got, _alone(q)), (q["op"], s)
+            if q["op"] == "repair":
+                assert torch.equal(got, q["obj"]["nodes"][q["failed"]])
+            elif q["op"] == "decode":
+                assert torch.equal(got, q["obj"]["X"])
+            srv.release(c["ticket"])
+        assert srv.stats()["completed"] == len(reqs)
+    finally:
+        srv.close()

@@ -138,9 +138,9 @@ def test_default_variant_never_compiles_by_itself():
     spec = ctypes.c_int(-1)
     ids = (ctypes.c_uint32 * 3)(0, 2, 5)
     c.set_variant(pm.OP_DECODE, 4, 2)           # explicit table variant: prepare compiles nothing
-    assert L.pm_prepare(c.h, pm.OP_DECODE, 0, ids, ctypes.byref(spec)) == pm.PM_OK and spec.value == 0
+    assert L.pm_prepare(c.h, pm.OP_DECODE, 0, ids, 0, ctypes.byref(spec)) == pm.PM_OK and spec.value == 0
     c.set_variant(pm.OP_DECODE, 0, 0)
-    assert L.pm_prepare(c.h, pm.OP_DECODE, 0, ids, ctypes.byref(spec)) == pm.PM_OK and spec.value == 1
+    assert L.pm_prepare(c.h, pm.OP_DECODE, 0, ids, 0, ctypes.byref(spec)) == pm.PM_OK and spec.value == 1
 
 
 def test_prepare_reports_table_kernel_cases():
@@ -148,8 +148,8 @@ def test_prepare_reports_table_kernel_cases():
     c = pm.Code(k=4, d=6, n=8)
     c.set_variant(pm.OP_ENCODE, 8, 2)
     assert c.prepare(pm.OP_ENCODE) is False
-    # the k=16 encode network is over the size limit: table kernel
-    assert pm.Code(k=16, d=30, n=32).prepare(pm.OP_ENCODE) is False
+    # a dense k=16 decode (from the 16 parity nodes) is over the size limit
+    assert pm.Code(k=16, d=30, n=32).prepare(pm.OP_DECODE, ids=list(range(16, 32))) is False
 
 
 @pytest.mark.parametrize("op,failed,ids", [
