@@ -176,12 +176,12 @@ pm_status pm_set_variant(pm_code *code, int op, uint32_t rows_per_group,
  * matrix (op 0 encode, 1 repair helper, 2 repair newcomer, 3 decode; failed
  * and ids as for those calls, ids on the host) and, under the default or the
  * bit-sliced variant, generates its bit-sliced kernel and compiles it with
- * hipRTC (seconds; no GPU needed; a no-op when already compiled).  With
- * PM_PREPARE_BATCHED in flags it also compiles the kernel's multi-set form,
- * which batches and the server use for this operation.  *specialized (may
- * be NULL) = 1 when the bit-sliced kernel is ready for this operation, 0
- * when the table kernel will run (matrix over the size limit, or an explicit
- * table variant).  PM_EINVAL for bad ids or flags, PM_EHIP if hipRTC fails. */
+ * hipRTC (seconds; no GPU needed; a no-op when already compiled): the
+ * single-set form that the calls above use, or with PM_PREPARE_BATCHED in
+ * flags the multi-set form that batches and the server use.  *specialized
+ * (may be NULL) = 1 when that kernel is ready, 0 when the table kernel will
+ * run (matrix over the size limit, or an explicit table variant).
+ * PM_EINVAL for bad ids or flags, PM_EHIP if hipRTC fails. */
 #define PM_PREPARE_BATCHED 1u
 pm_status pm_prepare(pm_code *code, int op, uint32_t failed, const uint32_t *ids, uint32_t flags,
                      int *specialized);

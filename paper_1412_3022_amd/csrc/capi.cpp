@@ -457,8 +457,8 @@ pm_status pm_prepare(pm_code *c, int op, uint32_t failed, const uint32_t *ids, u
     if (r.vec != kVecAuto && r.vec != kVecBitslice) return PM_OK;   // an explicit table variant
     std::shared_ptr<BsProgram> bp = r.pe->bitslice();
     if (!bp) return PM_OK;
-    if ((st = bs_compile(*bp, BS_SINGLE)) != ST_OK) return static_cast<pm_status>(st);
-    if ((flags & PM_PREPARE_BATCHED) && (st = bs_compile(*bp, BS_MULTI)) != ST_OK) return static_cast<pm_status>(st);
+    if ((st = bs_compile(*bp, (flags & PM_PREPARE_BATCHED) ? BS_MULTI : BS_SINGLE)) != ST_OK)
+        return static_cast<pm_status>(st);
     if (specialized) *specialized = 1;
     return PM_OK;
 }

@@ -232,9 +232,10 @@ class Code:
         _check(pm_set_variant(self.h, op, rows_per_group, dwords_per_lane), "pm_set_variant")
 
     def prepare(self, op, failed=0, ids=None, batched=False):
-        """Build the operation's matrix and compile its bit-sliced kernel (and,
-        if batched, the multi-set form batches and the server use); True when
-        that kernel is ready (False: the table kernel runs)."""
+        """Build the operation's matrix and compile its bit-sliced kernel: the
+        single-set form the calls use, or if batched the multi-set form that
+        batches and the server use; True when that kernel is ready (False:
+        the table kernel runs)."""
         st, spec = pm_prepare(self.h, op, failed, ids, PM_PREPARE_BATCHED if batched else 0)
         _check(st, "pm_prepare")
         return bool(spec)
