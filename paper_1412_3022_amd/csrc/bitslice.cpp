@@ -135,8 +135,42 @@ std::vector<Grp> read_groups(const Program &p) {
 
 int popc(unsigned m) { return __builtin_popcount(m); }
 
+// A load step for every column, the same in every table group that reads
+// it: the groups of a tile run at about the same pace, so a column shared
+// by several groups is then fetched by all of them within a short window
+// and the later fetches hit L2.  Greedy: columns read by most groups first,
+// each at the first step still free in all its groups.
+std::map<uint32_t, int> column_steps(const std::vector<Grp> &gs) {
+    std::map<uint32_t, std::vector<int>> users;
+    for (size_t g = 0; g < gs.size(); ++g) {
+        if (gs[g].kind == GROUP_COPY) continue;
+        for (size_t ci = 0; ci < gs[g].cols.size(); ++ci) {
+            bool any = false;
+            for (size_t r = 0; r < gs[g].rows.size(); ++r) any |= gs[g].coef[r][ci] != 0;
+            if (any) users[gs[g].cols[ci]].push_back(static_cast<int>(g));
+        }
+    }
+    std::vector<uint32_t> order;
+    for (auto &kv : users) order.push_back(kv.first);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t a, uint32_t b) { return users[a].size() > users[b].size(); });
+    std::vector<std::set<int>> taken(gs.size());
+    std::map<uint32_t, int> step;
+    for (uint32_t c : order) {
+        int s = 0;
+        for (;; ++s) {
+            bool free = true;
+            for (int g : users[c]) free &= !taken[g].count(s);
+            if (free) break;
+        }
+        step[c] = s;
+        for (int g : users[c]) taken[g].insert(s);
+    }
+    return step;
+}
+
 // Straight-line code of one table group.
-void emit_table_group(std::ostringstream &o, int gi, const Grp &G) {
+void emit_table_group(std::ostringstream &o, int gi, const Grp &G, const std::map<uint32_t, int> &steps) {
     const int n = static_cast<int>(G.rows.size());
     o << "__device__ __forceinline__ void g" << gi
       << "(const unsigned char *in, u64 ld, unsigned char *out, u64 old, u64 off) {\n" << kOpaqueStrides;
@@ -154,6 +188,8 @@ void emit_table_group(std::ostringstream &o, int gi, const Grp &G) {
         for (int r = 0; r < n; ++r) any |= G.coef[r][ci] != 0;
         if (any) used.push_back(ci);
     }
+    std::stable_sort(used.begin(), used.end(),
+                     [&](size_t a, size_t b) { return steps.at(G.cols[a]) < steps.at(G.cols[b]); });
     auto load = [&](size_t j) {
         o << "  const u32x4 x" << j << "l = *(const u32x4 *)(in + (u64)" << G.cols[used[j]] << "u * ld + off), x" << j
           << "h = *(const u32x4 *)(in + (u64)" << G.cols[used[j]] << "u * ld + off + 1024);\n";
@@ -282,9 +318,10 @@ std::unique_ptr<BsProgram> bs_generate(const Program &p8) {
     std::ostringstream o;
     // reduction polynomial of the field: x^8 = x * x^7
     o << "#define POLY " << (0x100u | gmul(0x80, 2)) << "u\n" << kPrelude;
+    const std::map<uint32_t, int> steps = column_steps(gs);
     for (size_t g = 0; g < gs.size(); ++g) {
         if (gs[g].kind == GROUP_COPY) emit_copy_group(o, static_cast<int>(g), gs[g]);
-        else emit_table_group(o, static_cast<int>(g), gs[g]);
+        else emit_table_group(o, static_cast<int>(g), gs[g], steps);
         emit_byte_tail(o, static_cast<int>(g), gs[g]);
     }
     const int G = bp->ngroups;
