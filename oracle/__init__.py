@@ -82,6 +82,8 @@ def lib():
         L.or_newcomer_matrix.argtypes = [ctypes.c_int, u8p, u8p, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_int, ip, u8p]
         L.or_decode_matrix.argtypes = [u8p, ctypes.c_int, ctypes.c_int, ip, ctypes.c_int, u8p, ip]
+        L.or_msr_specific_decode.argtypes = [u8p, u8p, ip, ctypes.c_int, ctypes.c_int, ip, pp, ctypes.c_int,
+                                             pp, ctypes.c_size_t]
         L.or_init()
         _lib = L
     return _lib
@@ -374,12 +376,34 @@ class Code:
     def decode_matrix(self, K):
         return decode_matrix(self.Gsys, self.B, self.alpha, list(K))
 
+    def decode_specific(self, K, Y):
+        """The same decode by the specific PM-MSR algorithm (MSR only)."""
+        if self.kind != MSR:
+            raise ValueError("specific decoding is defined here for PM-MSR")
+        return msr_specific_decode(self.psi, self.lam, self.L, self.k, K, Y, self.Gsys is not self.G)
+
     def decode(self, K, Y):
         """Y: (k alpha x s) blocks of the nodes in K, node-major."""
         D, kept = self.decode_matrix(K)
         if D is None:
             raise np.linalg.LinAlgError("undecodable node set")
         return apply(D, Y[kept])
+
+
+def msr_specific_decode(psi, lam, L, k, K, Y, systematic_form=True):
+    """Specific PM-MSR decoding from the k nodes K (their k alpha blocks Y,
+    node-major); returns the B data blocks, or None if singular."""
+    Y = np.ascontiguousarray(Y, dtype=np.uint8)
+    s = Y.shape[1]
+    alpha = k - 1
+    B = alpha * (alpha + 1)
+    X = np.zeros((B, s), np.uint8)
+    rc = lib().or_msr_specific_decode(_u8(psi), _u8(lam), _i32(np.ascontiguousarray(L, dtype=np.int32)), k,
+                                      psi.shape[0], _i32(np.array(K, dtype=np.int32)), _ptrs(list(Y)),
+                                      1 if systematic_form else 0, _ptrs(list(X)), s)
+    if rc == -2:
+        raise ValueError("Psi is not of the form [Phi, Lambda Phi]")
+    return None if rc != 0 else X
 
 
 def subsets(n, m):

@@ -511,6 +511,114 @@ int or_newcomer_matrix(int kind, const uint8_t *psi_or_g, const uint8_t *lam, in
 }
 
 /* ------------------------------------------------------------------------ */
+/* Specific PM-MSR decoding: the data-collector algorithm of the seminal
+ * product-matrix paper, which the paper's Section 2 refers to and whose cost
+ * Section 4.1 (decoding paragraph) compares with the linearized decode.
+ * Reading (the paper does not restate its steps; they follow from the MSR
+ * structure it gives in Section 2: Psi = [Phi, Lambda Phi], M = [S1; S2] with
+ * S1, S2 symmetric alpha x alpha, node i storing phi_i^t S1 + lambda_i phi_i^t S2):
+ *  1. Z = Y_DC Phi_DC^t, so Z[i][j] = P_ij + lambda_i Q_ij with
+ *     P = Phi_DC S1 Phi_DC^t and Q = Phi_DC S2 Phi_DC^t, both symmetric;
+ *  2. for i < j, the pair Z[i][j], Z[j][i] gives Q_ij = (Z[i][j] + Z[j][i]) /
+ *     (lambda_i + lambda_j) and P_ij = Z[i][j] + lambda_i Q_ij;
+ *  3. for each of the first alpha connected nodes i, the alpha values P_ij
+ *     (j != i) equal phi_i^t S1 phi_j, so phi_i^t S1 solves an alpha x alpha
+ *     system with rows phi_j^t (likewise phi_i^t S2 from Q);
+ *  4. those alpha rows form Phi_A S1 (Phi_A S2), inverted for S1 (S2);
+ *  5. M gives the message Z_m = M[l][j] at m = L[l][j]; a systematic code
+ *     (Section 3.2) stored G Z with Z = inverse(G~) X, so X = G~ Z is the
+ *     product-matrix encoding of Z for the first k nodes.
+ * The matrices of steps 3-4 do not depend on the data and are inverted once;
+ * the rest runs byte position by byte position.  K lists k distinct nodes,
+ * Y their k alpha blocks node-major, X receives B blocks.  Returns -1 when a
+ * system is singular or the lambda_i of K are not distinct, -2 when Psi does
+ * not have the [Phi, Lambda Phi] form. */
+int or_msr_specific_decode(const uint8_t *psi, const uint8_t *lam, const int *L, int k, int n,
+                           const int *K, const uint8_t *const *Y, int systematic,
+                           uint8_t *const *X, size_t s)
+{
+    const int alpha = k - 1, d = 2 * alpha, B = alpha * (alpha + 1);
+    (void)n;
+    for (int i = 0; i < k; i++)
+        for (int a = 0; a < alpha; a++)
+            if (psi[K[i] * d + alpha + a] != or_mul(lam[K[i]], psi[K[i] * d + a])) return -2;
+    for (int i = 0; i < k; i++)
+        for (int j = i + 1; j < k; j++)
+            if (lam[K[i]] == lam[K[j]]) return -1;
+    /* step 3 systems: Finv[i] inverts the rows phi_j^t, j != i (i < alpha) */
+    uint8_t *Finv = (uint8_t *)malloc((size_t)alpha * alpha * alpha);
+    uint8_t *F = (uint8_t *)malloc((size_t)alpha * alpha);
+    uint8_t *PhiA = (uint8_t *)malloc((size_t)alpha * alpha), *PhiAinv = (uint8_t *)malloc((size_t)alpha * alpha);
+    int rc = 0;
+    for (int i = 0; i < alpha && rc == 0; i++) {
+        int r = 0;
+        for (int j = 0; j < k; j++) {
+            if (j == i) continue;
+            memcpy(F + r * alpha, psi + K[j] * d, (size_t)alpha);
+            r++;
+        }
+        rc = or_invert(F, Finv + (size_t)i * alpha * alpha, alpha);
+    }
+    for (int i = 0; i < alpha; i++) memcpy(PhiA + i * alpha, psi + K[i] * d, (size_t)alpha);
+    if (rc == 0) rc = or_invert(PhiA, PhiAinv, alpha);
+    uint8_t *y = (uint8_t *)malloc((size_t)k * alpha), *z = (uint8_t *)malloc((size_t)k * k);
+    uint8_t *P = (uint8_t *)malloc((size_t)k * k), *Q = (uint8_t *)malloc((size_t)k * k);
+    uint8_t *U = (uint8_t *)malloc((size_t)alpha * alpha), *V = (uint8_t *)malloc((size_t)alpha * alpha);
+    uint8_t *S1 = (uint8_t *)malloc((size_t)alpha * alpha), *S2 = (uint8_t *)malloc((size_t)alpha * alpha);
+    uint8_t *Zm = (uint8_t *)malloc((size_t)B), *pv = (uint8_t *)malloc((size_t)alpha), *qv = (uint8_t *)malloc((size_t)alpha);
+    for (size_t p = 0; p < s && rc == 0; p++) {
+        for (int t = 0; t < k * alpha; t++) y[t] = Y[t][p];
+        /* step 1 */
+        for (int i = 0; i < k; i++)
+            for (int j = 0; j < k; j++) {
+                uint8_t acc = 0;
+                for (int a = 0; a < alpha; a++) acc ^= or_mul(y[i * alpha + a], psi[K[j] * d + a]);
+                z[i * k + j] = acc;
+            }
+        /* step 2 */
+        for (int i = 0; i < k; i++)
+            for (int j = i + 1; j < k; j++) {
+                uint8_t q = or_div(z[i * k + j] ^ z[j * k + i], lam[K[i]] ^ lam[K[j]]);
+                uint8_t pp = z[i * k + j] ^ or_mul(lam[K[i]], q);
+                P[i * k + j] = P[j * k + i] = pp;
+                Q[i * k + j] = Q[j * k + i] = q;
+            }
+        /* step 3: U[i] = phi_i^t S1, V[i] = phi_i^t S2 for the first alpha nodes */
+        for (int i = 0; i < alpha; i++) {
+            int r = 0;
+            for (int j = 0; j < k; j++) {
+                if (j == i) continue;
+                pv[r] = P[i * k + j];
+                qv[r] = Q[i * k + j];
+                r++;
+            }
+            or_matmul(Finv + (size_t)i * alpha * alpha, pv, U + i * alpha, alpha, alpha, 1);
+            or_matmul(Finv + (size_t)i * alpha * alpha, qv, V + i * alpha, alpha, alpha, 1);
+        }
+        /* step 4 */
+        or_matmul(PhiAinv, U, S1, alpha, alpha, alpha);
+        or_matmul(PhiAinv, V, S2, alpha, alpha, alpha);
+        /* step 5: message symbols, then the data */
+        for (int l = 0; l < d; l++)
+            for (int j = 0; j < alpha; j++)
+                Zm[L[l * alpha + j]] = l < alpha ? S1[l * alpha + j] : S2[(l - alpha) * alpha + j];
+        if (!systematic) {
+            for (int m = 0; m < B; m++) X[m][p] = Zm[m];
+        } else {
+            for (int i = 0; i < k; i++)
+                for (int j = 0; j < alpha; j++) {
+                    uint8_t acc = 0;
+                    for (int l = 0; l < d; l++) acc ^= or_mul(psi[i * d + l], Zm[L[l * alpha + j]]);
+                    X[i * alpha + j][p] = acc;
+                }
+        }
+    }
+    free(Finv); free(F); free(PhiA); free(PhiAinv); free(y); free(z); free(P); free(Q);
+    free(U); free(V); free(S1); free(S2); free(Zm); free(pv); free(qv);
+    return rc == 0 ? 0 : -1;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Decode (Section 2: X = inverse(G~) Y~ over the rows of the surviving
  * blocks).  Gsys is the generator the nodes were encoded with (systematic or
  * not), (n alpha) x B.  K lists k nodes; their k alpha rows are scanned in

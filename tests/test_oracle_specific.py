@@ -1,0 +1,56 @@
+"""Pins of the oracle's specific PM-MSR decoder (the seminal paper's
+data-collector algorithm, Section 2): decoding from every k-subset returns the
+encoded object, for both constructions, systematic and not; a repeated node
+(equal lambdas) is refused."""
+import numpy as np
+import pytest
+
+import oracle as O
+
+
+@pytest.mark.parametrize("k,d,n", [(3, 4, 6), (4, 6, 8), (3, 4, 5)])
+@pytest.mark.parametrize("construction", [O.SPARSE, O.VANILLA], ids=["sparse", "vanilla"])
+@pytest.mark.parametrize("systematic_form", [True, False], ids=["sys", "nonsys"])
+def test_every_k_subset_decodes_to_the_object(k, d, n, construction, systematic_form):
+    if construction == O.SPARSE and n < 2 * k - 1:
+        pytest.skip("the sparse construction needs n >= 2k - 1")
+    o = O.Code(O.MSR, k, d, n, construction, systematic_form)
+    rng = np.random.default_rng(k * 100 + n)
+    X = rng.integers(0, 256, (o.B, 53), dtype=np.uint8)
+    P = o.encode(X)
+    nodes = {i: o.node_blocks(i, X, P) for i in range(n)}
+    for K in O.subsets(n, k):
+        Y = np.concatenate([nodes[i] for i in K])
+        got = o.decode_specific(list(K), Y)
+        assert got is not None and np.array_equal(got, X), K
+
+
+def test_k8_random_subsets_and_all_parity():
+    o = O.Code(O.MSR, 8, 14, 16, O.SPARSE)
+    rng = np.random.default_rng(8)
+    X = rng.integers(0, 256, (o.B, 40), dtype=np.uint8)
+    P = o.encode(X, nthreads=4)
+    nodes = {i: o.node_blocks(i, X, P) for i in range(o.n)}
+    subsets = [list(range(8, 16)), list(range(8))] + [sorted(rng.choice(16, 8, replace=False)) for _ in range(6)]
+    for K in subsets:
+        Y = np.concatenate([nodes[i] for i in K])
+        assert np.array_equal(o.decode_specific(K, Y), X), K
+        # and the same bytes as the linearized decode
+        assert np.array_equal(o.decode(K, Y), X)
+
+
+def test_order_of_connected_nodes_does_not_matter():
+    o = O.Code(O.MSR, 4, 6, 8, O.SPARSE)
+    rng = np.random.default_rng(3)
+    X = rng.integers(0, 256, (o.B, 17), dtype=np.uint8)
+    P = o.encode(X)
+    nodes = {i: o.node_blocks(i, X, P) for i in range(o.n)}
+    for K in ([7, 2, 5, 0], [5, 7, 0, 2], [1, 3, 6, 4]):
+        Y = np.concatenate([nodes[i] for i in K])
+        assert np.array_equal(o.decode_specific(K, Y), X)
+
+
+def test_repeated_node_is_refused():
+    o = O.Code(O.MSR, 3, 4, 6, O.SPARSE)
+    Y = np.zeros((3 * o.alpha, 8), np.uint8)
+    assert o.decode_specific([0, 1, 1], Y) is None
