@@ -141,6 +141,29 @@ pm_status pm_decode(const pm_code *code, const uint32_t *nodes, const uint8_t *Y
                     size_t y_ld, uint8_t *X, size_t x_ld, size_t block_bytes,
                     pm_stream stream);
 
+/* Specific PM-MSR decoding: the seminal paper's data-collector algorithm
+ * (Section 2), which the paper's Section 4.1 finds faster than the
+ * linearized decode for large k.  Same nodes, Y and X as pm_decode; the
+ * result is the same bytes.  It runs as region products with small sparse
+ * matrices instead of the dense B x B inverse: (A) P_ij and Q_ij of every
+ * pair of the k nodes from the two nodes' blocks, (B) phi_i^t S1 and
+ * phi_i^t S2 for alpha of the nodes by alpha x alpha solves, (C) S1 and S2,
+ * i.e. the message symbols, and for systematic codes (D) their re-encoding
+ * into the data blocks.  Intermediates go to `workspace` (device, 16-byte
+ * aligned, at least pm_decode_specific_workspace bytes, not overlapping Y or
+ * X); the library allocates nothing.  PM_EUNSUPPORTED for MBR and RS.
+ * Passes use the bit-sliced kernels once compiled (pm_prepare op 4). */
+pm_status pm_decode_specific_workspace(const pm_code *code, size_t block_bytes, size_t *bytes);
+pm_status pm_decode_specific(const pm_code *code, const uint32_t *nodes, const uint8_t *Y, size_t y_ld,
+                             uint8_t *X, size_t x_ld, size_t block_bytes, uint8_t *workspace,
+                             size_t workspace_bytes, pm_stream stream);
+/* The four factors (which = 0..3: A, B, C, D above; D has 0 rows for
+ * non-systematic codes) for nodes, host row-major, cap bytes at dst (dst may
+ * be NULL to query rows and cols).  Their product D C B A is the linearized
+ * decode matrix of pm_decode. */
+pm_status pm_decode_specific_factor(const pm_code *code, const uint32_t *nodes, int which, uint8_t *dst,
+                                    size_t cap, uint32_t *rows, uint32_t *cols);
+
 /* The region engine itself (the constant-times-region multiply-XOR of the
  * paper's Section 4, batched over a matrix): out[r] = XOR_c A[r][c] * in[c]
  * for a host row-major rows x cols matrix A.  Tables are cached by content. */
@@ -173,8 +196,9 @@ pm_status pm_set_variant(pm_code *code, int op, uint32_t rows_per_group,
 
 /* Init phase of one operation, kept apart from the data phase as the
  * paper's evaluation separates them (Section 4): builds the operation's
- * matrix (op 0 encode, 1 repair helper, 2 repair newcomer, 3 decode; failed
- * and ids as for those calls, ids on the host) and, under the default or the
+ * matrix (op 0 encode, 1 repair helper, 2 repair newcomer, 3 decode, 4 the
+ * passes of pm_decode_specific; failed and ids as for those calls, ids on the
+ * host) and, under the default or the
  * bit-sliced variant, generates its bit-sliced kernel and compiles it with
  * hipRTC (seconds; no GPU needed; a no-op when already compiled): the
  * single-set form that the calls above use, or with PM_PREPARE_BATCHED in

@@ -222,6 +222,12 @@ struct pm_code {
     std::map<int, Mat> helper_mat;
     std::map<std::pair<int, std::vector<int>>, Mat> newcomer_mat;
     std::map<std::vector<int>, std::pair<Mat, std::vector<int>>> decode_mat;
+    // specific PM-MSR decode per node list: its factors and their programs
+    struct Specific {
+        Mat F[4];
+        std::map<int, std::unique_ptr<ProgEntry>> progs[4];   // by rg
+    };
+    std::map<std::vector<int>, Specific> specific;
 };
 
 namespace {
@@ -344,6 +350,61 @@ int resolve_op(pm_code *c, int op, uint32_t failed, const uint32_t *ids, Resolve
 
 }  // namespace pmrc
 
+namespace {
+
+// The specific decode of node list ids: factors (built once) and the
+// program of each pass.  npass = 3 for non-systematic codes, else 4.
+struct SpecificOps {
+    ProgEntry *pe[4] = {nullptr, nullptr, nullptr, nullptr};
+    int npass = 0;
+    int rows[4] = {0, 0, 0, 0};
+};
+
+int resolve_specific(pm_code *c, const uint32_t *ids, SpecificOps *out) {
+    if (!c || !ids) return ST_EINVAL;
+    const CodeMats &m = c->m;
+    if (m.kind != KIND_MSR) return ST_EUNSUPPORTED;
+    std::vector<int> list(ids, ids + m.k), sorted;
+    sorted = list;
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) return ST_EINVAL;
+    for (int v : list)
+        if (v < 0 || v >= m.n) return ST_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->specific.find(list);
+    if (it == c->specific.end()) {
+        pm_code::Specific sp;
+        int st = specific_decode_factors(m, list, sp.F);
+        if (st != ST_OK) return st;
+        it = c->specific.emplace(list, std::move(sp)).first;
+    }
+    pm_code::Specific &sp = it->second;
+    out->npass = sp.F[3].rows ? 4 : 3;
+    for (int p = 0; p < out->npass; ++p) {
+        const Mat &F = sp.F[p];
+        const int rg = pick_rg_cached(c->var[3], F);
+        auto &map = sp.progs[p];
+        auto pit = map.find(rg);
+        if (pit == map.end()) {
+            auto pe = std::make_unique<ProgEntry>();
+            pe->prog = build_program(F, rg);
+            pe->A = F;
+            pit = map.emplace(rg, std::move(pe)).first;
+        }
+        out->pe[p] = pit->second.get();
+        out->rows[p] = F.rows;
+    }
+    return ST_OK;
+}
+
+// Workspace blocks of a specific decode: pass A's B outputs, pass B's
+// 2 alpha^2, and for systematic codes the B message symbols.
+size_t specific_ws_blocks(const CodeMats &m) {
+    return static_cast<size_t>(m.B) + 2u * static_cast<size_t>(m.alpha) * m.alpha + (m.systematic ? m.B : 0);
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *pm_status_string(pm_status st) {
@@ -448,9 +509,86 @@ pm_status pm_set_variant(pm_code *c, int op, uint32_t rg, uint32_t vec) {
     return PM_OK;
 }
 
+
+pm_status pm_decode_specific_workspace(const pm_code *c, size_t s, size_t *bytes) {
+    if (!c || !bytes || s == 0) return PM_EINVAL;
+    if (c->m.kind != KIND_MSR) return PM_EUNSUPPORTED;
+    *bytes = specific_ws_blocks(c->m) * ((s + 15) / 16 * 16);
+    return PM_OK;
+}
+
+pm_status pm_decode_specific(const pm_code *cc, const uint32_t *nodes, const uint8_t *Y, size_t y_ld, uint8_t *X,
+                             size_t x_ld, size_t s, uint8_t *workspace, size_t workspace_bytes, pm_stream stream) {
+    if (s == 0) return PM_EINVAL;
+    pm_code *c = const_cast<pm_code *>(cc);
+    SpecificOps ops;
+    int st = resolve_specific(c, nodes, &ops);
+    if (st != ST_OK) return static_cast<pm_status>(st);
+    const CodeMats &m = c->m;
+    const size_t ld = (s + 15) / 16 * 16;
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 15u) ||
+        workspace_bytes < specific_ws_blocks(m) * ld)
+        return PM_EINVAL;
+    // the workspace must not overlap the caller's regions
+    const uintptr_t w0 = reinterpret_cast<uintptr_t>(workspace), w1 = w0 + specific_ws_blocks(m) * ld;
+    auto clear = [&](const uint8_t *base, size_t rld, size_t rows) {
+        const uintptr_t b0 = reinterpret_cast<uintptr_t>(base), b1 = b0 + (rows - 1) * rld + s;
+        return b1 <= w0 || w1 <= b0;
+    };
+    if (!clear(Y, y_ld, static_cast<size_t>(m.k) * m.alpha) || !clear(X, x_ld, static_cast<size_t>(m.B)))
+        return PM_EINVAL;
+    hipStream_t h = reinterpret_cast<hipStream_t>(stream);
+    uint8_t *w1p = workspace, *w2p = w1p + static_cast<size_t>(ops.rows[0]) * ld;
+    uint8_t *zp = w2p + static_cast<size_t>(ops.rows[1]) * ld;
+    const size_t ka = static_cast<size_t>(m.k) * m.alpha;
+    if ((st = launch_program(*ops.pe[0], kVecAuto, Y, y_ld, ka, w1p, ld, ops.rows[0], s, h)) != ST_OK)
+        return static_cast<pm_status>(st);
+    if ((st = launch_program(*ops.pe[1], kVecAuto, w1p, ld, ops.rows[0], w2p, ld, ops.rows[1], s, h)) != ST_OK)
+        return static_cast<pm_status>(st);
+    if (ops.npass == 3)
+        return static_cast<pm_status>(
+            launch_program(*ops.pe[2], kVecAuto, w2p, ld, ops.rows[1], X, x_ld, ops.rows[2], s, h));
+    if ((st = launch_program(*ops.pe[2], kVecAuto, w2p, ld, ops.rows[1], zp, ld, ops.rows[2], s, h)) != ST_OK)
+        return static_cast<pm_status>(st);
+    return static_cast<pm_status>(launch_program(*ops.pe[3], kVecAuto, zp, ld, ops.rows[2], X, x_ld, ops.rows[3], s, h));
+}
+
+pm_status pm_decode_specific_factor(const pm_code *cc, const uint32_t *nodes, int which, uint8_t *dst, size_t cap,
+                                    uint32_t *rows, uint32_t *cols) {
+    if (which < 0 || which > 3) return PM_EINVAL;
+    pm_code *c = const_cast<pm_code *>(cc);
+    SpecificOps ops;
+    int st = resolve_specific(c, nodes, &ops);
+    if (st != ST_OK) return static_cast<pm_status>(st);
+    std::lock_guard<std::mutex> lk(c->mu);
+    const Mat &F = c->specific.find(std::vector<int>(nodes, nodes + c->m.k))->second.F[which];
+    if (rows) *rows = static_cast<uint32_t>(F.rows);
+    if (cols) *cols = static_cast<uint32_t>(F.cols);
+    if (dst) {
+        if (cap < F.v.size()) return PM_EINVAL;
+        std::copy(F.v.begin(), F.v.end(), dst);
+    }
+    return PM_OK;
+}
+
+
 pm_status pm_prepare(pm_code *c, int op, uint32_t failed, const uint32_t *ids, uint32_t flags, int *specialized) {
     if (specialized) *specialized = 0;
-    if (!c || op < 0 || op > 3 || (flags & ~static_cast<uint32_t>(PM_PREPARE_BATCHED))) return PM_EINVAL;
+    if (!c || op < 0 || op > 4 || (flags & ~static_cast<uint32_t>(PM_PREPARE_BATCHED))) return PM_EINVAL;
+    if (op == 4) {   // the passes of the specific decode
+        SpecificOps ops;
+        int st = resolve_specific(c, ids, &ops);
+        if (st != ST_OK) return static_cast<pm_status>(st);
+        int all = 1;
+        for (int p = 0; p < ops.npass; ++p) {
+            std::shared_ptr<BsProgram> bp = ops.pe[p]->bitslice();
+            if (!bp) { all = 0; continue; }
+            if ((st = bs_compile(*bp, (flags & PM_PREPARE_BATCHED) ? BS_MULTI : BS_SINGLE)) != ST_OK)
+                return static_cast<pm_status>(st);
+        }
+        if (specialized) *specialized = all;
+        return PM_OK;
+    }
     Resolved r;
     int st = resolve_op(c, op, failed, ids, &r);
     if (st != ST_OK) return static_cast<pm_status>(st);

@@ -297,4 +297,85 @@ int decode_matrix(const CodeMats &c, const std::vector<int> &K, Mat &D, std::vec
     return ST_OK;
 }
 
+// The data collector of the product-matrix MSR code (Section 2: Psi =
+// [Phi, Lambda Phi], node i holds phi_i^t S1 + lambda_i phi_i^t S2), with
+// every step a matrix over blocks.  Node blocks i*alpha + a of K give
+// Z_ij = sum_a y_i[a] phi_j[a] = P_ij + lambda_i Q_ij; a pair i < j yields
+// Q_ij = c (Z_ij + Z_ji) and P_ij = Z_ij + lambda_i Q_ij with c = 1 /
+// (lambda_i + lambda_j); as lambda_i c + 1 = lambda_j c, P_ij takes
+// lambda_j c phi_j on node i's blocks and lambda_i c phi_i on node j's.
+int specific_decode_factors(const CodeMats &c, const std::vector<int> &K, Mat F[4]) {
+    if (c.kind != KIND_MSR) return ST_EUNSUPPORTED;
+    const int k = c.k, a = c.alpha, d = c.d, B = c.B;
+    if (static_cast<int>(K.size()) != k || d != 2 * a) return ST_EINVAL;
+    auto phi = [&](int i, int t) { return c.psi.at(K[i], t); };
+    auto lam = [&](int i) { return c.lambda[K[i]]; };
+    for (int i = 0; i < k; ++i)
+        for (int t = 0; t < a; ++t)
+            if (c.psi.at(K[i], a + t) != gmul(lam(i), phi(i, t))) return ST_EUNSUPPORTED;
+    const int npairs = k * (k - 1) / 2;   // = B / 2
+    std::vector<std::vector<int>> pair_of(k, std::vector<int>(k, -1));
+    Mat A(B, k * a);
+    int q = 0;
+    for (int i = 0; i < k; ++i)
+        for (int j = i + 1; j < k; ++j, ++q) {
+            const uint8_t sum = lam(i) ^ lam(j);
+            if (!sum) return ST_ESINGULAR;
+            const uint8_t cc = ginv(sum);
+            pair_of[i][j] = pair_of[j][i] = q;
+            for (int t = 0; t < a; ++t) {
+                A.at(q, i * a + t) = gmul(gmul(lam(j), cc), phi(j, t));            // P_ij
+                A.at(q, j * a + t) = gmul(gmul(lam(i), cc), phi(i, t));
+                A.at(npairs + q, i * a + t) = gmul(cc, phi(j, t));                 // Q_ij
+                A.at(npairs + q, j * a + t) = gmul(cc, phi(i, t));
+            }
+        }
+    // phi_i^t S1 from the alpha values P_ij (j != i, increasing j): rows
+    // phi_j^t of the system, solved by its inverse
+    Mat Bm(2 * a * a, B);
+    for (int i = 0; i < a; ++i) {
+        Mat Fi(a, a), Fi_inv;
+        std::vector<int> js;
+        for (int j = 0; j < k; ++j)
+            if (j != i) js.push_back(j);
+        for (int r = 0; r < a; ++r)
+            for (int t = 0; t < a; ++t) Fi.at(r, t) = phi(js[r], t);
+        if (!invert(Fi, Fi_inv)) return ST_ESINGULAR;
+        for (int b = 0; b < a; ++b)
+            for (int r = 0; r < a; ++r) {
+                const int qp = pair_of[i][js[r]];
+                Bm.at(i * a + b, qp) = Fi_inv.at(b, r);                    // U[i][b] from P
+                Bm.at(a * a + i * a + b, npairs + qp) = Fi_inv.at(b, r);   // V[i][b] from Q
+            }
+    }
+    // S1 = inverse(Phi_A) U, S2 = inverse(Phi_A) V; message symbol L[l][j]
+    Mat PhiA(a, a), PhiA_inv;
+    for (int i = 0; i < a; ++i)
+        for (int t = 0; t < a; ++t) PhiA.at(i, t) = phi(i, t);
+    if (!invert(PhiA, PhiA_inv)) return ST_ESINGULAR;
+    Mat Cm(B, 2 * a * a);
+    std::vector<char> done(B, 0);
+    for (int l = 0; l < d; ++l)
+        for (int j = 0; j < a; ++j) {
+            const int msym = c.L[l * a + j];
+            if (msym < 0 || done[msym]) continue;
+            done[msym] = 1;
+            const int half = l < a ? 0 : 1, row = l % a;
+            for (int i = 0; i < a; ++i) Cm.at(msym, half * a * a + i * a + j) = PhiA_inv.at(row, i);
+        }
+    for (int m = 0; m < B; ++m)
+        if (!done[m]) return ST_EINVAL;
+    F[0] = std::move(A);
+    F[1] = std::move(Bm);
+    F[2] = std::move(Cm);
+    if (c.systematic) {
+        Mat Gt(B, B);   // the first B rows of the linearized generator
+        std::copy(c.G.v.begin(), c.G.v.begin() + static_cast<long>(B) * B, Gt.v.begin());
+        F[3] = std::move(Gt);
+    } else {
+        F[3] = Mat();
+    }
+    return ST_OK;
+}
+
 }  // namespace pmrc

@@ -22,6 +22,7 @@ PM_MSR, PM_MBR, PM_RS = 0, 1, 2
 PM_VANILLA, PM_SPARSE = 0, 1
 MAT_PSI, MAT_LAMBDA, MAT_G, MAT_GSYS, MAT_ENC = 0, 1, 2, 3, 4
 OP_ENCODE, OP_HELPER, OP_NEWCOMER, OP_DECODE, OP_APPLY = 0, 1, 2, 3, 4
+OP_DECODE_SPECIFIC = 4   # pm_prepare only: the passes of pm_decode_specific
 
 
 class PMError(RuntimeError):
@@ -74,6 +75,9 @@ def _lib():
         L.pm_set_variant.argtypes = [vp, i32, u32, u32]
         L.pm_autotune_encode.argtypes = [vp, vp, sz, vp, sz, sz, u32, vp, u32p, u32p]
         L.pm_prepare.argtypes = [vp, i32, u32, u32p, u32, ctypes.POINTER(ctypes.c_int)]
+        L.pm_decode_specific_workspace.argtypes = [vp, sz, ctypes.POINTER(ctypes.c_size_t)]
+        L.pm_decode_specific.argtypes = [vp, u32p, vp, sz, vp, sz, sz, vp, sz, vp]
+        L.pm_decode_specific_factor.argtypes = [vp, u32p, i32, vp, sz, u32p, u32p]
         L.pm_batch_plan.argtypes = [ctypes.POINTER(pm_batch_item), sz, u32, ctypes.POINTER(vp)]
         L.pm_batch_set_variant.argtypes = [vp, u32, u32]
         L.pm_batch_autotune.argtypes = [vp, u32, vp, u32p]
@@ -165,6 +169,17 @@ def pm_prepare(h, op, failed=0, ids=None, flags=0):
     spec = ctypes.c_int()
     st = _lib().pm_prepare(h, op, failed, _u32arr(ids) if ids is not None else None, flags, ctypes.byref(spec))
     return st, spec.value
+
+
+def pm_decode_specific_workspace(h, block_bytes):
+    n = ctypes.c_size_t()
+    _check(_lib().pm_decode_specific_workspace(h, block_bytes, ctypes.byref(n)), "pm_decode_specific_workspace")
+    return n.value
+
+
+def pm_decode_specific(h, nodes, y_ptr, y_ld, x_ptr, x_ld, block_bytes, ws_ptr, ws_bytes, stream=0):
+    return _lib().pm_decode_specific(h, _u32arr(nodes), y_ptr, y_ld, x_ptr, x_ld, block_bytes, ws_ptr, ws_bytes,
+                                     stream or None)
 
 
 def pm_autotune_encode(h, x_ptr, x_ld, out_ptr, out_ld, block_bytes, reps=5, stream=0):
@@ -261,6 +276,31 @@ class Code:
         op, old = _regions(out, orows)
         _check(pm_repair_newcomer(self.h, failed, helpers, rp, rld, op, old, block_bytes, _stream_handle(stream)),
                "pm_repair_newcomer")
+
+    def specific_factor(self, nodes, which):
+        """Factor `which` (0..3) of the specific decode for nodes, as a numpy matrix."""
+        import numpy as np
+        r, c = ctypes.c_uint32(), ctypes.c_uint32()
+        _check(_lib().pm_decode_specific_factor(self.h, _u32arr(nodes), which, None, 0, ctypes.byref(r),
+                                                ctypes.byref(c)), "pm_decode_specific_factor")
+        m = np.zeros((r.value, c.value), np.uint8)
+        if m.size:
+            _check(_lib().pm_decode_specific_factor(self.h, _u32arr(nodes), which, m.ctypes.data, m.size, None, None),
+                   "pm_decode_specific_factor")
+        return m
+
+    def decode_specific(self, nodes, Y, X, block_bytes, workspace=None, stream=None):
+        """Specific PM-MSR decode; workspace: a device uint8 tensor of at least
+        pm_decode_specific_workspace bytes (allocated here when None)."""
+        import torch
+        yp, yld = _regions(Y, self.k * self.alpha)
+        xp, xld = _regions(X, self.B)
+        need = pm_decode_specific_workspace(self.h, block_bytes)
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=Y.device)
+        _check(pm_decode_specific(self.h, nodes, yp, yld, xp, xld, block_bytes, workspace.data_ptr(),
+                                  workspace.numel(), _stream_handle(stream)), "pm_decode_specific")
+        return workspace
 
     def decode(self, nodes, Y, X, block_bytes, stream=None):
         yp, yld = _regions(Y, len(nodes) * self.alpha)

@@ -48,6 +48,25 @@ def generated_source(code, op, failed=0, ids=None, workdir=None):
     return path
 
 
+def generated_apply_source(A, workdir=None):
+    """The single-set source of pm_apply's kernel for the matrix A (rows x
+    cols, uint8), or None if the matrix is not specialized."""
+    A = np.ascontiguousarray(A, dtype=np.uint8)
+    path = os.path.join(workdir or tempfile.mkdtemp(), "apply.hip")
+    os.environ["PMRC_BS_DUMP"] = path
+    try:
+        pm.pm_set_variant(None, pm.OP_APPLY, 8, 32)
+        s, base = 4096, 1 << 20
+        st = pm.pm_apply(A, base, s, base + (A.shape[1] + 1) * s * 2, s, s)
+    finally:
+        del os.environ["PMRC_BS_DUMP"]
+        pm.pm_set_variant(None, pm.OP_APPLY, 0, 0)
+    if not os.path.exists(path):
+        return None
+    assert st == pm.PM_EHIP, st
+    return path
+
+
 def build(source, multi, sanitize=True):
     """Compile one generated source for the host; returns the executable."""
     src = source + (".multi" if multi else "")

@@ -57,3 +57,27 @@ def test_generated_kernels_match_oracle_on_host(tmp_path, name, kw, ok, f, H, K,
                 outs = E.run(exe, P, [u for u, _ in use], high=high)
                 for got, (_, want) in zip(outs, use):
                     assert np.array_equal(got, want), (name, op, multi, P, high)
+
+
+@pytest.mark.parametrize("kw,K", [(dict(k=8, d=14, n=16), list(range(8, 16))),
+                                  (dict(k=6, d=10, n=12, systematic=False), [0, 2, 4, 6, 8, 10])],
+                         ids=["msr8-sys", "msr6-nonsys"])
+def test_specific_decode_factor_kernels_on_host(tmp_path, kw, K):
+    """The generated kernels of the specific decode's factor matrices (pair
+    solves: 2 alpha nonzeros a row; alpha x alpha solves; message symbols;
+    systematic re-encoding) against the oracle's product, on the host."""
+    c = pm.Code(**kw)
+    for w in range(4):
+        F = c.specific_factor(K, w)
+        if F.shape[0] == 0:
+            continue
+        src = E.generated_apply_source(F, workdir=str(tmp_path))
+        assert src is not None, w
+        s = 2048 + 77
+        X = synth.random_bytes(900 + w, F.shape[1] * s).reshape(F.shape[1], s)
+        want = O.apply(F, X, nthreads=4)
+        ld = (s + 15) // 16 * 16 + 16
+        for sanitize, high in ((True, False), (False, True)):
+            exe = E.build(src, False, sanitize=sanitize)
+            got, = E.run(exe, 5, [(X, ld, F.shape[0], ld, s)], high=high)
+            assert np.array_equal(got, want), (w, high)

@@ -162,3 +162,59 @@ def test_prepare_argument_errors(op, failed, ids):
     c = pm.Code(k=4, d=6, n=8)
     st, spec = pm.pm_prepare(c.h, op, failed, ids)
     assert st == pm.PM_EINVAL and spec == 0
+
+
+# ---------------------------------------------------- specific PM-MSR decode --
+SPECIFIC = [
+    (dict(k=3, d=4, n=6, construction=pm.PM_VANILLA, x=list(range(1, 7))), (O.MSR, 3, 4, 6, O.VANILLA), [3, 4, 5]),
+    (dict(k=4, d=6, n=8), (O.MSR, 4, 6, 8, O.SPARSE), [7, 2, 5, 0]),
+    (dict(k=4, d=6, n=8, systematic=False), (O.MSR, 4, 6, 8, O.SPARSE), [1, 3, 6, 4]),
+    (dict(k=8, d=14, n=16), (O.MSR, 8, 14, 16, O.SPARSE), list(range(8, 16))),
+    (dict(k=16, d=30, n=32), (O.MSR, 16, 30, 32, O.SPARSE), list(range(16, 32))),
+]
+
+
+@pytest.mark.parametrize("kw,ok,K", SPECIFIC, ids=lambda v: None)
+def test_specific_decode_factors_multiply_to_the_decode_matrix(kw, ok, K):
+    """The library's four sparse factors of the specific decode, multiplied
+    with the oracle's field arithmetic, give exactly the oracle's linearized
+    decode matrix for the same nodes (every MSR node set uses all k alpha
+    received blocks)."""
+    c = pm.Code(**kw)
+    o = O.Code(*ok[:4], ok[4], kw.get("systematic", True), x=np.array(kw["x"]) if "x" in kw else None)
+    F = [c.specific_factor(K, w) for w in range(4)]
+    a, B = c.alpha, c.B
+    assert F[0].shape == (B, c.k * a) and F[1].shape == (2 * a * a, B) and F[2].shape == (B, 2 * a * a)
+    # pass A reads two nodes per output block: at most 2 alpha nonzeros a row
+    assert (np.count_nonzero(F[0], axis=1) <= 2 * a).all()
+    prod = O.matmul(F[1], F[0])
+    prod = O.matmul(F[2], prod)
+    if kw.get("systematic", True):
+        assert F[3].shape == (B, B)
+        prod = O.matmul(F[3], prod)
+    else:
+        assert F[3].shape[0] == 0
+    D, kept = o.decode_matrix(K)
+    assert list(kept) == list(range(c.k * a))
+    assert np.array_equal(prod, D)
+
+
+def test_specific_decode_refusals():
+    assert pm.Code(k=8, d=14, n=16, kind=pm.PM_MBR).h
+    L = pm.lib()
+    for kw in (dict(k=8, d=14, n=16, kind=pm.PM_MBR), dict(k=8, d=8, n=16, kind=pm.PM_RS)):
+        c = pm.Code(**kw)
+        n = ctypes.c_size_t()
+        assert L.pm_decode_specific_workspace(c.h, 4096, ctypes.byref(n)) == pm.PM_EUNSUPPORTED
+    c = pm.Code(k=4, d=6, n=8)
+    bad = (ctypes.c_uint32 * 4)(0, 1, 1, 2)
+    assert L.pm_decode_specific_factor(c.h, bad, 0, None, 0, None, None) == pm.PM_EINVAL
+    good = (ctypes.c_uint32 * 4)(0, 1, 2, 3)
+    assert L.pm_decode_specific_factor(c.h, good, 4, None, 0, None, None) == pm.PM_EINVAL
+    n = ctypes.c_size_t()
+    assert L.pm_decode_specific_workspace(c.h, 100, ctypes.byref(n)) == pm.PM_OK
+    assert n.value == (c.B + 2 * c.alpha ** 2 + c.B) * 112
+    # workspace too small: refused before any GPU work
+    st = L.pm_decode_specific(c.h, good, ctypes.c_void_p(1 << 20), 112, ctypes.c_void_p(1 << 22), 112, 100,
+                              ctypes.c_void_p(1 << 24), n.value - 16, None)
+    assert st == pm.PM_EINVAL
