@@ -263,6 +263,47 @@ def msr_repair_decode(torch, pm, synth, steps, warmup):
     return out
 
 
+def msr16_decode_case(torch, pm, synth, steps, warmup):
+    """PM-MSR (16,30,32) sparse, 64 MiB object, decoded from the 16 parity
+    nodes (every data block lost): the linearized decode (dense 240 x 240
+    inverse) against the specific decode (pm_decode_specific, after
+    pm_prepare op 4 compiled its passes; that init time is reported apart)."""
+    dev = torch.device("cuda:0")
+    code = pm.Code(k=16, d=30, n=32)
+    S = 64 << 20
+    X, s = synth.split_object(S, code.B, synth.CONFIG_SEED + 6)
+    ld = (s + 15) // 16 * 16
+    x = torch.zeros((code.B, ld), dtype=torch.uint8, device=dev)
+    x[:, :s] = torch.from_numpy(X).to(dev)
+    P = torch.empty((code.enc_rows, ld), dtype=torch.uint8, device=dev)
+    code.encode(x, P, s)
+    nm = code.node_map()
+    K = list(range(16, 32))
+    Y = torch.stack([x[v] if v < code.B else P[v - code.B] for i in K for v in nm[i * code.alpha:(i + 1) * code.alpha]])
+    Y = Y.contiguous()
+    stream = torch.cuda.current_stream().cuda_stream
+    out = {}
+    xl = torch.empty_like(x)
+    n = max(5, steps // 10)
+    wall, _ = Timer(torch).run(lambda i: pm.pm_decode(code.h, K, Y.data_ptr(), ld, xl.data_ptr(), ld, s, stream),
+                               n, 2)
+    out["msr16_decode_linear_gbps"] = S * n / wall / 1e9
+    t0 = time.perf_counter()
+    ready = code.prepare(pm.OP_DECODE_SPECIFIC, ids=K)
+    out["msr16_specific_init_s"] = time.perf_counter() - t0
+    out["msr16_specific_all_passes_bitsliced"] = bool(ready)
+    ws_bytes = pm.pm_decode_specific_workspace(code.h, s)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    xs = torch.empty_like(x)
+    wall, _ = Timer(torch).run(lambda i: pm.pm_decode_specific(code.h, K, Y.data_ptr(), ld, xs.data_ptr(), ld, s,
+                                                               ws.data_ptr(), ws_bytes, stream), n, 2)
+    out["msr16_decode_specific_gbps"] = S * n / wall / 1e9
+    torch.cuda.synchronize()
+    out["msr16_decode_results_equal"] = bool(torch.equal(xs[:, :s], xl[:, :s]) and torch.equal(xs[:, :s], x[:, :s]))
+    del x, P, Y, xl, xs, ws
+    return out
+
+
 def batched_case(torch, pm, synth, steps):
     """Configuration 4: 4096 objects, sizes log-uniform 64 KiB - 16 MiB,
     sparse PM-MSR (4,6), (8,14), (16,30), n = 2k, all encoded by one
@@ -448,6 +489,8 @@ def main():
                       for k, v in msr_repair_decode(torch, pm, synth, args.steps, args.warmup).items()})
         extra.update({k: (round(v, 2) if isinstance(v, float) else v)
                       for k, v in mbr_cases(torch, pm, synth, args.steps, args.warmup).items()})
+        extra.update({k: (round(v, 2) if isinstance(v, float) else v)
+                      for k, v in msr16_decode_case(torch, pm, synth, args.steps, args.warmup).items()})
     batched = served = None
     if not args.no_batch:
         batched = batched_case(torch, pm, synth, max(5, args.steps // 20))

@@ -296,17 +296,25 @@ void emit_byte_tail(std::ostringstream &o, int gi, const Grp &G) {
       << "    out[(u64)tr" << gi << "[r] * old + pos] = (unsigned char)acc;\n  }\n}\n";
 }
 
+// Straight-line operations per lane chunk: per emitted column (nonzero
+// somewhere in the group) its transpose, combinations and one three-input XOR
+// per row plane; per row the output transpose.
 long estimate_ops(const std::vector<Grp> &gs) {
     long ops = 0;
     for (const Grp &G : gs) {
         if (G.kind == GROUP_COPY) continue;
-        ops += static_cast<long>(G.cols.size()) * (60 + 24 + 8 * static_cast<long>(G.rows.size()));
+        long cols = 0;
+        for (size_t ci = 0; ci < G.cols.size(); ++ci) {
+            bool any = false;
+            for (size_t r = 0; r < G.rows.size(); ++r) any |= G.coef[r][ci] != 0;
+            cols += any;
+        }
+        ops += cols * (60 + 24 + 8 * static_cast<long>(G.rows.size()));
         ops += 60 * static_cast<long>(G.rows.size());
     }
     return ops;
 }
 
-std::string thread_log;
 
 }  // namespace
 

@@ -224,8 +224,8 @@ struct pm_code {
     std::map<std::vector<int>, std::pair<Mat, std::vector<int>>> decode_mat;
     // specific PM-MSR decode per node list: its factors and their programs
     struct Specific {
-        Mat F[4];
-        std::map<int, std::unique_ptr<ProgEntry>> progs[4];   // by rg
+        Mat F[kSpecificPasses];
+        std::map<int, std::unique_ptr<ProgEntry>> progs[kSpecificPasses];   // by rg
     };
     std::map<std::vector<int>, Specific> specific;
 };
@@ -353,11 +353,12 @@ int resolve_op(pm_code *c, int op, uint32_t failed, const uint32_t *ids, Resolve
 namespace {
 
 // The specific decode of node list ids: factors (built once) and the
-// program of each pass.  npass = 3 for non-systematic codes, else 4.
+// program of each pass.  npass = kSpecificPasses - 1 for non-systematic
+// codes (no re-encoding), else kSpecificPasses.
 struct SpecificOps {
-    ProgEntry *pe[4] = {nullptr, nullptr, nullptr, nullptr};
+    ProgEntry *pe[kSpecificPasses] = {};
     int npass = 0;
-    int rows[4] = {0, 0, 0, 0};
+    int rows[kSpecificPasses] = {};
 };
 
 int resolve_specific(pm_code *c, const uint32_t *ids, SpecificOps *out) {
@@ -379,7 +380,7 @@ int resolve_specific(pm_code *c, const uint32_t *ids, SpecificOps *out) {
         it = c->specific.emplace(list, std::move(sp)).first;
     }
     pm_code::Specific &sp = it->second;
-    out->npass = sp.F[3].rows ? 4 : 3;
+    out->npass = sp.F[kSpecificPasses - 1].rows ? kSpecificPasses : kSpecificPasses - 1;
     for (int p = 0; p < out->npass; ++p) {
         const Mat &F = sp.F[p];
         const int rg = pick_rg_cached(c->var[3], F);
@@ -397,10 +398,12 @@ int resolve_specific(pm_code *c, const uint32_t *ids, SpecificOps *out) {
     return ST_OK;
 }
 
-// Workspace blocks of a specific decode: pass A's B outputs, pass B's
-// 2 alpha^2, and for systematic codes the B message symbols.
+// Workspace blocks of a specific decode: the outputs of every pass but the
+// last, back to back (Z: k(k-1), pairs: B, phi_i^t S: 2 alpha^2, and for
+// systematic codes the B message symbols).
 size_t specific_ws_blocks(const CodeMats &m) {
-    return static_cast<size_t>(m.B) + 2u * static_cast<size_t>(m.alpha) * m.alpha + (m.systematic ? m.B : 0);
+    return static_cast<size_t>(m.k) * (m.k - 1) + static_cast<size_t>(m.B) +
+           2u * static_cast<size_t>(m.alpha) * m.alpha + (m.systematic ? m.B : 0);
 }
 
 }  // namespace
@@ -538,24 +541,28 @@ pm_status pm_decode_specific(const pm_code *cc, const uint32_t *nodes, const uin
     if (!clear(Y, y_ld, static_cast<size_t>(m.k) * m.alpha) || !clear(X, x_ld, static_cast<size_t>(m.B)))
         return PM_EINVAL;
     hipStream_t h = reinterpret_cast<hipStream_t>(stream);
-    uint8_t *w1p = workspace, *w2p = w1p + static_cast<size_t>(ops.rows[0]) * ld;
-    uint8_t *zp = w2p + static_cast<size_t>(ops.rows[1]) * ld;
-    const size_t ka = static_cast<size_t>(m.k) * m.alpha;
-    if ((st = launch_program(*ops.pe[0], kVecAuto, Y, y_ld, ka, w1p, ld, ops.rows[0], s, h)) != ST_OK)
-        return static_cast<pm_status>(st);
-    if ((st = launch_program(*ops.pe[1], kVecAuto, w1p, ld, ops.rows[0], w2p, ld, ops.rows[1], s, h)) != ST_OK)
-        return static_cast<pm_status>(st);
-    if (ops.npass == 3)
-        return static_cast<pm_status>(
-            launch_program(*ops.pe[2], kVecAuto, w2p, ld, ops.rows[1], X, x_ld, ops.rows[2], s, h));
-    if ((st = launch_program(*ops.pe[2], kVecAuto, w2p, ld, ops.rows[1], zp, ld, ops.rows[2], s, h)) != ST_OK)
-        return static_cast<pm_status>(st);
-    return static_cast<pm_status>(launch_program(*ops.pe[3], kVecAuto, zp, ld, ops.rows[2], X, x_ld, ops.rows[3], s, h));
+    // pass p reads the previous pass's output (the node blocks for p = 0) and
+    // writes the next workspace slice (X for the last pass)
+    const uint8_t *in = Y;
+    size_t in_ld = y_ld, in_n = static_cast<size_t>(m.k) * m.alpha;
+    uint8_t *slice = workspace;
+    for (int p = 0; p < ops.npass; ++p) {
+        const bool last = p == ops.npass - 1;
+        uint8_t *out = last ? X : slice;
+        const size_t out_ld = last ? x_ld : ld;
+        if ((st = launch_program(*ops.pe[p], kVecAuto, in, in_ld, in_n, out, out_ld, ops.rows[p], s, h)) != ST_OK)
+            return static_cast<pm_status>(st);
+        in = out;
+        in_ld = out_ld;
+        in_n = static_cast<size_t>(ops.rows[p]);
+        slice += static_cast<size_t>(ops.rows[p]) * ld;
+    }
+    return PM_OK;
 }
 
 pm_status pm_decode_specific_factor(const pm_code *cc, const uint32_t *nodes, int which, uint8_t *dst, size_t cap,
                                     uint32_t *rows, uint32_t *cols) {
-    if (which < 0 || which > 3) return PM_EINVAL;
+    if (which < 0 || which >= kSpecificPasses) return PM_EINVAL;
     pm_code *c = const_cast<pm_code *>(cc);
     SpecificOps ops;
     int st = resolve_specific(c, nodes, &ops);

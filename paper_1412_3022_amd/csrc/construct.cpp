@@ -302,9 +302,9 @@ int decode_matrix(const CodeMats &c, const std::vector<int> &K, Mat &D, std::vec
 // every step a matrix over blocks.  Node blocks i*alpha + a of K give
 // Z_ij = sum_a y_i[a] phi_j[a] = P_ij + lambda_i Q_ij; a pair i < j yields
 // Q_ij = c (Z_ij + Z_ji) and P_ij = Z_ij + lambda_i Q_ij with c = 1 /
-// (lambda_i + lambda_j); as lambda_i c + 1 = lambda_j c, P_ij takes
-// lambda_j c phi_j on node i's blocks and lambda_i c phi_i on node j's.
-int specific_decode_factors(const CodeMats &c, const std::vector<int> &K, Mat F[4]) {
+// (lambda_i + lambda_j); as lambda_i c + 1 = lambda_j c, P_ij = lambda_j c
+// Z_ij + lambda_i c Z_ji.
+int specific_decode_factors(const CodeMats &c, const std::vector<int> &K, Mat F[kSpecificPasses]) {
     if (c.kind != KIND_MSR) return ST_EUNSUPPORTED;
     const int k = c.k, a = c.alpha, d = c.d, B = c.B;
     if (static_cast<int>(K.size()) != k || d != 2 * a) return ST_EINVAL;
@@ -314,8 +314,18 @@ int specific_decode_factors(const CodeMats &c, const std::vector<int> &K, Mat F[
         for (int t = 0; t < a; ++t)
             if (c.psi.at(K[i], a + t) != gmul(lam(i), phi(i, t))) return ST_EUNSUPPORTED;
     const int npairs = k * (k - 1) / 2;   // = B / 2
-    std::vector<std::vector<int>> pair_of(k, std::vector<int>(k, -1));
-    Mat A(B, k * a);
+    // Z_ij for i != j, rows i-major: row zrow[i][j]
+    std::vector<std::vector<int>> zrow(k, std::vector<int>(k, -1)), pair_of(k, std::vector<int>(k, -1));
+    Mat Zm(k * (k - 1), k * a);
+    int zr = 0;
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) {
+            if (j == i) continue;
+            zrow[i][j] = zr;
+            for (int t = 0; t < a; ++t) Zm.at(zr, i * a + t) = phi(j, t);
+            ++zr;
+        }
+    Mat A(B, k * (k - 1));
     int q = 0;
     for (int i = 0; i < k; ++i)
         for (int j = i + 1; j < k; ++j, ++q) {
@@ -323,12 +333,10 @@ int specific_decode_factors(const CodeMats &c, const std::vector<int> &K, Mat F[
             if (!sum) return ST_ESINGULAR;
             const uint8_t cc = ginv(sum);
             pair_of[i][j] = pair_of[j][i] = q;
-            for (int t = 0; t < a; ++t) {
-                A.at(q, i * a + t) = gmul(gmul(lam(j), cc), phi(j, t));            // P_ij
-                A.at(q, j * a + t) = gmul(gmul(lam(i), cc), phi(i, t));
-                A.at(npairs + q, i * a + t) = gmul(cc, phi(j, t));                 // Q_ij
-                A.at(npairs + q, j * a + t) = gmul(cc, phi(i, t));
-            }
+            A.at(q, zrow[i][j]) = gmul(lam(j), cc);            // P_ij
+            A.at(q, zrow[j][i]) = gmul(lam(i), cc);
+            A.at(npairs + q, zrow[i][j]) = cc;                 // Q_ij
+            A.at(npairs + q, zrow[j][i]) = cc;
         }
     // phi_i^t S1 from the alpha values P_ij (j != i, increasing j): rows
     // phi_j^t of the system, solved by its inverse
@@ -365,15 +373,16 @@ int specific_decode_factors(const CodeMats &c, const std::vector<int> &K, Mat F[
         }
     for (int m = 0; m < B; ++m)
         if (!done[m]) return ST_EINVAL;
-    F[0] = std::move(A);
-    F[1] = std::move(Bm);
-    F[2] = std::move(Cm);
+    F[0] = std::move(Zm);
+    F[1] = std::move(A);
+    F[2] = std::move(Bm);
+    F[3] = std::move(Cm);
     if (c.systematic) {
         Mat Gt(B, B);   // the first B rows of the linearized generator
         std::copy(c.G.v.begin(), c.G.v.begin() + static_cast<long>(B) * B, Gt.v.begin());
-        F[3] = std::move(Gt);
+        F[4] = std::move(Gt);
     } else {
-        F[3] = Mat();
+        F[4] = Mat();
     }
     return ST_OK;
 }

@@ -46,16 +46,19 @@ int newcomer_matrix(const CodeMats &c, int failed, const std::vector<int> &helpe
 // Decode from nodes K: D (B x B) and the received block indices it reads.
 int decode_matrix(const CodeMats &c, const std::vector<int> &nodes, Mat &D, std::vector<int> &used);
 
-// Specific PM-MSR decoding from the k nodes K, as four sparse factors whose
+// Specific PM-MSR decoding from the k nodes K, as five sparse factors whose
 // product is the linearized decode matrix:
-//   F[0] (B x k alpha): P_ij and Q_ij of every node pair i < j (pairs in
-//        order, all P rows then all Q rows) from the two nodes' blocks;
-//   F[1] (2 alpha^2 x B): phi_i^t S1 and phi_i^t S2 for the first alpha
+//   F[0] (k(k-1) x k alpha): Z_ij = y_i . phi_j for i != j, from node i's
+//        blocks only (rows i-major);
+//   F[1] (B x k(k-1)): P_ij and Q_ij of every node pair i < j (pairs in
+//        order, all P rows then all Q rows) from Z_ij and Z_ji;
+//   F[2] (2 alpha^2 x B): phi_i^t S1 and phi_i^t S2 for the first alpha
 //        nodes of K (alpha x alpha solves);
-//   F[2] (B x 2 alpha^2): the message symbols, S1 = inverse(Phi_A) U and
+//   F[3] (B x 2 alpha^2): the message symbols, S1 = inverse(Phi_A) U and
 //        S2 = inverse(Phi_A) V;
-//   F[3] (B x B): systematic codes only, X = G~ Z (rows 0 otherwise).
+//   F[4] (B x B): systematic codes only, X = G~ Z (rows 0 otherwise).
 // ST_EUNSUPPORTED for MBR / RS, ST_ESINGULAR for a singular system.
-int specific_decode_factors(const CodeMats &c, const std::vector<int> &K, Mat F[4]);
+constexpr int kSpecificPasses = 5;
+int specific_decode_factors(const CodeMats &c, const std::vector<int> &K, Mat F[kSpecificPasses]);
 
 }  // namespace pmrc

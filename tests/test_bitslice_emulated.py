@@ -63,11 +63,11 @@ def test_generated_kernels_match_oracle_on_host(tmp_path, name, kw, ok, f, H, K,
                                   (dict(k=6, d=10, n=12, systematic=False), [0, 2, 4, 6, 8, 10])],
                          ids=["msr8-sys", "msr6-nonsys"])
 def test_specific_decode_factor_kernels_on_host(tmp_path, kw, K):
-    """The generated kernels of the specific decode's factor matrices (pair
-    solves: 2 alpha nonzeros a row; alpha x alpha solves; message symbols;
+    """The generated kernels of the specific decode's factor matrices (node
+    times phi products, pair solves, alpha x alpha solves, message symbols,
     systematic re-encoding) against the oracle's product, on the host."""
     c = pm.Code(**kw)
-    for w in range(4):
+    for w in range(5):
         F = c.specific_factor(K, w)
         if F.shape[0] == 0:
             continue

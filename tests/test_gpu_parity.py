@@ -363,15 +363,16 @@ def _specific_oracle(kw):
 @pytest.mark.parametrize("name,kw,K", SPECIFIC_CASES, ids=[c[0] for c in SPECIFIC_CASES])
 @pytest.mark.parametrize("prepared", [False, True], ids=["table", "bitsliced"])
 def test_specific_decode_matches_oracle(name, kw, K, prepared):
-    """pm_decode_specific (pair solves, alpha x alpha solves, message symbols,
-    systematic re-encoding, each a region product) returns the object, on
+    """pm_decode_specific (node times phi products, pair solves, alpha x alpha
+    solves, message symbols, systematic re-encoding, each a region product)
+    returns the object, on
     the table kernels and after pm_prepare on the bit-sliced ones; ragged
     block lengths, guard bytes checked."""
     print("specific decode %s prepared=%s" % (name, prepared), flush=True)
     c = pm.Code(**kw)
     o = _specific_oracle(kw)
     if prepared:
-        assert c.prepare(pm.OP_DECODE_SPECIFIC, ids=K) is True
+        assert c.prepare(pm.OP_DECODE_SPECIFIC, ids=K) is True   # every pass specialized
     for s in (100, 2048 + 19, 3 * 2048 + 16):
         X = _rand(s + 3 * len(K), c.B, s)
         P = o.encode(X, nthreads=8)

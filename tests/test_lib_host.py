@@ -176,26 +176,29 @@ SPECIFIC = [
 
 @pytest.mark.parametrize("kw,ok,K", SPECIFIC, ids=lambda v: None)
 def test_specific_decode_factors_multiply_to_the_decode_matrix(kw, ok, K):
-    """The library's four sparse factors of the specific decode, multiplied
+    """The library's five sparse factors of the specific decode, multiplied
     with the oracle's field arithmetic, give exactly the oracle's linearized
     decode matrix for the same nodes (every MSR node set uses all k alpha
     received blocks)."""
     c = pm.Code(**kw)
     o = O.Code(*ok[:4], ok[4], kw.get("systematic", True), x=np.array(kw["x"]) if "x" in kw else None)
-    F = [c.specific_factor(K, w) for w in range(4)]
-    a, B = c.alpha, c.B
-    assert F[0].shape == (B, c.k * a) and F[1].shape == (2 * a * a, B) and F[2].shape == (B, 2 * a * a)
-    # pass A reads two nodes per output block: at most 2 alpha nonzeros a row
-    assert (np.count_nonzero(F[0], axis=1) <= 2 * a).all()
-    prod = O.matmul(F[1], F[0])
-    prod = O.matmul(F[2], prod)
+    F = [c.specific_factor(K, w) for w in range(5)]
+    k, a, B = c.k, c.alpha, c.B
+    assert F[0].shape == (k * (k - 1), k * a) and F[1].shape == (B, k * (k - 1))
+    assert F[2].shape == (2 * a * a, B) and F[3].shape == (B, 2 * a * a)
+    # pass 0 reads one node per output block, pass 1 two blocks per output
+    assert (np.count_nonzero(F[0], axis=1) <= a).all()
+    assert (np.count_nonzero(F[1], axis=1) == 2).all()
+    prod = F[0]
+    for w in (1, 2, 3):
+        prod = O.matmul(F[w], prod)
     if kw.get("systematic", True):
-        assert F[3].shape == (B, B)
-        prod = O.matmul(F[3], prod)
+        assert F[4].shape == (B, B)
+        prod = O.matmul(F[4], prod)
     else:
-        assert F[3].shape[0] == 0
+        assert F[4].shape[0] == 0
     D, kept = o.decode_matrix(K)
-    assert list(kept) == list(range(c.k * a))
+    assert list(kept) == list(range(k * a))
     assert np.array_equal(prod, D)
 
 
@@ -210,10 +213,10 @@ def test_specific_decode_refusals():
     bad = (ctypes.c_uint32 * 4)(0, 1, 1, 2)
     assert L.pm_decode_specific_factor(c.h, bad, 0, None, 0, None, None) == pm.PM_EINVAL
     good = (ctypes.c_uint32 * 4)(0, 1, 2, 3)
-    assert L.pm_decode_specific_factor(c.h, good, 4, None, 0, None, None) == pm.PM_EINVAL
+    assert L.pm_decode_specific_factor(c.h, good, 5, None, 0, None, None) == pm.PM_EINVAL
     n = ctypes.c_size_t()
     assert L.pm_decode_specific_workspace(c.h, 100, ctypes.byref(n)) == pm.PM_OK
-    assert n.value == (c.B + 2 * c.alpha ** 2 + c.B) * 112
+    assert n.value == (c.k * (c.k - 1) + c.B + 2 * c.alpha ** 2 + c.B) * 112
     # workspace too small: refused before any GPU work
     st = L.pm_decode_specific(c.h, good, ctypes.c_void_p(1 << 20), 112, ctypes.c_void_p(1 << 22), 112, 100,
                               ctypes.c_void_p(1 << 24), n.value - 16, None)
