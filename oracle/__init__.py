@@ -84,6 +84,7 @@ def lib():
         L.or_decode_matrix.argtypes = [u8p, ctypes.c_int, ctypes.c_int, ip, ctypes.c_int, u8p, ip]
         L.or_msr_specific_decode.argtypes = [u8p, u8p, ip, ctypes.c_int, ctypes.c_int, ip, pp, ctypes.c_int,
                                              pp, ctypes.c_size_t]
+        L.or_mbr_specific_decode.argtypes = [u8p, ip, ctypes.c_int, ctypes.c_int, ip, pp, pp, ctypes.c_size_t]
         L.or_init()
         _lib = L
     return _lib
@@ -377,10 +378,12 @@ class Code:
         return decode_matrix(self.Gsys, self.B, self.alpha, list(K))
 
     def decode_specific(self, K, Y):
-        """The same decode by the specific PM-MSR algorithm (MSR only)."""
-        if self.kind != MSR:
-            raise ValueError("specific decoding is defined here for PM-MSR")
-        return msr_specific_decode(self.psi, self.lam, self.L, self.k, K, Y, self.Gsys is not self.G)
+        """The same decode by the specific PM-MSR or PM-MBR algorithm."""
+        if self.kind == MSR:
+            return msr_specific_decode(self.psi, self.lam, self.L, self.k, K, Y, self.Gsys is not self.G)
+        if self.kind == MBR:
+            return mbr_specific_decode(self.psi, self.L, self.k, self.d, K, Y)
+        raise ValueError("specific decoding is defined here for PM-MSR and PM-MBR")
 
     def decode(self, K, Y):
         """Y: (k alpha x s) blocks of the nodes in K, node-major."""
@@ -403,6 +406,24 @@ def msr_specific_decode(psi, lam, L, k, K, Y, systematic_form=True):
                                       1 if systematic_form else 0, _ptrs(list(X)), s)
     if rc == -2:
         raise ValueError("Psi is not of the form [Phi, Lambda Phi]")
+    return None if rc != 0 else X
+
+
+def mbr_specific_decode(psi, L, k, d, K, Y):
+    """Specific PM-MBR decoding from the k nodes K (their k d blocks Y,
+    node-major); returns the B data blocks, or None if singular."""
+    K = list(K)
+    if len(K) != k:
+        raise ValueError("K must list k nodes")
+    Y = np.ascontiguousarray(Y, dtype=np.uint8)
+    if Y.shape[0] != k * d:
+        raise ValueError("Y must hold k d blocks")
+    s = Y.shape[1]
+    B = k * d - k * (k - 1) // 2
+    X = np.zeros((B, s), np.uint8)
+    rc = lib().or_mbr_specific_decode(_u8(np.ascontiguousarray(psi, dtype=np.uint8)),
+                                      _i32(np.ascontiguousarray(L, dtype=np.int32)), k, d,
+                                      _i32(np.array(K, dtype=np.int32)), _ptrs(list(Y)), _ptrs(list(X)), s)
     return None if rc != 0 else X
 
 

@@ -619,6 +619,57 @@ int or_msr_specific_decode(const uint8_t *psi, const uint8_t *lam, const int *L,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Specific PM-MBR decoding: the data-collector algorithm of the seminal
+ * product-matrix paper for MBR, which the paper's Section 2 refers to and
+ * whose cost its MBR subsection of Section 4 (decoding paragraph) compares
+ * with the linearized decode.  Reading (the paper does not restate the
+ * steps; they follow from the MBR structure: M = [[S, T], [T^t, 0]] with S
+ * symmetric k x k and T k x (d-k), Psi = [Phi, Delta] with Phi n x k and
+ * Delta n x (d-k), node i storing psi_i^t M):
+ *  1. the k connected nodes hold Psi_DC M = [Phi_DC S + Delta_DC T^t,
+ *     Phi_DC T], so T = inverse(Phi_DC) times their last d-k blocks;
+ *  2. S = inverse(Phi_DC) (their first k blocks + Delta_DC T^t) (minus is
+ *     plus in characteristic 2);
+ *  3. the message symbol m = L[l][j] is M[l][j].  This code is systematic
+ *     through Psi itself (its first k rows are [I_k, 0], Section 3.2), so
+ *     the data are the message symbols.
+ * K lists k distinct nodes, Y their k d blocks node-major, X receives B
+ * blocks.  Returns -1 when Phi_DC is singular. */
+int or_mbr_specific_decode(const uint8_t *psi, const int *L, int k, int d, const int *K,
+                           const uint8_t *const *Y, uint8_t *const *X, size_t s)
+{
+    const int dk = d - k;
+    uint8_t *Phi = (uint8_t *)malloc((size_t)k * k), *Phinv = (uint8_t *)malloc((size_t)k * k);
+    for (int i = 0; i < k; i++) memcpy(Phi + i * k, psi + K[i] * d, (size_t)k);
+    int rc = or_invert(Phi, Phinv, k);
+    uint8_t *yl = (uint8_t *)malloc((size_t)k * (dk ? dk : 1)), *T = (uint8_t *)malloc((size_t)k * (dk ? dk : 1));
+    uint8_t *R = (uint8_t *)malloc((size_t)k * k), *S = (uint8_t *)malloc((size_t)k * k);
+    for (size_t p = 0; p < s && rc == 0; p++) {
+        /* step 1 */
+        for (int i = 0; i < k; i++)
+            for (int t = 0; t < dk; t++) yl[i * dk + t] = Y[i * d + k + t][p];
+        if (dk) or_matmul(Phinv, yl, T, k, k, dk);
+        /* step 2: R[i][j] = y_i[j] + sum_t Delta[i][t] T[j][t] */
+        for (int i = 0; i < k; i++)
+            for (int j = 0; j < k; j++) {
+                uint8_t acc = Y[i * d + j][p];
+                for (int t = 0; t < dk; t++) acc ^= or_mul(psi[K[i] * d + k + t], T[j * dk + t]);
+                R[i * k + j] = acc;
+            }
+        or_matmul(Phinv, R, S, k, k, k);
+        /* step 3 */
+        for (int l = 0; l < d; l++)
+            for (int j = 0; j < d; j++) {
+                const int m = L[l * d + j];
+                if (m < 0) continue;
+                X[m][p] = l < k ? (j < k ? S[l * k + j] : T[l * dk + (j - k)]) : T[j * dk + (l - k)];
+            }
+    }
+    free(Phi); free(Phinv); free(yl); free(T); free(R); free(S);
+    return rc == 0 ? 0 : -1;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Decode (Section 2: X = inverse(G~) Y~ over the rows of the surviving
  * blocks).  Gsys is the generator the nodes were encoded with (systematic or
  * not), (n alpha) x B.  K lists k nodes; their k alpha rows are scanned in
