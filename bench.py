@@ -178,7 +178,8 @@ def prepare_all(code, pm, f, H, K):
 def mbr_cases(torch, pm, synth, steps, warmup):
     """Configuration 3: PM-MBR (8,14,16), 64 MiB: encode, repair of node 8 from
     14 helpers (helper projections + newcomer solve), decode from a seeded
-    random 8-subset."""
+    random 8-subset, and the specific decode from it and from the parity
+    nodes."""
     dev = torch.device("cuda:0")
     code = pm.Code(k=8, d=14, n=16, kind=pm.PM_MBR)
     S = 64 << 20
@@ -218,6 +219,35 @@ def mbr_cases(torch, pm, synth, steps, warmup):
                                 max(1, steps // 4), max(1, warmup // 4))
     out["mbr_decode_gbps"] = S * max(1, steps // 4) / wall / 1e9
     out["mbr_decode_nodes"] = K
+    # the specific PM-MBR decode (pm_decode_specific: T, then S) from the same
+    # nodes and, beside the linearized decode, from the 8 parity nodes (every
+    # data block lost); its init (kernels of both passes) is reported apart
+    Kp = list(range(code.k, code.n))
+    t0 = time.perf_counter()
+    code.prepare(pm.OP_DECODE, ids=Kp)
+    ready = all(code.prepare(pm.OP_DECODE_SPECIFIC, ids=KK) for KK in (K, Kp))
+    out["mbr_specific_init_s"] = time.perf_counter() - t0
+    out["mbr_specific_all_passes_bitsliced"] = bool(ready)
+    ws_bytes = pm.pm_decode_specific_workspace(code.h, s)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    n = max(1, steps // 4)
+    equal = True
+    for tag, KK in (("", K), ("_parity", Kp)):
+        Y = torch.cat([node(i) for i in KK])
+        if tag:
+            wall, _ = Timer(torch).run(
+                lambda i: pm.pm_decode(code.h, KK, Y.data_ptr(), s, xo.data_ptr(), s, s, stream), n, 2)
+            out["mbr_decode%s_linear_gbps" % tag] = S * n / wall / 1e9
+            torch.cuda.synchronize()
+            equal = equal and bool(torch.equal(xo, x))
+        xo.zero_()
+        wall, _ = Timer(torch).run(
+            lambda i: pm.pm_decode_specific(code.h, KK, Y.data_ptr(), s, xo.data_ptr(), s, s, ws.data_ptr(),
+                                            ws_bytes, stream), n, 2)
+        out["mbr_decode%s_specific_gbps" % tag] = S * n / wall / 1e9
+        torch.cuda.synchronize()
+        equal = equal and bool(torch.equal(xo, x))
+    out["mbr_decode_results_equal"] = equal
     return out
 
 

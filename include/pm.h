@@ -141,27 +141,34 @@ pm_status pm_decode(const pm_code *code, const uint32_t *nodes, const uint8_t *Y
                     size_t y_ld, uint8_t *X, size_t x_ld, size_t block_bytes,
                     pm_stream stream);
 
-/* Specific PM-MSR decoding: the seminal paper's data-collector algorithm
- * (Section 2), which the paper's Section 4.1 finds faster than the
- * linearized decode for large k.  Same nodes, Y and X as pm_decode; the
- * result is the same bytes.  It runs as region products with small sparse
- * matrices instead of the dense B x B inverse: (0) Z_ij = y_i . phi_j for
+/* Specific PM-MSR and PM-MBR decoding: the seminal paper's data-collector
+ * algorithms (Section 2), which the paper's Section 4 finds faster than the
+ * linearized decode for large k (MSR: Section 4.1; MBR: its MBR
+ * subsection, k >= 7).  Same nodes, Y and X as pm_decode; the result is the
+ * same bytes.  It runs as region products with small sparse matrices
+ * instead of the dense B x B inverse.  PM-MSR: (0) Z_ij = y_i . phi_j for
  * every ordered pair of the k nodes, from node i's blocks; (1) P_ij and
  * Q_ij of every pair from Z_ij and Z_ji; (2) phi_i^t S1 and phi_i^t S2 for
  * alpha of the nodes by alpha x alpha solves; (3) S1 and S2, i.e. the
  * message symbols; and for systematic codes (4) their re-encoding into the
- * data blocks.  Intermediates go to `workspace` (device, 16-byte aligned, at
- * least pm_decode_specific_workspace bytes, not overlapping Y or X); the
- * library allocates nothing.  PM_EUNSUPPORTED for MBR and RS.  Passes use
- * the bit-sliced kernels once compiled (pm_prepare op 4). */
+ * data blocks.  PM-MBR (M = [[S, T], [T^t, 0]], Psi = [Phi, Delta]):
+ * (0) T = inverse(Phi_K) times the last d - k blocks of the nodes, beside
+ * copies of their first k blocks; (1) the message symbols: T, and S from
+ * the first k blocks and Delta_K T^t.  Intermediates go to `workspace`
+ * (device, 16-byte aligned, at least pm_decode_specific_workspace bytes,
+ * not overlapping Y or X); the library allocates nothing.  PM_EUNSUPPORTED
+ * for RS.  Passes use the bit-sliced kernels once compiled (pm_prepare
+ * op 4). */
 pm_status pm_decode_specific_workspace(const pm_code *code, size_t block_bytes, size_t *bytes);
 pm_status pm_decode_specific(const pm_code *code, const uint32_t *nodes, const uint8_t *Y, size_t y_ld,
                              uint8_t *X, size_t x_ld, size_t block_bytes, uint8_t *workspace,
                              size_t workspace_bytes, pm_stream stream);
 /* The factor of pass `which` (0..4 above; factor 4 has 0 rows for
- * non-systematic codes) for nodes, host row-major, cap bytes at dst (dst may
- * be NULL to query rows and cols).  Their product F4 F3 F2 F1 F0 is the
- * linearized decode matrix of pm_decode. */
+ * non-systematic PM-MSR codes, factors 2..4 for PM-MBR) for nodes, host
+ * row-major, cap bytes at dst (dst may be NULL to query rows and cols).
+ * PM-MSR: their product F4 F3 F2 F1 F0 is the linearized decode matrix of
+ * pm_decode.  PM-MBR: F1 F0 (B x k d) reads all k d node blocks and is a
+ * left inverse of the generator rows of those blocks. */
 pm_status pm_decode_specific_factor(const pm_code *code, const uint32_t *nodes, int which, uint8_t *dst,
                                     size_t cap, uint32_t *rows, uint32_t *cols);
 

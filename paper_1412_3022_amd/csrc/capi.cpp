@@ -353,8 +353,8 @@ int resolve_op(pm_code *c, int op, uint32_t failed, const uint32_t *ids, Resolve
 namespace {
 
 // The specific decode of node list ids: factors (built once) and the
-// program of each pass.  npass = kSpecificPasses - 1 for non-systematic
-// codes (no re-encoding), else kSpecificPasses.
+// program of each pass.  The passes are the leading factors with rows: all
+// five for systematic PM-MSR, four without the re-encoding, two for PM-MBR.
 struct SpecificOps {
     ProgEntry *pe[kSpecificPasses] = {};
     int npass = 0;
@@ -364,7 +364,7 @@ struct SpecificOps {
 int resolve_specific(pm_code *c, const uint32_t *ids, SpecificOps *out) {
     if (!c || !ids) return ST_EINVAL;
     const CodeMats &m = c->m;
-    if (m.kind != KIND_MSR) return ST_EUNSUPPORTED;
+    if (m.kind != KIND_MSR && m.kind != KIND_MBR) return ST_EUNSUPPORTED;
     std::vector<int> list(ids, ids + m.k), sorted;
     sorted = list;
     std::sort(sorted.begin(), sorted.end());
@@ -380,7 +380,8 @@ int resolve_specific(pm_code *c, const uint32_t *ids, SpecificOps *out) {
         it = c->specific.emplace(list, std::move(sp)).first;
     }
     pm_code::Specific &sp = it->second;
-    out->npass = sp.F[kSpecificPasses - 1].rows ? kSpecificPasses : kSpecificPasses - 1;
+    out->npass = 0;
+    while (out->npass < kSpecificPasses && sp.F[out->npass].rows) ++out->npass;
     for (int p = 0; p < out->npass; ++p) {
         const Mat &F = sp.F[p];
         const int rg = pick_rg_cached(c->var[3], F);
@@ -399,9 +400,11 @@ int resolve_specific(pm_code *c, const uint32_t *ids, SpecificOps *out) {
 }
 
 // Workspace blocks of a specific decode: the outputs of every pass but the
-// last, back to back (Z: k(k-1), pairs: B, phi_i^t S: 2 alpha^2, and for
-// systematic codes the B message symbols).
+// last, back to back.  PM-MSR: Z: k(k-1), pairs: B, phi_i^t S: 2 alpha^2,
+// and for systematic codes the B message symbols.  PM-MBR: T and the copied
+// node blocks, at most k d.
 size_t specific_ws_blocks(const CodeMats &m) {
+    if (m.kind == KIND_MBR) return static_cast<size_t>(m.k) * m.d;
     return static_cast<size_t>(m.k) * (m.k - 1) + static_cast<size_t>(m.B) +
            2u * static_cast<size_t>(m.alpha) * m.alpha + (m.systematic ? m.B : 0);
 }
@@ -515,7 +518,7 @@ pm_status pm_set_variant(pm_code *c, int op, uint32_t rg, uint32_t vec) {
 
 pm_status pm_decode_specific_workspace(const pm_code *c, size_t s, size_t *bytes) {
     if (!c || !bytes || s == 0) return PM_EINVAL;
-    if (c->m.kind != KIND_MSR) return PM_EUNSUPPORTED;
+    if (c->m.kind != KIND_MSR && c->m.kind != KIND_MBR) return PM_EUNSUPPORTED;
     *bytes = specific_ws_blocks(c->m) * ((s + 15) / 16 * 16);
     return PM_OK;
 }

@@ -304,7 +304,79 @@ int decode_matrix(const CodeMats &c, const std::vector<int> &K, Mat &D, std::vec
 // Q_ij = c (Z_ij + Z_ji) and P_ij = Z_ij + lambda_i Q_ij with c = 1 /
 // (lambda_i + lambda_j); as lambda_i c + 1 = lambda_j c, P_ij = lambda_j c
 // Z_ij + lambda_i c Z_ji.
+// The data collector of the product-matrix MBR code (Section 2: M =
+// [[S, T], [T^t, 0]], Psi = [Phi, Delta]; the k nodes of K hold
+// [Phi_K S + Delta_K T^t, Phi_K T]) in two passes over blocks.  With
+// Phinv = inverse(Phi_K) and E = Phinv Delta_K:
+//   T[l][t] = sum_i Phinv[l][i] y_i[k + t],
+//   S[l][j] = sum_i Phinv[l][i] y_i[j] + sum_t E[l][t] T[j][t].
+// S is symmetric, so each of its symbols is taken from the side (l, j) or
+// (j, l) with fewer terms; for a node l < k of K (a row [I_k, 0] of Psi)
+// row l of Phinv is a unit vector and row l of E is zero, so its T and S
+// symbols become plain copies.
+static int mbr_specific_factors(const CodeMats &c, const std::vector<int> &K, Mat F[kSpecificPasses]) {
+    const int k = c.k, d = c.d, dk = d - k, B = c.B;
+    Mat Phi(k, k), Phinv;
+    for (int i = 0; i < k; ++i)
+        for (int t = 0; t < k; ++t) Phi.at(i, t) = c.psi.at(K[i], t);
+    if (!invert(Phi, Phinv)) return ST_ESINGULAR;
+    std::vector<uint8_t> E(static_cast<size_t>(k) * dk, 0);
+    for (int l = 0; l < k; ++l)
+        for (int t = 0; t < dk; ++t) {
+            uint8_t acc = 0;
+            for (int i = 0; i < k; ++i) acc ^= gmul(Phinv.at(l, i), c.psi.at(K[i], k + t));
+            E[static_cast<size_t>(l) * dk + t] = acc;
+        }
+    // second-pass inputs: T[l][t] at l*dk + t, then copies of y_i[j] at
+    // k*dk + i*k + j (renumbered below to the copies actually read)
+    const int nT = k * dk, nv = nT + k * k;
+    Mat F1(B, nv);
+    auto s_terms = [&](int l, int j) {
+        int cnt = 0;
+        for (int i = 0; i < k; ++i) cnt += Phinv.at(l, i) != 0;
+        for (int t = 0; t < dk; ++t) cnt += E[static_cast<size_t>(l) * dk + t] != 0;
+        return cnt;
+    };
+    for (int a = 0; a < k; ++a) {
+        for (int b = a; b < k; ++b) {
+            const int l = s_terms(a, b) <= s_terms(b, a) ? a : b, j = l == a ? b : a;
+            const int m = c.L[a * d + b];
+            for (int i = 0; i < k; ++i) F1.at(m, nT + i * k + j) ^= Phinv.at(l, i);
+            for (int t = 0; t < dk; ++t) F1.at(m, j * dk + t) ^= E[static_cast<size_t>(l) * dk + t];
+        }
+        for (int t = 0; t < dk; ++t) F1.at(c.L[a * d + k + t], a * dk + t) = 1;
+    }
+    std::vector<int> wrow(nv, -1);
+    int nw = nT;
+    for (int v = 0; v < nT; ++v) wrow[v] = v;
+    for (int v = nT; v < nv; ++v) {
+        bool used = false;
+        for (int m = 0; m < B && !used; ++m) used = F1.at(m, v) != 0;
+        if (used) wrow[v] = nw++;
+    }
+    Mat F0(nw, k * d), W1(B, nw);
+    for (int l = 0; l < k; ++l)
+        for (int t = 0; t < dk; ++t)
+            for (int i = 0; i < k; ++i) F0.at(l * dk + t, i * d + k + t) = Phinv.at(l, i);
+    for (int v = nT; v < nv; ++v)
+        if (wrow[v] >= 0) {
+            const int i = (v - nT) / k, j = (v - nT) % k;
+            F0.at(wrow[v], i * d + j) = 1;
+        }
+    for (int m = 0; m < B; ++m)
+        for (int v = 0; v < nv; ++v)
+            if (F1.at(m, v)) W1.at(m, wrow[v]) = F1.at(m, v);
+    F[0] = std::move(F0);
+    F[1] = std::move(W1);
+    for (int p = 2; p < kSpecificPasses; ++p) F[p] = Mat();
+    return ST_OK;
+}
+
 int specific_decode_factors(const CodeMats &c, const std::vector<int> &K, Mat F[kSpecificPasses]) {
+    if (c.kind == KIND_MBR) {
+        if (static_cast<int>(K.size()) != c.k) return ST_EINVAL;
+        return mbr_specific_factors(c, K, F);
+    }
     if (c.kind != KIND_MSR) return ST_EUNSUPPORTED;
     const int k = c.k, a = c.alpha, d = c.d, B = c.B;
     if (static_cast<int>(K.size()) != k || d != 2 * a) return ST_EINVAL;

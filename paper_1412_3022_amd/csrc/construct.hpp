@@ -57,7 +57,14 @@ int decode_matrix(const CodeMats &c, const std::vector<int> &nodes, Mat &D, std:
 //   F[3] (B x 2 alpha^2): the message symbols, S1 = inverse(Phi_A) U and
 //        S2 = inverse(Phi_A) V;
 //   F[4] (B x B): systematic codes only, X = G~ Z (rows 0 otherwise).
-// ST_EUNSUPPORTED for MBR / RS, ST_ESINGULAR for a singular system.
+// Specific PM-MBR decoding from the k nodes K, as two factors:
+//   F[0] (w x k d): T = inverse(Phi_K) times the last d - k blocks of each
+//        node (k (d-k) rows), then copies of the first-k node blocks that
+//        F[1] reads;
+//   F[1] (B x w): the message symbols, T copied and S from the first-k
+//        blocks and T; F[2..4] are empty.
+// The passes run in order while F[p] has rows.  ST_EUNSUPPORTED for RS,
+// ST_ESINGULAR for a singular system.
 constexpr int kSpecificPasses = 5;
 int specific_decode_factors(const CodeMats &c, const std::vector<int> &K, Mat F[kSpecificPasses]);
 

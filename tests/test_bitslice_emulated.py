@@ -60,12 +60,14 @@ def test_generated_kernels_match_oracle_on_host(tmp_path, name, kw, ok, f, H, K,
 
 
 @pytest.mark.parametrize("kw,K", [(dict(k=8, d=14, n=16), list(range(8, 16))),
-                                  (dict(k=6, d=10, n=12, systematic=False), [0, 2, 4, 6, 8, 10])],
-                         ids=["msr8-sys", "msr6-nonsys"])
+                                  (dict(k=6, d=10, n=12, systematic=False), [0, 2, 4, 6, 8, 10]),
+                                  (dict(k=8, d=14, n=16, kind=pm.PM_MBR), [0, 1, 2, 6, 10, 12, 13, 15])],
+                         ids=["msr8-sys", "msr6-nonsys", "mbr8-mixed"])
 def test_specific_decode_factor_kernels_on_host(tmp_path, kw, K):
-    """The generated kernels of the specific decode's factor matrices (node
-    times phi products, pair solves, alpha x alpha solves, message symbols,
-    systematic re-encoding) against the oracle's product, on the host."""
+    """The generated kernels of the specific decode's factor matrices (MSR:
+    node times phi products, pair solves, alpha x alpha solves, message
+    symbols, systematic re-encoding; MBR: T beside copies, then the message
+    symbols) against the oracle's product, on the host."""
     c = pm.Code(**kw)
     for w in range(5):
         F = c.specific_factor(K, w)

@@ -351,10 +351,17 @@ SPECIFIC_CASES = [
     ("msr8-parity", dict(k=8, d=14, n=16), list(range(8, 16))),
     ("msr8-mixed", dict(k=8, d=14, n=16), [0, 3, 5, 8, 9, 11, 13, 15]),
     ("msr16-parity", dict(k=16, d=30, n=32), list(range(16, 32))),
+    ("mbr4-parity", dict(k=4, d=6, n=8, kind=pm.PM_MBR), [7, 4, 6, 5]),
+    ("mbr4-dk", dict(k=4, d=4, n=6, kind=pm.PM_MBR), [5, 1, 4, 2]),
+    ("mbr8-parity", dict(k=8, d=14, n=16, kind=pm.PM_MBR), list(range(8, 16))),
+    ("mbr8-mixed", dict(k=8, d=14, n=16, kind=pm.PM_MBR), [0, 1, 2, 6, 10, 12, 13, 15]),
+    ("mbr8-sys", dict(k=8, d=14, n=16, kind=pm.PM_MBR), list(range(8))),
 ]
 
 
 def _specific_oracle(kw):
+    if kw.get("kind") == pm.PM_MBR:
+        return O.Code(O.MBR, kw["k"], kw["d"], kw["n"])
     cons = O.VANILLA if kw.get("construction") == pm.PM_VANILLA else O.SPARSE
     x = np.array(kw["x"]) if "x" in kw else None
     return O.Code(O.MSR, kw["k"], kw["d"], kw["n"], cons, kw.get("systematic", True), x=x)
@@ -363,9 +370,10 @@ def _specific_oracle(kw):
 @pytest.mark.parametrize("name,kw,K", SPECIFIC_CASES, ids=[c[0] for c in SPECIFIC_CASES])
 @pytest.mark.parametrize("prepared", [False, True], ids=["table", "bitsliced"])
 def test_specific_decode_matches_oracle(name, kw, K, prepared):
-    """pm_decode_specific (node times phi products, pair solves, alpha x alpha
-    solves, message symbols, systematic re-encoding, each a region product)
-    returns the object, on
+    """pm_decode_specific (MSR: node times phi products, pair solves, alpha x
+    alpha solves, message symbols, systematic re-encoding; MBR: T beside
+    copies, then the message symbols; each a region product) returns the
+    object, on
     the table kernels and after pm_prepare on the bit-sliced ones; ragged
     block lengths, guard bytes checked."""
     print("specific decode %s prepared=%s" % (name, prepared), flush=True)

@@ -164,7 +164,7 @@ def test_prepare_argument_errors(op, failed, ids):
     assert st == pm.PM_EINVAL and spec == 0
 
 
-# ---------------------------------------------------- specific PM-MSR decode --
+# ------------------------------------------- specific PM-MSR / PM-MBR decode --
 SPECIFIC = [
     (dict(k=3, d=4, n=6, construction=pm.PM_VANILLA, x=list(range(1, 7))), (O.MSR, 3, 4, 6, O.VANILLA), [3, 4, 5]),
     (dict(k=4, d=6, n=8), (O.MSR, 4, 6, 8, O.SPARSE), [7, 2, 5, 0]),
@@ -202,13 +202,55 @@ def test_specific_decode_factors_multiply_to_the_decode_matrix(kw, ok, K):
     assert np.array_equal(prod, D)
 
 
+MBR_SPECIFIC = [
+    ((3, 4, 6), [3, 4, 5]),
+    ((4, 4, 6), [5, 1, 4, 2]),
+    ((4, 6, 8), [0, 1, 2, 3]),
+    ((8, 14, 16), list(range(8, 16))),
+    ((8, 14, 16), [0, 1, 2, 6, 10, 12, 13, 15]),
+    ((16, 30, 32), list(range(16, 32))),
+]
+
+
+@pytest.mark.parametrize("kdn,K", MBR_SPECIFIC, ids=lambda v: None)
+def test_mbr_specific_factors_invert_the_received_rows(kdn, K):
+    """The library's two PM-MBR factors: F1 F0 times the oracle's generator
+    rows of the k d received blocks is the identity (they decode every
+    object), and the nodes of K among the first k (rows [I_k, 0] of Psi)
+    make their message symbols plain copies."""
+    k, d, n = kdn
+    c = pm.Code(k=k, d=d, n=n, kind=pm.PM_MBR)
+    o = O.Code(O.MBR, k, d, n)
+    F = [c.specific_factor(K, w) for w in range(5)]
+    w = F[0].shape[0]
+    assert F[0].shape == (w, k * d) and F[1].shape == (c.B, w)
+    assert all(F[p].shape[0] == 0 for p in (2, 3, 4))
+    assert k * (d - k) <= w <= k * d
+    GK = np.concatenate([o.Gsys[i * d:(i + 1) * d] for i in K])
+    assert np.array_equal(O.matmul(O.matmul(F[1], F[0]), GK), np.eye(c.B, dtype=np.uint8))
+    # a message symbol held by a node l < k of K: one term, a copy of a copy
+    sysK = [i for i in K if i < k]
+    for a in sysK:
+        for b in range(d):
+            m = np.asarray(o.L).reshape(-1)[a * d + b]
+            row = F[1][m]
+            assert np.count_nonzero(row) == 1 and row.max() == 1
+            src = F[0][np.flatnonzero(row)[0]]
+            assert np.count_nonzero(src) == 1 and src.max() == 1
+    if len(sysK) == k:
+        assert (np.count_nonzero(F[0], axis=1) == 1).all() and (np.count_nonzero(F[1], axis=1) == 1).all()
+
+
 def test_specific_decode_refusals():
-    assert pm.Code(k=8, d=14, n=16, kind=pm.PM_MBR).h
     L = pm.lib()
-    for kw in (dict(k=8, d=14, n=16, kind=pm.PM_MBR), dict(k=8, d=8, n=16, kind=pm.PM_RS)):
-        c = pm.Code(**kw)
-        n = ctypes.c_size_t()
-        assert L.pm_decode_specific_workspace(c.h, 4096, ctypes.byref(n)) == pm.PM_EUNSUPPORTED
+    c = pm.Code(k=8, d=8, n=16, kind=pm.PM_RS)
+    n = ctypes.c_size_t()
+    assert L.pm_decode_specific_workspace(c.h, 4096, ctypes.byref(n)) == pm.PM_EUNSUPPORTED
+    c = pm.Code(k=8, d=14, n=16, kind=pm.PM_MBR)
+    assert L.pm_decode_specific_workspace(c.h, 4090, ctypes.byref(n)) == pm.PM_OK
+    assert n.value == 8 * 14 * 4096
+    bad = (ctypes.c_uint32 * 8)(0, 1, 2, 3, 4, 5, 6, 6)
+    assert L.pm_decode_specific_factor(c.h, bad, 0, None, 0, None, None) == pm.PM_EINVAL
     c = pm.Code(k=4, d=6, n=8)
     bad = (ctypes.c_uint32 * 4)(0, 1, 1, 2)
     assert L.pm_decode_specific_factor(c.h, bad, 0, None, 0, None, None) == pm.PM_EINVAL
