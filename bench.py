@@ -334,6 +334,45 @@ def msr16_decode_case(torch, pm, synth, steps, warmup):
     return out
 
 
+def gpu_init_case(torch, pm, synth):
+    """GPU-side init (pm_decode_matrices, batched Gauss-Jordan): the decode
+    matrices of every 8-subset of the 16 nodes of the (8,14,16) sparse MSR
+    code in one launch, 1024 seeded node sets of the (16,30,32) code and
+    2048 of the (8,14,16) MBR code; the library's host init of the same
+    matrices (pm_decode_matrix, one thread) timed on a sample of the sets,
+    and that sample compared with the GPU's matrices."""
+    import itertools
+    dev = torch.device("cuda:0")
+    out = {}
+    cases = [("msr8_all", dict(k=8, d=14, n=16), None, 200),
+             ("msr16", dict(k=16, d=30, n=32), 1024, 8),
+             ("mbr8", dict(k=8, d=14, n=16, kind=pm.PM_MBR), 2048, 100)]
+    equal = True
+    for name, kw, nsets, nsample in cases:
+        code = pm.Code(**kw)
+        if nsets is None:
+            sets = [list(K) for K in itertools.combinations(range(code.n), code.k)]
+        else:
+            st = synth.Stream(synth.CONFIG_SEED + 7)
+            sets = [st.subset(code.n, code.k) for _ in range(nsets)]
+        S = torch.tensor(sets, dtype=torch.int32, device=dev)
+        D, kept, status = code.decode_matrices(S)          # uploads the generator
+        _, ev = Timer(torch).run(lambda i: code.decode_matrices(S), 5, 1)
+        out["init_%s_sets" % name] = len(sets)
+        out["init_%s_gpu_ms" % name] = ev / 5 * 1e3
+        out["init_%s_gpu_sets_per_s" % name] = len(sets) * 5 / ev
+        idx = synth.Stream(synth.CONFIG_SEED + 8).subset(len(sets), nsample)
+        t0 = time.perf_counter()
+        want = [code.decode_matrix(sets[i])[0] for i in idx]
+        host = time.perf_counter() - t0
+        out["init_%s_host_sets_per_s" % name] = nsample / host
+        Dc, stc = D.cpu().numpy(), status.cpu().numpy()
+        equal = equal and bool((stc == 0).all()) and all((Dc[i] == w).all() for i, w in zip(idx, want))
+        del D, kept, status, S
+    out["init_gpu_matches_host_sample"] = equal
+    return out
+
+
 def batched_case(torch, pm, synth, steps):
     """Configuration 4: 4096 objects, sizes log-uniform 64 KiB - 16 MiB,
     sparse PM-MSR (4,6), (8,14), (16,30), n = 2k, all encoded by one
@@ -532,6 +571,8 @@ def main():
                       for k, v in mbr_cases(torch, pm, synth, args.steps, args.warmup).items()})
         extra.update({k: (round(v, 2) if isinstance(v, float) else v)
                       for k, v in msr16_decode_case(torch, pm, synth, args.steps, args.warmup).items()})
+        extra.update({k: (round(v, 3) if isinstance(v, float) else v)
+                      for k, v in gpu_init_case(torch, pm, synth).items()})
     batched = served = None
     if not args.no_batch:
         batched = batched_case(torch, pm, synth, max(5, args.steps // 20))

@@ -172,6 +172,45 @@ pm_status pm_decode_specific(const pm_code *code, const uint32_t *nodes, const u
 pm_status pm_decode_specific_factor(const pm_code *code, const uint32_t *nodes, int which, uint8_t *dst,
                                     size_t cap, uint32_t *rows, uint32_t *cols);
 
+/* Host init of pm_decode for one node set (Section 2: X = inverse(G~) Y~):
+ * the B x B decode matrix it applies, row-major into host `D` (cap >= B*B
+ * bytes; may be NULL), and in host `kept` (B entries; may be NULL) the
+ * indices, among the k alpha received blocks, of the blocks it reads.
+ * Built once per node set and kept with the code, as pm_decode does.
+ * PM_EINVAL for a bad node list, PM_ESINGULAR if undecodable. */
+pm_status pm_decode_matrix(const pm_code *code, const uint32_t *nodes, uint8_t *D, size_t cap, uint32_t *kept);
+
+/* GPU-side init: batched Gauss-Jordan elimination over GF(2^8), one
+ * work-group per problem.  The paper reports the initialization (building
+ * and inverting the per-failure-pattern matrices) apart from the data phase
+ * and finds that it dominates for small objects (Section 4); this computes
+ * the decode matrices of `count` node sets at once.  node_sets: device,
+ * count x k node ids.  For set p, D + p*d_stride (device, d_stride >= B*B)
+ * receives the B x B row-major matrix that pm_decode applies for that set
+ * (Section 2: X = inverse(G~) Y~): the inverse of the generator rows of the
+ * first B independent blocks, in order, among the set's k alpha blocks
+ * (node-major; for MSR and RS all of them, for MBR B of the k d); and
+ * kept + p*B (device, may be NULL) receives their indices among those
+ * blocks.  status[p] (device) = PM_OK, PM_EINVAL (a node id >= n or
+ * repeated) or PM_ESINGULAR (rank < B); D of a failed set is zero.
+ * Asynchronous on `stream`; the first call on a device also uploads the
+ * generator, which the code keeps.  PM_EUNSUPPORTED when a problem's
+ * B x 2B bytes of elimination state exceed one work-group's LDS (PM-MBR
+ * with k = 16 on MI355X). */
+pm_status pm_decode_matrices(const pm_code *code, const uint32_t *node_sets, uint32_t count, uint8_t *D,
+                             size_t d_stride, uint32_t *kept, int32_t *status, pm_stream stream);
+
+/* The same elimination on caller matrices: the inverses of `count` m x m
+ * matrices over GF(2^8).  A: device, matrix p at A + p*a_stride with rows
+ * a_ld apart; Ainv: device, p at Ainv + p*inv_stride with rows inv_ld
+ * apart (Ainv may equal A with the same layout; distinct problems must not
+ * overlap).  status[p] (device) = PM_OK or PM_ESINGULAR (inverse zero).
+ * Asynchronous on `stream`.  PM_EINVAL for bad sizes or strides,
+ * PM_EUNSUPPORTED when m x 2m bytes exceed one work-group's LDS. */
+pm_status pm_gf_invert_batch(const uint8_t *A, size_t a_ld, size_t a_stride, uint32_t m, uint32_t count,
+                             uint8_t *Ainv, size_t inv_ld, size_t inv_stride, int32_t *status,
+                             pm_stream stream);
+
 /* The region engine itself (the constant-times-region multiply-XOR of the
  * paper's Section 4, batched over a matrix): out[r] = XOR_c A[r][c] * in[c]
  * for a host row-major rows x cols matrix A.  Tables are cached by content. */

@@ -23,12 +23,12 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
 HOST_SOURCES = ["gf256.cpp", "construct.cpp", "program.cpp", "capi.cpp", "batch.cpp", "server.cpp", "bitslice.cpp"]
-HIP_SOURCES = ["kernels.hip"]
+HIP_SOURCES = ["kernels.hip", "gj.hip"]
 
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__",
               "-I" + os.path.join(ROCM, "include"), "-I" + INCLUDE, "-pthread"]
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions.
-HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I" + INCLUDE,
+HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I" + INCLUDE, "-I" + CSRC,
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 

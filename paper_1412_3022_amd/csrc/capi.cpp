@@ -14,6 +14,7 @@
 
 #include "construct.hpp"
 #include "engine.hpp"
+#include "gj.hpp"
 #include "pm.h"
 #include "program.hpp"
 
@@ -46,14 +47,10 @@ static int upload_stream(int dev, hipStream_t *out) {
     return ST_OK;
 }
 
-ProgEntry::~ProgEntry() {
-    for (auto &kv : dev) {
-        if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
-        if (kv.second.ptr) (void)hipFree(kv.second.ptr);
-    }
-}
+ProgEntry::~ProgEntry() { free_device_copies(dev); }
 
-int ProgEntry::device_ptr(hipStream_t user, const uint32_t **out) {
+int device_copy(std::mutex &mu, std::map<int, DevCopy> &dev, const void *host, size_t bytes, hipStream_t user,
+                const void **out) {
     int devid = 0;
     hipError_t e = hipGetDevice(&devid);
     if (e != hipSuccess) return hip_fail(e);
@@ -63,9 +60,8 @@ int ProgEntry::device_ptr(hipStream_t user, const uint32_t **out) {
         hipStream_t up = nullptr;
         int st = upload_stream(devid, &up);
         if (st != ST_OK) return st;
-        const size_t bytes = prog.blob.size() * sizeof(uint32_t);
         if ((e = hipMalloc(&dc.ptr, bytes)) != hipSuccess) { dc.ptr = nullptr; return hip_fail(e); }
-        if ((e = hipMemcpyAsync(dc.ptr, prog.blob.data(), bytes, hipMemcpyHostToDevice, up)) != hipSuccess)
+        if ((e = hipMemcpyAsync(dc.ptr, host, bytes, hipMemcpyHostToDevice, up)) != hipSuccess)
             return hip_fail(e);
         if ((e = hipEventCreateWithFlags(&dc.ready, hipEventDisableTiming)) != hipSuccess) return hip_fail(e);
         if ((e = hipEventRecord(dc.ready, up)) != hipSuccess) return hip_fail(e);
@@ -80,8 +76,23 @@ int ProgEntry::device_ptr(hipStream_t user, const uint32_t **out) {
             return hip_fail(e);
         }
     }
-    *out = static_cast<const uint32_t *>(dc.ptr);
+    *out = dc.ptr;
     return ST_OK;
+}
+
+void free_device_copies(std::map<int, DevCopy> &dev) {
+    for (auto &kv : dev) {
+        if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
+        if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+    }
+    dev.clear();
+}
+
+int ProgEntry::device_ptr(hipStream_t user, const uint32_t **out) {
+    const void *p = nullptr;
+    int st = device_copy(mu, dev, prog.blob.data(), prog.blob.size() * sizeof(uint32_t), user, &p);
+    if (st == ST_OK) *out = static_cast<const uint32_t *>(p);
+    return st;
 }
 
 int ProgEntry::device_ptr_sync(const uint32_t **out) {
@@ -228,6 +239,11 @@ struct pm_code {
         std::map<int, std::unique_ptr<ProgEntry>> progs[kSpecificPasses];   // by rg
     };
     std::map<std::vector<int>, Specific> specific;
+    // device copies of the generator the node contents follow (Gsys), for
+    // the batched decode-matrix init
+    std::mutex dev_mu;
+    std::map<int, DevCopy> gsys_dev;
+    ~pm_code() { free_device_copies(gsys_dev); }
 };
 
 namespace {
@@ -581,6 +597,84 @@ pm_status pm_decode_specific_factor(const pm_code *cc, const uint32_t *nodes, in
     return PM_OK;
 }
 
+
+}  // extern "C"
+
+namespace {
+
+// Whether one problem of m candidates, B columns and nsets node ids fits
+// one work-group's LDS on the current device.
+int gj_check(uint32_t B, uint32_t m, uint32_t nsets) {
+    if (B == 0 || m < B) return ST_EINVAL;
+    int dev = 0, maxlds = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e);
+    if ((e = hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess)
+        return hip_fail(e);
+    return pmk_gj_lds_bytes(B, m, nsets) <= static_cast<size_t>(maxlds) ? ST_OK : ST_EUNSUPPORTED;
+}
+
+}  // namespace
+
+extern "C" {
+
+pm_status pm_decode_matrix(const pm_code *cc, const uint32_t *nodes, uint8_t *D, size_t cap, uint32_t *kept) {
+    if (!cc || !nodes) return PM_EINVAL;
+    pm_code *c = const_cast<pm_code *>(cc);
+    const CodeMats &m = c->m;
+    std::vector<int> list(nodes, nodes + m.k), sorted = list;
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) return PM_EINVAL;
+    for (int v : list)
+        if (v < 0 || v >= m.n) return PM_EINVAL;
+    if (D && cap < static_cast<size_t>(m.B) * m.B) return PM_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->decode_mat.find(list);
+    if (it == c->decode_mat.end()) {
+        Mat Dm;
+        std::vector<int> used;
+        int st = decode_matrix(m, list, Dm, used);
+        if (st != ST_OK) return static_cast<pm_status>(st);
+        it = c->decode_mat.emplace(list, std::make_pair(std::move(Dm), std::move(used))).first;
+    }
+    if (D) std::copy(it->second.first.v.begin(), it->second.first.v.end(), D);
+    if (kept)
+        for (size_t q = 0; q < it->second.second.size(); ++q) kept[q] = static_cast<uint32_t>(it->second.second[q]);
+    return PM_OK;
+}
+
+pm_status pm_decode_matrices(const pm_code *cc, const uint32_t *node_sets, uint32_t count, uint8_t *D,
+                             size_t d_stride, uint32_t *kept, int32_t *status, pm_stream stream) {
+    if (!cc || !node_sets || !D || !status) return PM_EINVAL;
+    pm_code *c = const_cast<pm_code *>(cc);
+    const CodeMats &m = c->m;
+    const uint32_t B = static_cast<uint32_t>(m.B);
+    if (d_stride < static_cast<size_t>(B) * B) return PM_EINVAL;
+    if (count == 0) return PM_OK;
+    int st = gj_check(B, static_cast<uint32_t>(m.k * m.alpha), static_cast<uint32_t>(m.k));
+    if (st != ST_OK) return static_cast<pm_status>(st);
+    hipStream_t h = reinterpret_cast<hipStream_t>(stream);
+    const void *g = nullptr;
+    if ((st = device_copy(c->dev_mu, c->gsys_dev, m.Gsys.v.data(), m.Gsys.v.size(), h, &g)) != ST_OK)
+        return static_cast<pm_status>(st);
+    const PmkGj a{static_cast<const uint8_t *>(g), B, 0, node_sets, static_cast<uint32_t>(m.k),
+                  static_cast<uint32_t>(m.alpha), static_cast<uint32_t>(m.n),
+                  static_cast<uint32_t>(m.k * m.alpha), B, D, B, d_stride, kept, status};
+    hipError_t e = pmk_gj(&a, count, h);
+    return e == hipSuccess ? PM_OK : static_cast<pm_status>(hip_fail(e));
+}
+
+pm_status pm_gf_invert_batch(const uint8_t *A, size_t a_ld, size_t a_stride, uint32_t m, uint32_t count,
+                             uint8_t *Ainv, size_t inv_ld, size_t inv_stride, int32_t *status, pm_stream stream) {
+    if (!A || !Ainv || !status || m == 0 || a_ld < m || inv_ld < m) return PM_EINVAL;
+    if (count > 1 && (a_stride < (m - 1) * a_ld + m || inv_stride < (m - 1) * inv_ld + m)) return PM_EINVAL;
+    if (count == 0) return PM_OK;
+    int st = gj_check(m, m, 0);
+    if (st != ST_OK) return static_cast<pm_status>(st);
+    const PmkGj a{A, a_ld, a_stride, nullptr, 0, 1, 0, m, m, Ainv, inv_ld, inv_stride, nullptr, status};
+    hipError_t e = pmk_gj(&a, count, reinterpret_cast<hipStream_t>(stream));
+    return e == hipSuccess ? PM_OK : static_cast<pm_status>(hip_fail(e));
+}
 
 pm_status pm_prepare(pm_code *c, int op, uint32_t failed, const uint32_t *ids, uint32_t flags, int *specialized) {
     if (specialized) *specialized = 0;

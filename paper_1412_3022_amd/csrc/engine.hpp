@@ -38,6 +38,13 @@ struct DevCopy {
     bool done = false;
 };
 
+// The copy of `bytes` host bytes on the current device in `dev` (guarded by
+// mu), uploaded on first use there on an internal stream; `user` is made to
+// wait for the upload until it is known to be complete.
+int device_copy(std::mutex &mu, std::map<int, DevCopy> &dev, const void *host, size_t bytes, hipStream_t user,
+                const void **out);
+void free_device_copies(std::map<int, DevCopy> &dev);
+
 // A program plus its per-device copies.  device_ptr() uploads on first use
 // on the current device (on an internal stream) and makes `user` wait for
 // the upload until it is known to be complete.

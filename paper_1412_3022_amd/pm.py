@@ -78,6 +78,9 @@ def _lib():
         L.pm_decode_specific_workspace.argtypes = [vp, sz, ctypes.POINTER(ctypes.c_size_t)]
         L.pm_decode_specific.argtypes = [vp, u32p, vp, sz, vp, sz, sz, vp, sz, vp]
         L.pm_decode_specific_factor.argtypes = [vp, u32p, i32, vp, sz, u32p, u32p]
+        L.pm_decode_matrix.argtypes = [vp, u32p, vp, sz, u32p]
+        L.pm_decode_matrices.argtypes = [vp, vp, u32, vp, sz, vp, vp, vp]
+        L.pm_gf_invert_batch.argtypes = [vp, sz, sz, u32, u32, vp, sz, sz, vp, vp]
         L.pm_batch_plan.argtypes = [ctypes.POINTER(pm_batch_item), sz, u32, ctypes.POINTER(vp)]
         L.pm_batch_set_variant.argtypes = [vp, u32, u32]
         L.pm_batch_autotune.argtypes = [vp, u32, vp, u32p]
@@ -89,6 +92,7 @@ def _lib():
         L.pm_status_string.argtypes = [i32]
         L.pm_status_string.restype = ctypes.c_char_p
         for name in ("pm_code_create", "pm_code_dims", "pm_code_matrix", "pm_code_node_map", "pm_encode",
+                     "pm_decode_matrix", "pm_decode_matrices", "pm_gf_invert_batch",
                      "pm_repair_helper", "pm_repair_newcomer", "pm_decode", "pm_apply", "pm_set_variant",
                      "pm_autotune_encode", "pm_batch_plan", "pm_batch_set_variant", "pm_batch_autotune",
                      "pm_batch_run", "pm_batch_info"):
@@ -180,6 +184,31 @@ def pm_decode_specific_workspace(h, block_bytes):
 def pm_decode_specific(h, nodes, y_ptr, y_ld, x_ptr, x_ld, block_bytes, ws_ptr, ws_bytes, stream=0):
     return _lib().pm_decode_specific(h, _u32arr(nodes), y_ptr, y_ld, x_ptr, x_ld, block_bytes, ws_ptr, ws_bytes,
                                      stream or None)
+
+
+def pm_decode_matrices(h, sets_ptr, count, d_ptr, d_stride, kept_ptr, status_ptr, stream=0):
+    return _lib().pm_decode_matrices(h, sets_ptr, count, d_ptr, d_stride, kept_ptr or None, status_ptr,
+                                     stream or None)
+
+
+def pm_gf_invert_batch(a_ptr, a_ld, a_stride, m, count, inv_ptr, inv_ld, inv_stride, status_ptr, stream=0):
+    return _lib().pm_gf_invert_batch(a_ptr, a_ld, a_stride, m, count, inv_ptr, inv_ld, inv_stride, status_ptr,
+                                     stream or None)
+
+
+def gf_invert_batch(A, stream=None):
+    """Inverses of the m x m matrices A[p] (device uint8 tensor, count x m x
+    m) over GF(2^8) by the batched Gauss-Jordan kernel; returns (Ainv,
+    status) with status[p] = PM_OK or PM_ESINGULAR (inverse zero)."""
+    import torch
+    if A.dim() != 3 or A.shape[1] != A.shape[2] or A.dtype != torch.uint8 or not A.is_contiguous():
+        raise ValueError("A must be a contiguous count x m x m uint8 tensor")
+    count, m = A.shape[0], A.shape[1]
+    inv = torch.empty_like(A)
+    status = torch.empty(count, dtype=torch.int32, device=A.device)
+    _check(pm_gf_invert_batch(A.data_ptr(), m, m * m, m, count, inv.data_ptr(), m, m * m, status.data_ptr(),
+                              _stream_handle(stream)), "pm_gf_invert_batch")
+    return inv, status
 
 
 def pm_autotune_encode(h, x_ptr, x_ld, out_ptr, out_ld, block_bytes, reps=5, stream=0):
@@ -301,6 +330,33 @@ class Code:
         _check(pm_decode_specific(self.h, nodes, yp, yld, xp, xld, block_bytes, workspace.data_ptr(),
                                   workspace.numel(), _stream_handle(stream)), "pm_decode_specific")
         return workspace
+
+    def decode_matrix(self, nodes):
+        """The host-built decode matrix of pm_decode for nodes and the received
+        blocks it reads: (D B x B uint8, kept list)."""
+        import numpy as np
+        D = np.zeros((self.B, self.B), np.uint8)
+        kept = (ctypes.c_uint32 * self.B)()
+        _check(_lib().pm_decode_matrix(self.h, _u32arr(nodes), D.ctypes.data, D.size, kept), "pm_decode_matrix")
+        return D, list(kept)
+
+    def decode_matrices(self, node_sets, stream=None):
+        """Decode matrices of many node sets at once on the GPU (batched
+        Gauss-Jordan).  node_sets: device int32/uint32-valued tensor, count x k.
+        Returns (D count x B x B uint8, kept count x B int32, status count
+        int32), all on the device; status[p] = PM_OK, PM_EINVAL or
+        PM_ESINGULAR."""
+        import torch
+        if node_sets.dim() != 2 or node_sets.shape[1] != self.k or node_sets.dtype != torch.int32:
+            raise ValueError("node_sets must be a count x k int32 tensor")
+        sets = node_sets.contiguous()
+        count = sets.shape[0]
+        D = torch.empty((count, self.B, self.B), dtype=torch.uint8, device=sets.device)
+        kept = torch.empty((count, self.B), dtype=torch.int32, device=sets.device)
+        status = torch.empty(count, dtype=torch.int32, device=sets.device)
+        _check(pm_decode_matrices(self.h, sets.data_ptr(), count, D.data_ptr(), self.B * self.B, kept.data_ptr(),
+                                  status.data_ptr(), _stream_handle(stream)), "pm_decode_matrices")
+        return D, kept, status
 
     def decode(self, nodes, Y, X, block_bytes, stream=None):
         yp, yld = _regions(Y, len(nodes) * self.alpha)

@@ -263,3 +263,44 @@ def test_specific_decode_refusals():
     st = L.pm_decode_specific(c.h, good, ctypes.c_void_p(1 << 20), 112, ctypes.c_void_p(1 << 22), 112, 100,
                               ctypes.c_void_p(1 << 24), n.value - 16, None)
     assert st == pm.PM_EINVAL
+
+
+# ------------------------------------------------ GPU-side init: arguments --
+def test_init_entry_points_refuse_bad_arguments_before_any_gpu_work():
+    L = pm.lib()
+    vp = ctypes.c_void_p
+    c = pm.Code(k=8, d=14, n=16)
+    B = c.B
+    assert L.pm_decode_matrices(None, vp(1 << 20), 1, vp(1 << 21), B * B, None, vp(1 << 22), None) == pm.PM_EINVAL
+    assert L.pm_decode_matrices(c.h, None, 1, vp(1 << 21), B * B, None, vp(1 << 22), None) == pm.PM_EINVAL
+    assert L.pm_decode_matrices(c.h, vp(1 << 20), 1, None, B * B, None, vp(1 << 22), None) == pm.PM_EINVAL
+    assert L.pm_decode_matrices(c.h, vp(1 << 20), 1, vp(1 << 21), B * B, None, None, None) == pm.PM_EINVAL
+    assert L.pm_decode_matrices(c.h, vp(1 << 20), 1, vp(1 << 21), B * B - 1, None, vp(1 << 22), None) == pm.PM_EINVAL
+    assert L.pm_decode_matrices(c.h, vp(1 << 20), 0, vp(1 << 21), B * B, None, vp(1 << 22), None) == pm.PM_OK
+    inv = L.pm_gf_invert_batch
+    assert inv(vp(1 << 20), 8, 64, 0, 1, vp(1 << 21), 8, 64, vp(1 << 22), None) == pm.PM_EINVAL    # m = 0
+    assert inv(vp(1 << 20), 7, 64, 8, 1, vp(1 << 21), 8, 64, vp(1 << 22), None) == pm.PM_EINVAL    # a_ld < m
+    assert inv(vp(1 << 20), 8, 64, 8, 1, vp(1 << 21), 7, 64, vp(1 << 22), None) == pm.PM_EINVAL    # inv_ld < m
+    assert inv(vp(1 << 20), 8, 63, 8, 2, vp(1 << 21), 8, 64, vp(1 << 22), None) == pm.PM_EINVAL    # overlap
+    assert inv(vp(1 << 20), 8, 64, 8, 2, vp(1 << 21), 8, 63, vp(1 << 22), None) == pm.PM_EINVAL
+    assert inv(None, 8, 64, 8, 1, vp(1 << 21), 8, 64, vp(1 << 22), None) == pm.PM_EINVAL
+    assert inv(vp(1 << 20), 8, 64, 8, 1, vp(1 << 21), 8, 64, None, None) == pm.PM_EINVAL
+    assert inv(vp(1 << 20), 8, 64, 8, 0, vp(1 << 21), 8, 64, vp(1 << 22), None) == pm.PM_OK
+
+
+@pytest.mark.parametrize("kw,ok,K", [
+    (dict(k=8, d=14, n=16), (O.MSR, 8, 14, 16, O.SPARSE), [15, 3, 9, 0, 12, 6, 10, 1]),
+    (dict(k=8, d=14, n=16, kind=pm.PM_MBR), (O.MBR, 8, 14, 16, O.SPARSE), [0, 1, 2, 6, 10, 12, 13, 15]),
+    (dict(k=8, d=8, n=16, kind=pm.PM_RS), (O.RS, 8, 8, 16, O.SPARSE), list(range(8, 16))),
+], ids=["msr8", "mbr8", "rs"])
+def test_host_decode_matrix_matches_the_oracle(kw, ok, K):
+    c = pm.Code(**kw)
+    o = O.Code(*ok[:4], ok[4]) if ok[0] == O.MSR else O.Code(*ok[:4])
+    D, kept = c.decode_matrix(K)
+    Dw, kw_ = o.decode_matrix(K)
+    assert np.array_equal(D, Dw) and kept == list(kw_)
+    L = pm.lib()
+    bad = (ctypes.c_uint32 * c.k)(*([0] * c.k))
+    assert L.pm_decode_matrix(c.h, bad, None, 0, None) == pm.PM_EINVAL
+    good = (ctypes.c_uint32 * c.k)(*K)
+    assert L.pm_decode_matrix(c.h, good, ctypes.c_void_p(1), c.B * c.B - 1, None) == pm.PM_EINVAL
