@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched and served configurations")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--init-only", action="store_true",
+                    help="only run the GPU-side init measurement (batched decode matrices)")
     return ap.parse_args()
 
 
@@ -547,6 +549,10 @@ def main():
         calibrate_copy(torch)
         return
     pm.lib()
+    if args.init_only:
+        print(json.dumps({k: (round(v, 3) if isinstance(v, float) else v)
+                          for k, v in gpu_init_case(torch, pm, synth).items()}), flush=True)
+        return
 
     S = 64 << 20
     head_kw = dict(k=8, d=14, n=16, kind=pm.PM_MSR, construction=pm.PM_SPARSE)
