@@ -51,6 +51,8 @@ def parse():
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--init-only", action="store_true",
                     help="only run the GPU-side init measurement (batched decode matrices)")
+    ap.add_argument("--part", choices=("batched", "served"),
+                    help="only run configuration 4 (batched) or 5 (served) and print its fields")
     return ap.parse_args()
 
 
@@ -552,6 +554,12 @@ def main():
     if args.init_only:
         print(json.dumps({k: (round(v, 3) if isinstance(v, float) else v)
                           for k, v in gpu_init_case(torch, pm, synth).items()}), flush=True)
+        return
+    if args.part == "batched":
+        print(json.dumps({"batched": batched_case(torch, pm, synth, max(5, args.steps // 20))}), flush=True)
+        return
+    if args.part == "served":
+        print(json.dumps({"served": served_case(torch, pm, synth)}), flush=True)
         return
 
     S = 64 << 20
