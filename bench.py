@@ -539,8 +539,8 @@ def cpu_baseline(synth, budget_s=12.0):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the method shards with no exchange; see DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(objects and byte ranges split across GPUs with no exchange).", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1412_3022_amd import pm, synth
