@@ -41,8 +41,10 @@ TABLE_SRC = os.path.join(CSRC, "kernels.hip")
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    # the headline step is ~30 us: a long warmup brings the shader clock up
+    # from idle before timing, and many steps give the sustained rate
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--no-extra", action="store_true", help="headline only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--sweep", action="store_true", help="print the headline kernel time of every variant")

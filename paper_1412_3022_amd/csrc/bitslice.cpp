@@ -14,7 +14,8 @@
 // planes 4-7 that the group's rows need (the "four Russians" table), so every
 // output plane costs one three-input XOR per column.  The 8x8 bit transposes
 // in and out cost 12 masked swaps each.  Rows of a group number at most 8
-// (64 plane accumulators); copy groups move bytes without transposing.
+// (64 plane accumulators), or 16 for a matrix of at most 16 x 16 that is
+// then one group; copy groups move bytes without transposing.
 //
 // Launch geometry: each lane owns 32 bytes of a wave tile (two 16-byte
 // pieces 1 KiB apart, so every load instruction is one contiguous KiB).
