@@ -251,11 +251,13 @@ class Code:
         self.alpha, self.beta, self.B, self.enc_rows = a.value, b.value, B.value, e.value
         self.d = k if kind == PM_RS else d
 
-    def __del__(self):
+    # (sys.is_finalizing is bound when the class is defined: module globals
+    # may already be cleared when a destructor runs at interpreter exit)
+    def __del__(self, _finalizing=sys.is_finalizing):
         h, self.h = getattr(self, "h", None), None
         # At interpreter exit the HIP runtime may already be gone; the process
         # frees everything anyway.
-        if h and _L is not None and not sys.is_finalizing():
+        if h and _L is not None and not _finalizing():
             _L.pm_code_destroy(h)
 
     def matrix(self, which):
@@ -405,9 +407,9 @@ class Batch:
         self.h = h.value
         self.codes = [it["code"] for it in items]   # keep codes alive
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         h, self.h = getattr(self, "h", None), None
-        if h and _L is not None and not sys.is_finalizing():
+        if h and _L is not None and not _finalizing():
             _L.pm_batch_destroy(h)
 
     def info(self):
@@ -498,8 +500,8 @@ class Server:
         if h:
             _lib().pm_server_destroy(h)
 
-    def __del__(self):
-        if not sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if not _finalizing():
             self.close()
 
     def _submit(self, req, keep):
