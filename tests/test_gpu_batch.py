@@ -259,3 +259,45 @@ def test_specialized_k16_encode_single_and_batched():
     b = pm.Batch(items, graph=False, specialize=True)
     b.run()
     _check(items, expected)
+
+
+@pytest.mark.timeout(400)
+def test_config4_full_size_in_the_bench_launch_configuration():
+    """Configuration 4 as bench.py times it: 4096 objects (log-uniform 64 KiB -
+    16 MiB, sparse MSR (4,6), (8,14), (16,30), n = 2k, 12.3 GB of source),
+    the encode kernels prepared in both forms, one graph-captured batch with
+    autotuned tile width; sampled outputs of a seeded sample of objects
+    against the oracle, and a second replay gives the same bytes."""
+    from paper_1412_3022_amd import workloads
+    print("config4 full size", flush=True)
+    objs, codes, inbuf, outbuf = workloads.batched_objects(4096, 64 << 10, 16 << 20, synth.CONFIG_SEED + 3, device())
+    for c in codes.values():
+        assert c.prepare(pm.OP_ENCODE) is True
+        assert c.prepare(pm.OP_ENCODE, batched=True) is True
+    oracles = {k: O.Code(O.MSR, k, c.d, c.n, O.SPARSE) for k, c in codes.items()}
+    batch = pm.Batch([dict(code=o["code"], op="encode", inp=o["X"], out=o["P"], block_bytes=o["s"])
+                      for o in objs], graph=True)
+    batch.autotune(reps=1)
+    units, launches = batch.info()
+    assert launches == 5, launches      # three multi-set bit-sliced kernels + table kernels for short blocks
+    outbuf.fill_(0x5A)
+    batch.run()
+    torch.cuda.synchronize()
+    st = synth.Stream(0xC0F4)
+    sample = sorted(set(st.below(len(objs)) for _ in range(48)))
+    snap = {}
+    for i in sample:
+        o = objs[i]
+        s, c = o["s"], o["code"]
+        pos = np.unique(np.array([0, s - 1] + [st.below(s) for _ in range(96)]))
+        X = o["X"][:, pos].cpu().numpy()
+        got = o["P"][:, pos].cpu().numpy()
+        assert np.array_equal(got, O.apply(oracles[c.k].enc, X)), (i, c.k, s)
+        snap[i] = (pos, got)
+    outbuf.fill_(0x33)
+    batch.run()
+    torch.cuda.synchronize()
+    for i in sample:
+        pos, got = snap[i]
+        assert np.array_equal(objs[i]["P"][:, pos].cpu().numpy(), got), i
+    del batch

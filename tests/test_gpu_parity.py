@@ -191,6 +191,33 @@ def test_config2_encode_64mib_sampled(name, kw):
     _check_sampled(out, o.enc, X, s, seed=len(name))
 
 
+def test_headline_in_the_bench_launch_configuration_sampled():
+    """The headline as bench.py times it: the 64 MiB configuration-2 object
+    (56 x 1198400 B), encode autotuned over every variant on it and then run
+    in the chosen one over 8 buffer sets (the bit-sliced kernel once tuned);
+    sampled outputs of every set against the oracle, and the two timed
+    launch sequences give the same bytes."""
+    kw = dict(k=8, d=14, n=16, kind=pm.PM_MSR, construction=pm.PM_SPARSE)
+    c = pm.Code(**kw)
+    o = _oracle_for(kw)
+    X, s = synth.split_object(64 << 20, c.B, synth.CONFIG_SEED + 1)
+    assert s == 1198400
+    xs = [torch.from_numpy(X).to(device()) for _ in range(2)]
+    outs = [torch.empty((c.enc_rows, s), dtype=torch.uint8, device=device()) for _ in range(2)]
+    stream = torch.cuda.current_stream().cuda_stream
+    st, rg, vec = pm.pm_autotune_encode(c.h, xs[0].data_ptr(), s, outs[0].data_ptr(), s, s, 3, stream)
+    assert st == pm.PM_OK
+    print("headline variant (%d, %d)" % (rg, vec), flush=True)
+    for i in range(6):
+        j = i % 2
+        outs[j].zero_()
+        assert pm.pm_encode(c.h, xs[j].data_ptr(), s, outs[j].data_ptr(), s, s, stream) == pm.PM_OK
+    for j in range(2):
+        _check_sampled(outs[j], o.enc, X, s, seed=100 + j)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1])
+
+
 @pytest.mark.parametrize("name,kw", CFG2, ids=[c[0] for c in CFG2])
 def test_config2_codes_full_compare_small_object(name, kw):
     """The same codes on an object spanning several tiles and a ragged tail."""

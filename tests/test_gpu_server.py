@@ -8,7 +8,7 @@ import pytest
 import torch
 
 from gpu_util import device
-from paper_1412_3022_amd import pm, workloads
+from paper_1412_3022_amd import pm, synth, workloads
 
 pytestmark = pytest.mark.gpu
 
@@ -154,5 +154,53 @@ def test_served_mix_with_specialized_kernels():
                 assert torch.equal(got, q["obj"]["X"])
             srv.release(c["ticket"])
         assert srv.stats()["completed"] == len(reqs)
+    finally:
+        srv.close()
+
+
+@pytest.mark.timeout(400)
+def test_config5_full_size_in_the_bench_configuration():
+    """Configuration 5 as bench.py serves it: the same mix (4 KiB - 64 MiB;
+    MSR (4,6), (8,14), (16,30), MBR (8,14)), the same prepared kernels, a
+    server of 8 streams x 128 requests; 1500 requests replayed as fast as
+    they can be submitted.  Every repair equals the lost node's blocks and
+    every decode the object (whole blocks); encodes are checked against the
+    oracle at sampled byte positions."""
+    import oracle as O
+    from concurrent.futures import ThreadPoolExecutor
+    print("config5 full size", flush=True)
+    wl = workloads.ServeWorkload(synth.CONFIG_SEED + 4, device(), 4 << 10, 64 << 20, resident_per_family=4)
+    jobs = []
+    for name, c in wl.codes.items():
+        jobs.append((c, pm.OP_ENCODE, 0, None))
+        for obj in wl.resident[name]:
+            jobs.append((c, pm.OP_HELPER, obj["failed"], None))
+            jobs.append((c, pm.OP_NEWCOMER, obj["failed"], obj["helpers"]))
+            jobs.append((c, pm.OP_DECODE, 0, obj["K"]))
+    with ThreadPoolExecutor(8) as ex:
+        list(ex.map(lambda j: j[0].prepare(j[1], failed=j[2], ids=j[3], batched=True), jobs))
+    oracles = {}
+    for name, c in wl.codes.items():
+        oracles[c.h] = O.Code(O.MBR, c.k, c.d, c.n) if c.kind == pm.PM_MBR else O.Code(O.MSR, c.k, c.d, c.n, O.SPARSE)
+    reqs, _, _ = wl.requests(1500, rate_per_s=1.0)
+    srv = pm.Server(64 * 10**9, streams=8, max_batch=128, queue_cap=1 << 16)
+    st = synth.Stream(0xC0F5)
+    try:
+        comps = srv.replay(reqs, [0] * len(reqs), keep=True)
+        torch.cuda.synchronize()
+        assert srv.stats()["max_concurrent_batches"] > 1
+        for q, c in zip(reqs, comps):
+            assert c["status"] == pm.PM_OK
+            s = q["block_bytes"]
+            got = _result(c, c["out_blocks"], s)
+            if q["op"] == "repair":
+                assert torch.equal(got, q["obj"]["nodes"][q["failed"]]), s
+            elif q["op"] == "decode":
+                assert torch.equal(got, q["obj"]["X"]), s
+            else:
+                pos = np.unique(np.array([0, s - 1] + [st.below(s) for _ in range(32)]))
+                X = q["X"][:, pos].cpu().numpy()
+                assert np.array_equal(got[:, pos].cpu().numpy(), O.apply(oracles[q["code"].h].enc, X)), s
+            srv.release(c["ticket"])
     finally:
         srv.close()
