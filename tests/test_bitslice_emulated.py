@@ -59,10 +59,10 @@ def test_generated_kernels_match_oracle_on_host(tmp_path, name, kw, ok, f, H, K,
                     assert np.array_equal(got, want), (name, op, multi, P, high)
 
 
-@pytest.mark.parametrize("kw,K", [(dict(k=8, d=14, n=16), list(range(8, 16))),
+@pytest.mark.parametrize("kw,K", [(dict(k=5, d=8, n=10), list(range(5, 10))),
                                   (dict(k=6, d=10, n=12, systematic=False), [0, 2, 4, 6, 8, 10]),
                                   (dict(k=8, d=14, n=16, kind=pm.PM_MBR), [0, 1, 2, 6, 10, 12, 13, 15])],
-                         ids=["msr8-sys", "msr6-nonsys", "mbr8-mixed"])
+                         ids=["msr5-sys", "msr6-nonsys", "mbr8-mixed"])
 def test_specific_decode_factor_kernels_on_host(tmp_path, kw, K):
     """The generated kernels of the specific decode's factor matrices (MSR:
     node times phi products, pair solves, alpha x alpha solves, message
