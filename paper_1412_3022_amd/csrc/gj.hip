@@ -120,7 +120,7 @@ extern "C" __global__ __launch_bounds__(1024) void pm_gj(PmkGj a) {
         // row is zero before column c, so dwords before c / 4 stay zero);
         // keep column c of every row for the updates
         const uint32_t linv = (255u - lg[rows[pr * W + c]]) % 255u;
-        for (uint32_t i = tid; i < m; i += T) fcol[i] = rows[i * W + c];
+        for (uint32_t i = tid; i < m; i += T) fcol[i] = i == pr ? 0 : rows[i * W + c];
         for (uint32_t j4 = c / 4u + tid; j4 < W4; j4 += T) {
             const uint32_t x = rows4[pr * W4 + j4];
             uint32_t y = 0;
@@ -138,24 +138,24 @@ extern "C" __global__ __launch_bounds__(1024) void pm_gj(PmkGj a) {
             }
         }
         __syncthreads();
-        // clear column c from every other row; the pivot row becomes P.  A
-        // thread owns dword column j4 of rows g, g + G, ...: it holds the
-        // eight multiples of P there and selects them by the bits of f_i.
+        // clear column c from every other row (f of the pivot row is 0);
+        // the pivot row becomes P.  A thread owns dword column j4 of rows
+        // g, g + G, ...: it holds the eight multiples of P there and selects
+        // them by the bits of f_i, acc ^ (mask & P) in one three-input op.
         if (g0 < G)
             for (uint32_t j4 = j0; j4 < W4; j4 += cols) {
                 if (j4 < c / 4u) continue;
                 uint32_t P[8];
                 for (uint32_t t = 0; t < 8; ++t) P[t] = pw[t * W4 + j4];
+                if (pr % G == g0) rows4[pr * W4 + j4] = P[0];
                 for (uint32_t i = g0; i < m; i += G) {
-                    if (i == pr) {
-                        rows4[i * W4 + j4] = P[0];
-                        continue;
-                    }
                     const uint32_t f = fcol[i];
                     if (!f) continue;
-                    uint32_t acc = 0;
-                    for (uint32_t t = 0; t < 8; ++t) acc ^= P[t] & (0u - ((f >> t) & 1u));
-                    rows4[i * W4 + j4] ^= acc;
+                    uint32_t acc = rows4[i * W4 + j4];
+                    for (uint32_t t = 0; t < 8; ++t)
+                        acc = __builtin_amdgcn_bitop3_b32(acc, static_cast<uint32_t>(-static_cast<int32_t>((f >> t) & 1u)),
+                                                          P[t], 0x78);
+                    rows4[i * W4 + j4] = acc;
                 }
             }
         if (tid == 0) {

@@ -40,6 +40,13 @@ typedef void *hipStream_t;
 #define hipGetLastError() 0
 
 static inline uint32_t atomicOr(uint32_t *p, uint32_t v) { return std::atomic_ref<uint32_t>(*p).fetch_or(v); }
+// v_bitop3_b32: bit i of the result is bit (a_i << 2 | b_i << 1 | c_i) of imm
+static inline uint32_t __builtin_amdgcn_bitop3_b32(uint32_t a, uint32_t b, uint32_t c, unsigned imm) {
+    uint32_t r = 0;
+    for (unsigned k = 0; k < 8; ++k)
+        if ((imm >> k) & 1u) r |= ((k & 4u) ? a : ~a) & ((k & 2u) ? b : ~b) & ((k & 1u) ? c : ~c);
+    return r;
+}
 static inline uint32_t atomicMin(uint32_t *p, uint32_t v) {
     std::atomic_ref<uint32_t> r(*p);
     uint32_t o = r.load();
