@@ -249,7 +249,9 @@ pm_status pm_set_variant(pm_code *code, int op, uint32_t rows_per_group,
  * bit-sliced variant, generates its bit-sliced kernel and compiles it with
  * hipRTC (seconds; no GPU needed; a no-op when already compiled): the
  * single-set form that the calls above use, or with PM_PREPARE_BATCHED in
- * flags the multi-set form that batches and the server use.  *specialized
+ * flags the multi-set form that batches and the server use.  With a GPU
+ * present it also uploads the operation's tables and loads the kernel on
+ * the current device, so the first data call does neither.  *specialized
  * (may be NULL) = 1 when that kernel is ready, 0 when the table kernel will
  * run (matrix over the size limit, or an explicit table variant).
  * PM_EINVAL for bad ids or flags, PM_EHIP if hipRTC fails. */

@@ -681,6 +681,29 @@ pm_status pm_gf_invert_batch(const uint8_t *A, size_t a_ld, size_t a_stride, uin
     return e == hipSuccess ? PM_OK : static_cast<pm_status>(hip_fail(e));
 }
 
+}  // extern "C"
+
+namespace {
+
+// With a GPU present, the init phase also uploads the table program and
+// loads the compiled kernel (if any) on the current device, so that the
+// first data call after pm_prepare does neither; with none it only compiles.
+int stage_on_device(ProgEntry &pe, BsProgram *bp, BsKind kind) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n == 0) {
+        (void)hipGetLastError();
+        return ST_OK;
+    }
+    const uint32_t *d = nullptr;
+    int st = pe.device_ptr_sync(&d);
+    if (st == ST_OK && bp) st = bs_load(*bp, kind);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
 pm_status pm_prepare(pm_code *c, int op, uint32_t failed, const uint32_t *ids, uint32_t flags, int *specialized) {
     if (specialized) *specialized = 0;
     if (!c || op < 0 || op > 4 || (flags & ~static_cast<uint32_t>(PM_PREPARE_BATCHED))) return PM_EINVAL;
@@ -688,12 +711,13 @@ pm_status pm_prepare(pm_code *c, int op, uint32_t failed, const uint32_t *ids, u
         SpecificOps ops;
         int st = resolve_specific(c, ids, &ops);
         if (st != ST_OK) return static_cast<pm_status>(st);
+        const BsKind kind = (flags & PM_PREPARE_BATCHED) ? BS_MULTI : BS_SINGLE;
         int all = 1;
         for (int p = 0; p < ops.npass; ++p) {
             std::shared_ptr<BsProgram> bp = ops.pe[p]->bitslice();
-            if (!bp) { all = 0; continue; }
-            if ((st = bs_compile(*bp, (flags & PM_PREPARE_BATCHED) ? BS_MULTI : BS_SINGLE)) != ST_OK)
-                return static_cast<pm_status>(st);
+            if (!bp) all = 0;
+            else if ((st = bs_compile(*bp, kind)) != ST_OK) return static_cast<pm_status>(st);
+            if ((st = stage_on_device(*ops.pe[p], bp.get(), kind)) != ST_OK) return static_cast<pm_status>(st);
         }
         if (specialized) *specialized = all;
         return PM_OK;
@@ -701,12 +725,12 @@ pm_status pm_prepare(pm_code *c, int op, uint32_t failed, const uint32_t *ids, u
     Resolved r;
     int st = resolve_op(c, op, failed, ids, &r);
     if (st != ST_OK) return static_cast<pm_status>(st);
-    if (r.vec != kVecAuto && r.vec != kVecBitslice) return PM_OK;   // an explicit table variant
-    std::shared_ptr<BsProgram> bp = r.pe->bitslice();
-    if (!bp) return PM_OK;
-    if ((st = bs_compile(*bp, (flags & PM_PREPARE_BATCHED) ? BS_MULTI : BS_SINGLE)) != ST_OK)
-        return static_cast<pm_status>(st);
-    if (specialized) *specialized = 1;
+    const BsKind kind = (flags & PM_PREPARE_BATCHED) ? BS_MULTI : BS_SINGLE;
+    std::shared_ptr<BsProgram> bp;
+    if (r.vec == kVecAuto || r.vec == kVecBitslice) bp = r.pe->bitslice();   // else an explicit table variant
+    if (bp && (st = bs_compile(*bp, kind)) != ST_OK) return static_cast<pm_status>(st);
+    if ((st = stage_on_device(*r.pe, bp.get(), kind)) != ST_OK) return static_cast<pm_status>(st);
+    if (specialized) *specialized = bp ? 1 : 0;
     return PM_OK;
 }
 
