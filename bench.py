@@ -53,8 +53,9 @@ def parse():
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--init-only", action="store_true",
                     help="only run the GPU-side init measurement (batched decode matrices)")
-    ap.add_argument("--part", choices=("batched", "served"),
-                    help="only run configuration 4 (batched) or 5 (served) and print its fields")
+    ap.add_argument("--part", choices=("batched", "served", "dense"),
+                    help="only run configuration 4 (batched), 5 (served) or the other configuration-2 "
+                         "encodes (dense) and print their fields")
     return ap.parse_args()
 
 
@@ -340,6 +341,24 @@ def msr16_decode_case(torch, pm, synth, steps, warmup):
     return out
 
 
+def dense_config2(torch, pm, synth, S, steps, warmup):
+    """The other encodes of configuration 2 on the same 64 MiB object: the
+    dense non-systematic vanilla form, the vanilla systematic form (dense
+    G'') and RS(16,8); each autotuned, then timed like the headline."""
+    codes = [
+        ("msr_vanilla_nonsys", dict(k=8, d=14, n=16, kind=pm.PM_MSR, construction=pm.PM_VANILLA,
+                                    systematic=False)),
+        ("msr_vanilla_sys", dict(k=8, d=14, n=16, kind=pm.PM_MSR, construction=pm.PM_VANILLA)),
+        ("rs_16_8", dict(k=8, d=8, n=16, kind=pm.PM_RS)),
+    ]
+    out = {}
+    for name, kw in codes:
+        _, r = encode_case(torch, pm, synth, kw, S, synth.CONFIG_SEED + 1, max(20, steps // 4),
+                           max(2, warmup // 4))
+        out[name] = r
+    return out
+
+
 def gpu_init_case(torch, pm, synth):
     """GPU-side init (pm_decode_matrices, batched Gauss-Jordan): the decode
     matrices of every 8-subset of the 16 nodes of the (8,14,16) sparse MSR
@@ -568,6 +587,12 @@ def main():
     if args.part == "served":
         print(json.dumps({"served": served_case(torch, pm, synth)}), flush=True)
         return
+    if args.part == "dense":
+        res = dense_config2(torch, pm, synth, 64 << 20, args.steps, args.warmup)
+        print(json.dumps({name: {"gbps": round(r["gbps"], 2), "kernel_us": round(r["kernel_us"], 3),
+                                 "variant": r["variant"], "alg_bytes_per_launch": r["alg_bytes_per_launch"]}
+                          for name, r in res.items()}), flush=True)
+        return
 
     S = 64 << 20
     head_kw = dict(k=8, d=14, n=16, kind=pm.PM_MSR, construction=pm.PM_SPARSE)
@@ -576,16 +601,9 @@ def main():
     extra = {"headline_kernel_us": round(head["kernel_us"], 3), "headline_variant": head["variant"],
              "headline_event_gbps": round(S / (head["kernel_us"] * 1e-6) / 1e9, 2)}
     if not args.no_extra:
-        others = [
-            ("msr_vanilla_nonsys", dict(k=8, d=14, n=16, kind=pm.PM_MSR, construction=pm.PM_VANILLA,
-                                        systematic=False)),
-            ("msr_vanilla_sys", dict(k=8, d=14, n=16, kind=pm.PM_MSR, construction=pm.PM_VANILLA)),
-            ("rs_16_8", dict(k=8, d=8, n=16, kind=pm.PM_RS)),
-        ]
-        for name, kw in others:
-            _, r = encode_case(torch, pm, synth, kw, S, synth.CONFIG_SEED + 1, max(20, args.steps // 4),
-                               max(2, args.warmup // 4))
+        for name, r in dense_config2(torch, pm, synth, S, args.steps, args.warmup).items():
             extra[name + "_encode_gbps"] = round(r["gbps"], 2)
+            extra[name + "_variant"] = r["variant"]
         extra.update({k: (round(v, 2) if isinstance(v, float) else v)
                       for k, v in msr_repair_decode(torch, pm, synth, args.steps, args.warmup).items()})
         extra.update({k: (round(v, 2) if isinstance(v, float) else v)
