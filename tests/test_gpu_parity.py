@@ -416,3 +416,35 @@ def test_specific_decode_matches_oracle(name, kw, K, prepared):
         xo = out_regions(c.B, s)
         c.decode_specific(K, Y, xo, s)
         assert np.array_equal(read(xo, s), X), s
+
+
+@pytest.mark.timeout(300)
+def test_blocks_larger_than_4_gib():
+    """Maximum sizes: RS(16,8) encode of 8 blocks of 4 GiB + 4112 bytes
+    (34 GB in, 34 GB out), on the table kernel and then on the bit-sliced
+    kernel: byte offsets past 2^32 in every address computation.  Sampled
+    positions (the start, both sides of 2^32, the end) against the oracle."""
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info()
+    if free < 100 * 10**9:
+        pytest.skip("needs about 70 GB of free device memory")
+    print("blocks > 4 GiB", flush=True)
+    c = pm.Code(k=8, d=8, n=16, kind=pm.PM_RS)
+    o = _oracle_for(dict(k=8, d=8, n=16, kind=pm.PM_RS))
+    s = (1 << 32) + 4112
+    X = synth.random_bytes_torch(0x4613, c.B * s, device()).view(c.B, s)
+    out = torch.empty((c.enc_rows, s), dtype=torch.uint8, device=device())
+    st = synth.Stream(0x4614)
+    pos = sorted({0, 1, 2047, (1 << 32) - 16, (1 << 32) - 1, 1 << 32, (1 << 32) + 1, s - 17, s - 16, s - 1} |
+                 {st.below(s) for _ in range(200)})
+    pos_t = torch.tensor(pos, dtype=torch.int64, device=device())
+    Xs = X.index_select(1, pos_t).cpu().numpy()
+    want = O.apply(o.enc, Xs)
+    for prepared in (False, True):
+        if prepared:
+            assert c.prepare(pm.OP_ENCODE) is True
+        out.fill_(0x5A)
+        c.encode(X, out, s)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.index_select(1, pos_t).cpu().numpy(), want), prepared
+    del X, out
