@@ -20,7 +20,7 @@ from itertools import combinations
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "oracle.c")
+_SRCS = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "oracle16.c")]
 _LIB = os.path.join(_HERE, "_liboracle.so")
 
 MSR, MBR, RS = 0, 1, 2
@@ -28,11 +28,12 @@ VANILLA, SPARSE = 0, 1
 
 
 def build(force: bool = False) -> str:
-    """Compile oracle.c with gcc into _liboracle.so (next to the source)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile oracle.c and oracle16.c with gcc into _liboracle.so (next to
+    the sources)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(map(os.path.getmtime, _SRCS)):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC",
-                               "-o", tmp, _SRC, "-lpthread"])
+                               "-o", tmp] + _SRCS + ["-lpthread"])
         os.replace(tmp, _LIB)
     return _LIB
 
