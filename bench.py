@@ -53,9 +53,9 @@ def parse():
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--init-only", action="store_true",
                     help="only run the GPU-side init measurement (batched decode matrices)")
-    ap.add_argument("--part", choices=("batched", "served", "dense"),
-                    help="only run configuration 4 (batched), 5 (served) or the other configuration-2 "
-                         "encodes (dense) and print their fields")
+    ap.add_argument("--part", choices=("batched", "served", "dense", "gf16"),
+                    help="only run configuration 4 (batched), 5 (served), the other configuration-2 "
+                         "encodes (dense) or the GF(2^16) codes (gf16) and print their fields")
     return ap.parse_args()
 
 
@@ -359,6 +359,55 @@ def dense_config2(torch, pm, synth, S, steps, warmup):
     return out
 
 
+def gf16_cases(torch, pm, synth, steps, warmup):
+    """Sparse PM-MSR over GF(2^16) (Section 3.3), 64 MiB objects: systematic
+    encode at k = 8 (n = 16) and k = 16 (n = 32), non-systematic encode at
+    k = 40 (n = 79, beyond the byte field's range), and at k = 8 the repair of node 0 (helper and
+    newcomer) and the decode from the last k nodes, on the GF(2^16) region
+    kernel.  GB/s of source bytes (node bytes for repair and decode)."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream().cuda_stream
+    S = 64 << 20
+    out = {}
+
+    def timed(fn, in_bytes, rows_in, rows_out, s, key):
+        def step(i):
+            st = fn(i)
+            if st != pm.PM_OK:
+                raise pm.PMError(st, key)
+        wall, ev = Timer(torch).run(step, steps, warmup)
+        out[key + "_gbps"] = in_bytes * steps / wall / 1e9
+        out[key + "_kernel_us"] = ev / steps * 1e6
+        out[key + "_hbm_gbps"] = (rows_in + rows_out) * s * steps / ev / 1e9
+
+    for k, n, sys_ in ((8, 16, True), (16, 32, True), (40, 79, False)):
+        code = pm.Code(k=k, d=2 * k - 2, n=n, systematic=sys_, w=16)
+        s = synth.block_bytes_for(S, code.B)
+        xs = [synth.random_bytes_torch(0x1600 + k + j, code.B * s, dev).view(code.B, s) for j in range(NBUF)]
+        outs = [torch.empty((code.enc_rows, s), dtype=torch.uint8, device=dev) for _ in range(NBUF)]
+        code.prepare(pm.OP_ENCODE)
+        key = "gf16_k%d_%s_encode" % (k, "sys" if sys_ else "nonsys")
+        timed(lambda i: pm.pm_encode(code.h, xs[i % NBUF].data_ptr(), s, outs[i % NBUF].data_ptr(), s, s, stream),
+              code.B * s, code.B, code.enc_rows, s, key)
+        if k == 8:
+            f, H, K = 0, list(range(1, 15)), list(range(8, 16))
+            node = torch.empty((code.alpha, s), dtype=torch.uint8, device=dev)
+            recv = torch.empty((code.d, s), dtype=torch.uint8, device=dev)
+            rep_out = torch.empty((code.alpha, s), dtype=torch.uint8, device=dev)
+            Y = torch.empty((code.B, s), dtype=torch.uint8, device=dev)
+            code.prepare(pm.OP_HELPER, failed=f)
+            code.prepare(pm.OP_NEWCOMER, failed=f, ids=H)
+            code.prepare(pm.OP_DECODE, ids=K)
+            timed(lambda i: pm.pm_repair_helper(code.h, f, node.data_ptr(), s, recv.data_ptr(), s, stream),
+                  code.alpha * s, code.alpha, 1, s, "gf16_k8_helper")
+            timed(lambda i: pm.pm_repair_newcomer(code.h, f, H, recv.data_ptr(), s, rep_out.data_ptr(), s, s,
+                                                  stream), code.d * s, code.d, code.alpha, s, "gf16_k8_newcomer")
+            timed(lambda i: pm.pm_decode(code.h, K, Y.data_ptr(), s, xs[i % NBUF].data_ptr(), s, s, stream),
+                  code.B * s, code.B, code.B, s, "gf16_k8_decode")
+        del xs, outs
+    return out
+
+
 def gpu_init_case(torch, pm, synth):
     """GPU-side init (pm_decode_matrices, batched Gauss-Jordan): the decode
     matrices of every 8-subset of the 16 nodes of the (8,14,16) sparse MSR
@@ -587,6 +636,10 @@ def main():
     if args.part == "served":
         print(json.dumps({"served": served_case(torch, pm, synth)}), flush=True)
         return
+    if args.part == "gf16":
+        print(json.dumps({k: round(v, 2) for k, v in gf16_cases(torch, pm, synth, args.steps, args.warmup).items()}),
+              flush=True)
+        return
     if args.part == "dense":
         res = dense_config2(torch, pm, synth, 64 << 20, args.steps, args.warmup)
         print(json.dumps({name: {"gbps": round(r["gbps"], 2), "kernel_us": round(r["kernel_us"], 3),
@@ -612,6 +665,7 @@ def main():
                       for k, v in msr16_decode_case(torch, pm, synth, args.steps, args.warmup).items()})
         extra.update({k: (round(v, 3) if isinstance(v, float) else v)
                       for k, v in gpu_init_case(torch, pm, synth).items()})
+        extra.update({k: round(v, 2) for k, v in gf16_cases(torch, pm, synth, args.steps, args.warmup).items()})
     batched = served = None
     if not args.no_batch:
         batched = batched_case(torch, pm, synth, max(5, args.steps // 20))

@@ -62,7 +62,8 @@ typedef enum {
 } pm_construction;
 
 typedef struct {
-    uint32_t w;            /* field width; only 8 is supported */
+    uint32_t w;            /* field width: 8, or 16 for the sparse PM-MSR code
+                              over GF(2^16) (below) */
     uint32_t k, d, n;      /* MSR: d = 2k-2, n >= d+1 (sparse: n in {2k-1, 2k});
                               MBR: k <= d <= n-1; RS: d ignored, k < n; n <= 255 */
     int32_t kind;          /* pm_kind */
@@ -72,6 +73,22 @@ typedef struct {
     const uint8_t *x;      /* MSR vanilla only: n distinct evaluation points
                               (host memory, copied), NULL = x_i = g^i */
 } pm_params;
+
+/* GF(2^16) codes (w = 16).  Section 3.3 states that the sparse PM-MSR
+ * construction, valid for k up to 39 over GF(2^8), is valid for k up to 64
+ * over GF(2^16).  Field: x^16 + x^12 + x^3 + x + 1 (0x1100B), g = 2.
+ * Only kind PM_MSR with construction PM_SPARSE (n = 2k-1 or 2k, n <= 65535),
+ * systematic or not; others give PM_EUNSUPPORTED.  A block holds 16-bit
+ * symbols, little-endian (symbol p in bytes 2p and 2p+1), so block_bytes must
+ * be even (else PM_EINVAL).  pm_encode, pm_repair_helper, pm_repair_newcomer
+ * and pm_decode run on the GF(2^16) region kernel with the same arguments
+ * as for w = 8; pm_prepare builds the operation's matrix and stages it on the
+ * device (*specialized = 0).  pm_code_matrix writes two bytes per entry,
+ * little-endian (cap counts bytes).  The specific decode, pm_decode_matrix(es),
+ * pm_set_variant, pm_autotune_encode, batches and the server take GF(2^8)
+ * codes only: PM_EUNSUPPORTED.  Building a systematic code inverts a B x B
+ * matrix (B = k(k-1)) on the host, as does each new decode node set: seconds
+ * at k = 40, minutes at k = 64. */
 
 typedef struct pm_code pm_code;
 
@@ -95,7 +112,7 @@ pm_status pm_code_dims(const pm_code *code, uint32_t *alpha, uint32_t *beta,
                        uint32_t *B, uint32_t *enc_rows);
 
 /* Copy a host matrix of the code into host buffer `dst` of `cap` bytes
- * (row-major), and its shape into *rows, *cols.  which: 0 = Psi (n x d; RS:
+ * (row-major; two bytes per entry for w = 16), and its shape into *rows, *cols.  which: 0 = Psi (n x d; RS:
  * the n x k generator), 1 = Lambda (1 x n, MSR), 2 = G linearized
  * (n alpha x B), 3 = the generator node contents follow (G' or G),
  * 4 = the encode matrix (enc_rows x B).  PM_EINVAL if cap is too small. */

@@ -14,6 +14,7 @@
 
 #include "construct.hpp"
 #include "engine.hpp"
+#include "gf16.hpp"
 #include "gj.hpp"
 #include "pm.h"
 #include "program.hpp"
@@ -161,7 +162,7 @@ int check_regions(const void *base, size_t ld, size_t nblocks, size_t s) {
     return ST_OK;
 }
 
-static bool overlaps(const void *a, size_t a_ld, size_t a_n, const void *b, size_t b_ld, size_t b_n,
+bool overlaps(const void *a, size_t a_ld, size_t a_n, const void *b, size_t b_ld, size_t b_n,
                      size_t s) {
     if (!a_n || !b_n) return false;
     const uintptr_t a0 = reinterpret_cast<uintptr_t>(a), a1 = a0 + (a_n - 1) * a_ld + s;
@@ -229,6 +230,8 @@ ProgEntry *apply_program(const Mat &A, int *vec) {
 // ---- the code object -------------------------------------------------------------
 struct pm_code {
     CodeMats m;
+    // GF(2^16) codes keep everything here (m holds only k, d, n, alpha, B)
+    std::unique_ptr<w16::Ctx16> w16;
     std::mutex mu;
     Variant var[4];
     std::map<std::tuple<int>, std::unique_ptr<ProgEntry>> enc;                      // rg
@@ -300,6 +303,7 @@ namespace pmrc {
 // caches the per-failure-pattern matrices (the initialization phase).
 int resolve_op(pm_code *c, int op, uint32_t failed, const uint32_t *ids, Resolved *r) {
     if (!c) return ST_EINVAL;
+    if (c->w16) return ST_EUNSUPPORTED;   // batches and the server take GF(2^8) codes
     const CodeMats &m = c->m;
     if ((op == OPK_HELPER || op == OPK_NEWCOMER) && failed >= static_cast<uint32_t>(m.n)) return ST_EINVAL;
     std::vector<int> list;
@@ -384,6 +388,7 @@ struct SpecificOps {
 
 int resolve_specific(pm_code *c, const uint32_t *ids, SpecificOps *out) {
     if (!c || !ids) return ST_EINVAL;
+    if (c->w16) return ST_EUNSUPPORTED;
     const CodeMats &m = c->m;
     if (m.kind != KIND_MSR && m.kind != KIND_MBR) return ST_EUNSUPPORTED;
     std::vector<int> list(ids, ids + m.k), sorted;
@@ -452,7 +457,7 @@ const char *pm_last_hip_error(void) { return g_hip_msg.c_str(); }
 pm_status pm_code_create(const pm_params *p, pm_code **out) {
     if (!p || !out) return PM_EINVAL;
     *out = nullptr;
-    if (p->w != 8) return PM_EUNSUPPORTED;
+    if (p->w != 8 && p->w != 16) return PM_EUNSUPPORTED;
     if (p->kind < 0 || p->kind > 2) return PM_EINVAL;
     CodeSpec spec;
     spec.kind = p->kind;
@@ -468,6 +473,18 @@ pm_status pm_code_create(const pm_params *p, pm_code **out) {
     }
     try {
         std::unique_ptr<pm_code> c(new pm_code());
+        if (p->w == 16) {
+            c->w16 = std::make_unique<w16::Ctx16>();
+            int st = w16::build_code(spec, c->w16->m);
+            if (st != ST_OK) return static_cast<pm_status>(st);
+            const w16::Code16 &m = c->w16->m;
+            c->m.kind = KIND_MSR;
+            c->m.construction = CONS_SPARSE;
+            c->m.systematic = m.systematic;
+            c->m.k = m.k; c->m.d = m.d; c->m.n = m.n; c->m.alpha = m.alpha; c->m.B = m.B;
+            *out = c.release();
+            return PM_OK;
+        }
         int st = build_code(spec, c->m);
         if (st != ST_OK) return static_cast<pm_status>(st);
         *out = c.release();
@@ -484,12 +501,38 @@ pm_status pm_code_dims(const pm_code *c, uint32_t *alpha, uint32_t *beta, uint32
     if (alpha) *alpha = static_cast<uint32_t>(c->m.alpha);
     if (beta) *beta = 1;
     if (B) *B = static_cast<uint32_t>(c->m.B);
-    if (enc_rows) *enc_rows = static_cast<uint32_t>(c->m.enc.rows);
+    if (enc_rows) *enc_rows = static_cast<uint32_t>(c->w16 ? c->w16->m.enc.rows : c->m.enc.rows);
     return PM_OK;
 }
 
 pm_status pm_code_matrix(const pm_code *c, int which, uint8_t *dst, size_t cap, uint32_t *rows, uint32_t *cols) {
     if (!c) return PM_EINVAL;
+    if (c->w16) {   // two bytes per entry, little-endian
+        const w16::Code16 &m = c->w16->m;
+        w16::Mat16 lam;
+        const w16::Mat16 *M = nullptr;
+        switch (which) {
+            case 0: M = &m.psi; break;
+            case 1:
+                lam = w16::Mat16(1, m.n);
+                std::copy(m.lambda.begin(), m.lambda.end(), lam.v.begin());
+                M = &lam;
+                break;
+            case 2: M = &m.G; break;
+            case 3: M = &m.Gsys; break;
+            case 4: M = &m.enc; break;
+            default: return PM_EINVAL;
+        }
+        if (rows) *rows = static_cast<uint32_t>(M->rows);
+        if (cols) *cols = static_cast<uint32_t>(M->cols);
+        if (!dst) return PM_OK;
+        if (cap < 2 * M->v.size()) return PM_EINVAL;
+        for (size_t i = 0; i < M->v.size(); ++i) {
+            dst[2 * i] = static_cast<uint8_t>(M->v[i]);
+            dst[2 * i + 1] = static_cast<uint8_t>(M->v[i] >> 8);
+        }
+        return PM_OK;
+    }
     const Mat *M = nullptr;
     Mat lam;
     switch (which) {
@@ -514,8 +557,10 @@ pm_status pm_code_matrix(const pm_code *c, int which, uint8_t *dst, size_t cap, 
 }
 
 pm_status pm_code_node_map(const pm_code *c, int32_t *map, size_t cap) {
-    if (!c || !map || cap < c->m.node_map.size()) return PM_EINVAL;
-    std::copy(c->m.node_map.begin(), c->m.node_map.end(), map);
+    if (!c || !map) return PM_EINVAL;
+    const std::vector<int32_t> &nm = c->w16 ? c->w16->m.node_map : c->m.node_map;
+    if (cap < nm.size()) return PM_EINVAL;
+    std::copy(nm.begin(), nm.end(), map);
     return PM_OK;
 }
 
@@ -530,6 +575,7 @@ pm_status pm_set_variant(pm_code *c, int op, uint32_t rg, uint32_t vec) {
         return PM_OK;
     }
     if (!c || op < 0 || op > 3) return PM_EINVAL;
+    if (c->w16) return PM_EUNSUPPORTED;
     std::lock_guard<std::mutex> lk(c->mu);
     c->var[op].rg = static_cast<int>(rg);
     c->var[op].vec = reset ? 0 : static_cast<int>(vec);
@@ -539,7 +585,7 @@ pm_status pm_set_variant(pm_code *c, int op, uint32_t rg, uint32_t vec) {
 
 pm_status pm_decode_specific_workspace(const pm_code *c, size_t s, size_t *bytes) {
     if (!c || !bytes || s == 0) return PM_EINVAL;
-    if (c->m.kind != KIND_MSR && c->m.kind != KIND_MBR) return PM_EUNSUPPORTED;
+    if (c->w16 || (c->m.kind != KIND_MSR && c->m.kind != KIND_MBR)) return PM_EUNSUPPORTED;
     *bytes = specific_ws_blocks(c->m) * ((s + 15) / 16 * 16);
     return PM_OK;
 }
@@ -625,6 +671,7 @@ extern "C" {
 
 pm_status pm_decode_matrix(const pm_code *cc, const uint32_t *nodes, uint8_t *D, size_t cap, uint32_t *kept) {
     if (!cc || !nodes) return PM_EINVAL;
+    if (cc->w16) return PM_EUNSUPPORTED;
     pm_code *c = const_cast<pm_code *>(cc);
     const CodeMats &m = c->m;
     std::vector<int> list(nodes, nodes + m.k), sorted = list;
@@ -651,6 +698,7 @@ pm_status pm_decode_matrix(const pm_code *cc, const uint32_t *nodes, uint8_t *D,
 pm_status pm_decode_matrices(const pm_code *cc, const uint32_t *node_sets, uint32_t count, uint8_t *D,
                              size_t d_stride, uint32_t *kept, int32_t *status, pm_stream stream) {
     if (!cc || !node_sets || !D || !status) return PM_EINVAL;
+    if (cc->w16) return PM_EUNSUPPORTED;
     pm_code *c = const_cast<pm_code *>(cc);
     const CodeMats &m = c->m;
     const uint32_t B = static_cast<uint32_t>(m.B);
@@ -702,11 +750,37 @@ int stage_on_device(ProgEntry &pe, BsProgram *bp, BsKind kind) {
 
 }  // namespace
 
+namespace {
+
+// One data-phase operation of a GF(2^16) code on the GF(2^16) region kernel.
+pm_status run16(const pm_code *cc, int op, uint32_t failed, const uint32_t *ids, const uint8_t *in, size_t in_ld,
+                uint8_t *out, size_t out_ld, size_t s, pm_stream stream) {
+    w16::Prog16 *pe = nullptr;
+    size_t in_n = 0, out_n = 0;
+    int st = w16::resolve16(*const_cast<pm_code *>(cc)->w16, op, failed, ids, &pe, &in_n, &out_n);
+    if (st != ST_OK) return static_cast<pm_status>(st);
+    return static_cast<pm_status>(
+        w16::launch16(*pe, in, in_ld, in_n, out, out_ld, out_n, s, reinterpret_cast<hipStream_t>(stream)));
+}
+
+}  // namespace
+
 extern "C" {
 
 pm_status pm_prepare(pm_code *c, int op, uint32_t failed, const uint32_t *ids, uint32_t flags, int *specialized) {
     if (specialized) *specialized = 0;
     if (!c || op < 0 || op > 4 || (flags & ~static_cast<uint32_t>(PM_PREPARE_BATCHED))) return PM_EINVAL;
+    if (c->w16) {   // the matrix and its program, staged on the device; no specialized kernel
+        if (op == 4 || (flags & PM_PREPARE_BATCHED)) return PM_EUNSUPPORTED;
+        w16::Prog16 *pe = nullptr;
+        size_t in_n = 0, out_n = 0;
+        int st = w16::resolve16(*c->w16, op, failed, ids, &pe, &in_n, &out_n);
+        if (st == ST_OK) {
+            int ndev = 0;
+            if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) st = w16::stage16(*pe);
+        }
+        return static_cast<pm_status>(st);
+    }
     if (op == 4) {   // the passes of the specific decode
         SpecificOps ops;
         int st = resolve_specific(c, ids, &ops);
@@ -737,6 +811,7 @@ pm_status pm_prepare(pm_code *c, int op, uint32_t failed, const uint32_t *ids, u
 pm_status pm_encode(const pm_code *cc, const uint8_t *X, size_t x_ld, uint8_t *out, size_t out_ld,
                     size_t s, pm_stream stream) {
     if (s == 0) return PM_EINVAL;
+    if (cc && cc->w16) return run16(cc, OPK_ENCODE, 0, nullptr, X, x_ld, out, out_ld, s, stream);
     Resolved r;
     int st = resolve_op(const_cast<pm_code *>(cc), OPK_ENCODE, 0, nullptr, &r);
     if (st != ST_OK) return static_cast<pm_status>(st);
@@ -747,6 +822,7 @@ pm_status pm_encode(const pm_code *cc, const uint8_t *X, size_t x_ld, uint8_t *o
 pm_status pm_repair_helper(const pm_code *cc, uint32_t failed, const uint8_t *node, size_t node_ld,
                            uint8_t *out, size_t s, pm_stream stream) {
     if (s == 0) return PM_EINVAL;
+    if (cc && cc->w16) return run16(cc, OPK_HELPER, failed, nullptr, node, node_ld, out, (s + 15) / 16 * 16, s, stream);
     Resolved r;
     int st = resolve_op(const_cast<pm_code *>(cc), OPK_HELPER, failed, nullptr, &r);
     if (st != ST_OK) return static_cast<pm_status>(st);
@@ -758,6 +834,7 @@ pm_status pm_repair_helper(const pm_code *cc, uint32_t failed, const uint8_t *no
 pm_status pm_repair_newcomer(const pm_code *cc, uint32_t failed, const uint32_t *helpers, const uint8_t *recv,
                              size_t recv_ld, uint8_t *out, size_t out_ld, size_t s, pm_stream stream) {
     if (s == 0) return PM_EINVAL;
+    if (cc && cc->w16) return run16(cc, OPK_NEWCOMER, failed, helpers, recv, recv_ld, out, out_ld, s, stream);
     Resolved r;
     int st = resolve_op(const_cast<pm_code *>(cc), OPK_NEWCOMER, failed, helpers, &r);
     if (st != ST_OK) return static_cast<pm_status>(st);
@@ -768,6 +845,7 @@ pm_status pm_repair_newcomer(const pm_code *cc, uint32_t failed, const uint32_t 
 pm_status pm_decode(const pm_code *cc, const uint32_t *nodes, const uint8_t *Y, size_t y_ld, uint8_t *X,
                     size_t x_ld, size_t s, pm_stream stream) {
     if (s == 0) return PM_EINVAL;
+    if (cc && cc->w16) return run16(cc, OPK_DECODE, 0, nodes, Y, y_ld, X, x_ld, s, stream);
     Resolved r;
     int st = resolve_op(const_cast<pm_code *>(cc), OPK_DECODE, 0, nodes, &r);
     if (st != ST_OK) return static_cast<pm_status>(st);
@@ -789,6 +867,7 @@ pm_status pm_apply(const uint8_t *A, uint32_t rows, uint32_t cols, const uint8_t
 pm_status pm_autotune_encode(pm_code *c, const uint8_t *X, size_t x_ld, uint8_t *out, size_t out_ld, size_t s,
                              uint32_t reps, pm_stream stream, uint32_t *best_rg, uint32_t *best_vec) {
     if (!c || s == 0 || reps == 0) return PM_EINVAL;
+    if (c->w16) return PM_EUNSUPPORTED;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     hipEvent_t e0, e1;
     hipError_t e;

@@ -106,6 +106,8 @@ int msr_sparse(const CodeSpec &s, int alpha, Mat &psi, std::vector<uint8_t> &lam
     return ST_OK;
 }
 
+}  // namespace
+
 // Index matrix of PM-MSR: M = [S1; S2], both symmetric alpha x alpha, upper
 // triangles numbered row by row, S1 first (Section 3.1 example).
 std::vector<int> index_msr(int alpha) {
@@ -122,6 +124,8 @@ std::vector<int> index_msr(int alpha) {
     }
     return L;
 }
+
+namespace {
 
 // Index matrix of PM-MBR: M = [[S, T], [T^t, 0]], S symmetric k x k then T
 // k x (d-k), each numbered row by row.

@@ -39,6 +39,10 @@ enum {
 
 int build_code(const CodeSpec &spec, CodeMats &out);
 
+// Index matrix of PM-MSR (2 alpha x alpha, row-major): M = [S1; S2] with the
+// upper triangles of S1 then S2 numbered row by row (Section 3.1).
+std::vector<int> index_msr(int alpha);
+
 // Repair: the helper's projection row (1 x alpha; RS 1 x 1).
 Mat helper_row(const CodeMats &c, int failed);
 // Repair: the newcomer's matrix for helpers H (alpha x d; RS 1 x k).

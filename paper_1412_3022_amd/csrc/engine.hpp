@@ -83,6 +83,9 @@ struct Variant {
 };
 
 int check_regions(const void *base, size_t ld, size_t nblocks, size_t s);
+// Whether two region sets (a_n blocks at a with stride a_ld, b_n at b) of s
+// bytes per block share a byte range.
+bool overlaps(const void *a, size_t a_ld, size_t a_n, const void *b, size_t b_ld, size_t b_n, size_t s);
 int launch_program(ProgEntry &pe, int vec, const uint8_t *in, size_t in_ld, size_t in_n, uint8_t *out,
                    size_t out_ld, size_t out_n, size_t s, hipStream_t stream);
 

@@ -1,0 +1,420 @@
+// GF(2^16) codes (Section 3.3): field, construction, per-operation matrices,
+// and the host side of the GF(2^16) region kernel (gf16.hip).
+#include "gf16.hpp"
+
+#include <algorithm>
+#include <numeric>
+
+#include "gf16k.hpp"
+
+namespace pmrc {
+namespace w16 {
+namespace {
+
+constexpr uint32_t kPoly = 0x1100Bu;
+constexpr int kOrder = 65535;
+
+// exp[e] = g^e for e in [0, 2 * 65535) (so a sum of two logs indexes it),
+// lg[a] = log_g a for a != 0
+struct Field {
+    std::vector<uint16_t> ex;
+    std::vector<int32_t> lg;
+    Field() : ex(2 * kOrder), lg(65536, -1) {
+        uint32_t a = 1;
+        for (int e = 0; e < kOrder; ++e) {
+            ex[e] = ex[e + kOrder] = static_cast<uint16_t>(a);
+            lg[a] = e;
+            a <<= 1;
+            if (a & 0x10000u) a ^= kPoly;
+        }
+    }
+};
+
+const Field &field() {
+    static const Field f;
+    return f;
+}
+
+// Gauss-Jordan on [A | I] in place; rows of the right half become the
+// inverse.  Row updates run in the log domain: the pivot row's logarithms
+// are taken once per pivot.
+bool gauss_jordan(std::vector<uint16_t> &M, int n, int w) {
+    const Field &F = field();
+    std::vector<int32_t> plog(w);
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        while (p < n && M[static_cast<size_t>(p) * w + c] == 0) ++p;
+        if (p == n) return false;
+        if (p != c)
+            std::swap_ranges(M.begin() + static_cast<long>(p) * w, M.begin() + static_cast<long>(p + 1) * w,
+                             M.begin() + static_cast<long>(c) * w);
+        uint16_t *pr = M.data() + static_cast<size_t>(c) * w;
+        const int32_t linv = (kOrder - F.lg[pr[c]]) % kOrder;
+        for (int j = 0; j < w; ++j) {
+            if (pr[j]) {
+                plog[j] = F.lg[pr[j]] + linv;
+                if (plog[j] >= kOrder) plog[j] -= kOrder;
+                pr[j] = F.ex[plog[j]];
+            } else {
+                plog[j] = -1;
+            }
+        }
+        for (int r = 0; r < n; ++r) {
+            uint16_t *row = M.data() + static_cast<size_t>(r) * w;
+            if (r == c || row[c] == 0) continue;
+            const int32_t lf = F.lg[row[c]];
+            for (int j = c; j < w; ++j)
+                if (plog[j] >= 0) row[j] ^= F.ex[lf + plog[j]];
+        }
+    }
+    return true;
+}
+
+bool subsets_invertible(const Mat16 &psi, int must) {
+    const int n = psi.rows, d = psi.cols;
+    std::vector<int> idx(d);
+    std::iota(idx.begin(), idx.end(), 0);
+    Mat16 S(d, d), Si;
+    while (true) {
+        if (must < 0 || std::find(idx.begin(), idx.end(), must) != idx.end()) {
+            for (int i = 0; i < d; ++i)
+                std::copy(psi.v.begin() + static_cast<long>(idx[i]) * d,
+                          psi.v.begin() + static_cast<long>(idx[i] + 1) * d, S.v.begin() + static_cast<long>(i) * d);
+            if (!invert(S, Si)) return false;
+        }
+        int i = d - 1;
+        while (i >= 0 && idx[i] == n - d + i) --i;
+        if (i < 0) return true;
+        ++idx[i];
+        for (int j = i + 1; j < d; ++j) idx[j] = idx[j - 1] + 1;
+    }
+}
+
+bool distinct(std::vector<uint16_t> v) {
+    std::sort(v.begin(), v.end());
+    return std::adjacent_find(v.begin(), v.end()) == v.end();
+}
+
+// Sparse construction (Section 3.3) over GF(2^16): Phi = identity on top of
+// the Cauchy rows 1 / (g^(i + alpha) + g^(j - 1)), Lambda_i = (g^(i + alpha)
+// + 1) / (g^(i + alpha) + g^alpha) (1-based i, j).  At n = 2k the last node's
+// Lambda becomes the first power of g that is new and keeps every helper
+// set holding that node invertible.
+int msr_sparse(int k, int n, Mat16 &psi, std::vector<uint16_t> &lam) {
+    const int alpha = k - 1, d = 2 * alpha;
+    if (n != 2 * k - 1 && n != 2 * k) return ST_EUNSUPPORTED;
+    psi = Mat16(n, d);
+    lam.assign(n, 0);
+    const uint16_t ga = gpow(alpha);
+    for (int i1 = 1; i1 <= n; ++i1) {
+        const uint16_t xi = gpow(i1 + alpha);
+        for (int j1 = 1; j1 <= alpha; ++j1) {
+            uint16_t v = 0;
+            if (i1 <= alpha) {
+                v = i1 == j1 ? 1 : 0;
+            } else {
+                const uint16_t den = xi ^ gpow(j1 - 1);
+                if (!den) return ST_EUNSUPPORTED;
+                v = inv(den);
+            }
+            psi.at(i1 - 1, j1 - 1) = v;
+        }
+        if (!(xi ^ ga)) return ST_EUNSUPPORTED;
+        lam[i1 - 1] = mul(xi ^ 1, inv(xi ^ ga));
+        for (int j = 0; j < alpha; ++j) psi.at(i1 - 1, alpha + j) = mul(lam[i1 - 1], psi.at(i1 - 1, j));
+    }
+    if (n == 2 * k) {
+        const int last = n - 1;
+        bool found = false;
+        for (int t = 0; t < kOrder && !found; ++t) {
+            const uint16_t cand = gpow(t);
+            if (std::find(lam.begin(), lam.begin() + last, cand) != lam.begin() + last) continue;
+            lam[last] = cand;
+            for (int j = 0; j < alpha; ++j) psi.at(last, alpha + j) = mul(cand, psi.at(last, j));
+            found = subsets_invertible(psi, last);
+        }
+        if (!found) return ST_EUNSUPPORTED;
+    }
+    if (!distinct(lam) || !subsets_invertible(psi, -1)) return ST_EUNSUPPORTED;
+    return ST_OK;
+}
+
+}  // namespace
+
+uint16_t mul(uint16_t a, uint16_t b) {
+    if (!a || !b) return 0;
+    const Field &F = field();
+    return F.ex[F.lg[a] + F.lg[b]];
+}
+
+uint16_t inv(uint16_t a) {
+    if (!a) return 0;
+    const Field &F = field();
+    return F.ex[(kOrder - F.lg[a]) % kOrder];
+}
+
+uint16_t gpow(long e) {
+    long r = e % kOrder;
+    if (r < 0) r += kOrder;
+    return field().ex[r];
+}
+
+Mat16 matmul(const Mat16 &A, const Mat16 &B) {
+    Mat16 C(A.rows, B.cols);
+    for (int i = 0; i < A.rows; ++i)
+        for (int t = 0; t < A.cols; ++t) {
+            const uint16_t a = A.at(i, t);
+            if (!a) continue;
+            for (int j = 0; j < B.cols; ++j) C.at(i, j) ^= mul(a, B.at(t, j));
+        }
+    return C;
+}
+
+bool invert(const Mat16 &A, Mat16 &out) {
+    const int n = A.rows, w = 2 * n;
+    if (A.cols != n) return false;
+    std::vector<uint16_t> M(static_cast<size_t>(n) * w, 0);
+    for (int i = 0; i < n; ++i) {
+        std::copy(A.v.begin() + static_cast<long>(i) * n, A.v.begin() + static_cast<long>(i + 1) * n,
+                  M.begin() + static_cast<long>(i) * w);
+        M[static_cast<size_t>(i) * w + n + i] = 1;
+    }
+    if (!gauss_jordan(M, n, w)) return false;
+    out = Mat16(n, n);
+    for (int i = 0; i < n; ++i)
+        std::copy(M.begin() + static_cast<long>(i) * w + n, M.begin() + static_cast<long>(i + 1) * w,
+                  out.v.begin() + static_cast<long>(i) * n);
+    return true;
+}
+
+int build_code(const CodeSpec &s, Code16 &c) {
+    c = Code16();
+    if (s.kind != KIND_MSR || s.construction != CONS_SPARSE || !s.x.empty()) return ST_EUNSUPPORTED;
+    if (s.k < 2 || s.n < s.d + 1 || s.n > 65535) return ST_EINVAL;
+    if (s.d != 2 * s.k - 2) return ST_EUNSUPPORTED;
+    c.k = s.k; c.d = s.d; c.n = s.n;
+    c.alpha = s.k - 1;
+    c.B = s.k * c.alpha;
+    c.systematic = s.systematic ? 1 : 0;
+    int st = msr_sparse(s.k, s.n, c.psi, c.lambda);
+    if (st != ST_OK) return st;
+    c.L = index_msr(c.alpha);
+    // linearization (Section 3.1): G[alpha i + j][L[l][j]] = Psi[i][l]
+    c.G = Mat16(c.n * c.alpha, c.B);
+    for (int i = 0; i < c.n; ++i)
+        for (int j = 0; j < c.alpha; ++j)
+            for (int l = 0; l < c.d; ++l) c.G.at(c.alpha * i + j, c.L[l * c.alpha + j]) ^= c.psi.at(i, l);
+    if (c.systematic) {
+        // G' = G inverse(G~), G~ the first B rows (Section 3.2)
+        Mat16 top(c.B, c.B), topinv;
+        std::copy(c.G.v.begin(), c.G.v.begin() + static_cast<long>(c.B) * c.B, top.v.begin());
+        if (!invert(top, topinv)) return ST_ESINGULAR;
+        c.Gsys = matmul(c.G, topinv);
+        c.enc = Mat16(c.n * c.alpha - c.B, c.B);
+        std::copy(c.Gsys.v.begin() + static_cast<long>(c.B) * c.B, c.Gsys.v.end(), c.enc.v.begin());
+        for (int t = 0; t < c.n * c.alpha; ++t) c.node_map.push_back(t);
+    } else {
+        c.Gsys = c.G;
+        c.enc = c.G;
+        for (int t = 0; t < c.n * c.alpha; ++t) c.node_map.push_back(c.B + t);
+    }
+    return ST_OK;
+}
+
+Mat16 helper_row(const Code16 &c, int f) {
+    Mat16 r(1, c.alpha);
+    for (int a = 0; a < c.alpha; ++a) r.at(0, a) = c.psi.at(f, a);
+    return r;
+}
+
+// [I | lambda_f I] inverse(Psi_H): the newcomer's alpha x d matrix (Section 2).
+int newcomer_matrix(const Code16 &c, int f, const std::vector<int> &H, Mat16 &R) {
+    const int d = c.d;
+    if (static_cast<int>(H.size()) != d) return ST_EINVAL;
+    Mat16 PH(d, d), PHinv;
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) PH.at(i, j) = c.psi.at(H[i], j);
+    if (!invert(PH, PHinv)) return ST_ESINGULAR;
+    R = Mat16(c.alpha, d);
+    for (int a = 0; a < c.alpha; ++a)
+        for (int j = 0; j < d; ++j) R.at(a, j) = PHinv.at(a, j) ^ mul(c.lambda[f], PHinv.at(c.alpha + a, j));
+    return ST_OK;
+}
+
+// The inverse of the k alpha = B generator rows of the nodes K, node-major.
+int decode_matrix(const Code16 &c, const std::vector<int> &K, Mat16 &D) {
+    Mat16 rows(c.B, c.B);
+    for (size_t i = 0; i < K.size(); ++i)
+        for (int j = 0; j < c.alpha; ++j)
+            std::copy(c.Gsys.v.begin() + static_cast<long>(K[i] * c.alpha + j) * c.B,
+                      c.Gsys.v.begin() + static_cast<long>(K[i] * c.alpha + j + 1) * c.B,
+                      rows.v.begin() + static_cast<long>(i * c.alpha + j) * c.B);
+    return invert(rows, D) ? ST_OK : ST_ESINGULAR;
+}
+
+// Groups of kPm16Rows consecutive rows, each with the columns any of its
+// rows reads, in increasing order.
+Prog16::Prog16(const Mat16 &A) : rows(A.rows), cols(A.cols) {
+    const int R = static_cast<int>(kPm16Rows);
+    ngroups = static_cast<uint32_t>((A.rows + R - 1) / R);
+    words.assign(kPm16Header + static_cast<size_t>(ngroups) * (2 + R), 0);
+    words[0] = ngroups;
+    for (uint32_t g = 0; g < ngroups; ++g) {
+        uint32_t *gd = &words[kPm16Header + static_cast<size_t>(g) * (2 + R)];
+        const int r0 = static_cast<int>(g) * R, r1 = std::min(A.rows, r0 + R);
+        std::vector<uint32_t> rec;
+        uint32_t ncols = 0;
+        for (int c = 0; c < A.cols; ++c) {
+            bool any = false;
+            for (int r = r0; r < r1; ++r) any |= A.at(r, c) != 0;
+            if (!any) continue;
+            rec.push_back(static_cast<uint32_t>(c));
+            for (int i = 0; i < R; i += 2) {
+                const uint32_t lo = r0 + i < r1 ? A.at(r0 + i, c) : 0;
+                const uint32_t hi = r0 + i + 1 < r1 ? A.at(r0 + i + 1, c) : 0;
+                rec.push_back(lo | hi << 16);
+            }
+            ++ncols;
+        }
+        gd[0] = static_cast<uint32_t>(words.size());
+        gd[1] = ncols;
+        for (int i = 0; i < R; ++i) gd[2 + i] = r0 + i < r1 ? static_cast<uint32_t>(r0 + i) : kPm16NoRow;
+        words.insert(words.end(), rec.begin(), rec.end());
+        // words may have moved: gd is not used after this point
+    }
+}
+
+namespace {
+
+// The split tables of every field element (layout in gf16k.hpp).
+const std::vector<uint32_t> &tables() {
+    static const std::vector<uint32_t> t = [] {
+        std::vector<uint32_t> w(static_cast<size_t>(65536) * kPm16TableWords, 0);
+        for (uint32_t c = 0; c < 65536u; ++c) {
+            uint32_t *e = &w[static_cast<size_t>(c) * kPm16TableWords];
+            for (uint32_t q = 0; q < 4; ++q)
+                for (uint32_t h = 0; h < 2; ++h) {
+                    uint32_t *slot = e + (2 * q + h) * 4;
+                    for (uint32_t v = 0; v < 8; ++v) {
+                        const uint32_t b = (mul(static_cast<uint16_t>(c), static_cast<uint16_t>(v << (4 * q))) >> (8 * h)) & 0xFFu;
+                        slot[v / 4] |= b << (8 * (v % 4));
+                    }
+                    const uint32_t top = (mul(static_cast<uint16_t>(c), static_cast<uint16_t>(8u << (4 * q))) >> (8 * h)) & 0xFFu;
+                    slot[2] = top * 0x01010101u;
+                }
+        }
+        return w;
+    }();
+    return t;
+}
+
+std::mutex g_tab_mu;
+std::map<int, DevCopy> &g_tab_dev = *new std::map<int, DevCopy>();
+
+int table_ptr(hipStream_t user, const uint32_t **out) {
+    const std::vector<uint32_t> &t = tables();
+    const void *p = nullptr;
+    int st = device_copy(g_tab_mu, g_tab_dev, t.data(), t.size() * sizeof(uint32_t), user, &p);
+    if (st == ST_OK) *out = static_cast<const uint32_t *>(p);
+    return st;
+}
+
+int prog_ptr(Prog16 &p, hipStream_t user, const uint32_t **out) {
+    const void *d = nullptr;
+    int st = device_copy(p.mu, p.dev, p.words.data(), p.words.size() * sizeof(uint32_t), user, &d);
+    if (st == ST_OK) *out = static_cast<const uint32_t *>(d);
+    return st;
+}
+
+}  // namespace
+
+int resolve16(Ctx16 &c, int op, uint32_t failed, const uint32_t *ids, Prog16 **pe, size_t *in_n, size_t *out_n) {
+    const Code16 &m = c.m;
+    if ((op == OPK_HELPER || op == OPK_NEWCOMER) && failed >= static_cast<uint32_t>(m.n)) return ST_EINVAL;
+    std::vector<int> list;
+    if (op == OPK_NEWCOMER || op == OPK_DECODE) {
+        if (!ids) return ST_EINVAL;
+        list.assign(ids, ids + (op == OPK_NEWCOMER ? m.d : m.k));
+        std::vector<int> sorted = list;
+        std::sort(sorted.begin(), sorted.end());
+        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) return ST_EINVAL;
+        for (int v : list)
+            if (v < 0 || v >= m.n || (op == OPK_NEWCOMER && v == static_cast<int>(failed))) return ST_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(c.mu);
+    switch (op) {
+        case OPK_ENCODE:
+            if (!c.enc) c.enc = std::make_unique<Prog16>(m.enc);
+            *pe = c.enc.get();
+            *in_n = static_cast<size_t>(m.B);
+            *out_n = static_cast<size_t>(m.enc.rows);
+            return ST_OK;
+        case OPK_HELPER: {
+            auto &p = c.helper[static_cast<int>(failed)];
+            if (!p) p = std::make_unique<Prog16>(helper_row(m, static_cast<int>(failed)));
+            *pe = p.get();
+            *in_n = static_cast<size_t>(m.alpha);
+            *out_n = 1;
+            return ST_OK;
+        }
+        case OPK_NEWCOMER: {
+            auto &p = c.newcomer[std::make_pair(static_cast<int>(failed), list)];
+            if (!p) {
+                Mat16 R;
+                int st = newcomer_matrix(m, static_cast<int>(failed), list, R);
+                if (st != ST_OK) return st;
+                p = std::make_unique<Prog16>(R);
+            }
+            *pe = p.get();
+            *in_n = static_cast<size_t>(m.d);
+            *out_n = static_cast<size_t>(m.alpha);
+            return ST_OK;
+        }
+        case OPK_DECODE: {
+            auto &p = c.decode[list];
+            if (!p) {
+                Mat16 D;
+                int st = decode_matrix(m, list, D);
+                if (st != ST_OK) return st;
+                p = std::make_unique<Prog16>(D);
+            }
+            *pe = p.get();
+            *in_n = static_cast<size_t>(m.B);
+            *out_n = static_cast<size_t>(m.B);
+            return ST_OK;
+        }
+        default:
+            return ST_EINVAL;
+    }
+}
+
+int stage16(Prog16 &p) {
+    const uint32_t *d = nullptr;
+    int st = table_ptr(nullptr, &d);
+    if (st == ST_OK) st = prog_ptr(p, nullptr, &d);
+    if (st != ST_OK) return st;
+    hipError_t e = hipDeviceSynchronize();
+    return e == hipSuccess ? ST_OK : hip_fail(e);
+}
+
+int launch16(Prog16 &p, const uint8_t *in, size_t in_ld, size_t in_n, uint8_t *out, size_t out_ld, size_t out_n,
+             size_t s, hipStream_t stream) {
+    if (s == 0 || s % 2 != 0) return ST_EINVAL;
+    int st;
+    if ((st = check_regions(in, in_ld, in_n, s)) != ST_OK) return st;
+    if ((st = check_regions(out, out_ld, out_n, s)) != ST_OK) return st;
+    if (overlaps(in, in_ld, in_n, out, out_ld, out_n, s)) return ST_EINVAL;
+    if (p.ngroups == 0) return ST_OK;
+    const uint64_t ntiles = (s + kPm16TileBytes - 1) / kPm16TileBytes;
+    // tile numbers are 32-bit and the grid holds at most 2^31 - 1 work-groups of 4 items
+    if (ntiles > 0xFFFFFFFFull || ntiles * p.ngroups > 0x1FFFFFFFCull) return ST_EINVAL;
+    const uint32_t *dt = nullptr, *dp = nullptr;
+    if ((st = table_ptr(stream, &dt)) != ST_OK) return st;
+    if ((st = prog_ptr(p, stream, &dp)) != ST_OK) return st;
+    PmkApply16 a{in, in_ld, out, out_ld, s, dp, dt, p.ngroups, static_cast<uint32_t>(ntiles)};
+    hipError_t e = pmk_apply16(&a, stream);
+    return e == hipSuccess ? ST_OK : hip_fail(e);
+}
+
+}  // namespace w16
+}  // namespace pmrc

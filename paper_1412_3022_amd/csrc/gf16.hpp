@@ -1,0 +1,85 @@
+// GF(2^16) codes: the sparse PM-MSR construction over GF(2^16) (Section 3.3:
+// valid there for k up to 64, against 39 in GF(2^8)), its matrices, and the
+// host side of the GF(2^16) region kernel.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "construct.hpp"
+#include "engine.hpp"
+
+namespace pmrc {
+namespace w16 {
+
+// Field: x^16 + x^12 + x^3 + x + 1 (0x1100B), generator g = 2: GF-Complete's
+// default GF(2^16).
+uint16_t mul(uint16_t a, uint16_t b);
+uint16_t inv(uint16_t a);
+uint16_t gpow(long e);
+
+// Row-major dense matrix over GF(2^16).
+struct Mat16 {
+    int rows = 0, cols = 0;
+    std::vector<uint16_t> v;
+    Mat16() = default;
+    Mat16(int r, int c) : rows(r), cols(c), v(static_cast<size_t>(r) * c, 0) {}
+    uint16_t &at(int r, int c) { return v[static_cast<size_t>(r) * cols + c]; }
+    uint16_t at(int r, int c) const { return v[static_cast<size_t>(r) * cols + c]; }
+};
+
+Mat16 matmul(const Mat16 &A, const Mat16 &B);
+bool invert(const Mat16 &A, Mat16 &out);
+
+struct Code16 {
+    int k = 0, d = 0, n = 0, alpha = 0, B = 0, systematic = 1;
+    Mat16 psi;                      // n x d
+    std::vector<uint16_t> lambda;   // n
+    std::vector<int> L;             // d x alpha index matrix
+    Mat16 G, Gsys, enc;
+    std::vector<int32_t> node_map;  // as CodeMats::node_map
+};
+
+// Sparse PM-MSR only (d = 2k - 2, n = 2k - 1 or 2k); other kinds and
+// constructions: ST_EUNSUPPORTED.
+int build_code(const CodeSpec &spec, Code16 &out);
+Mat16 helper_row(const Code16 &c, int failed);
+int newcomer_matrix(const Code16 &c, int failed, const std::vector<int> &helpers, Mat16 &R);
+int decode_matrix(const Code16 &c, const std::vector<int> &nodes, Mat16 &D);
+
+// A matrix packed for the kernel, with its per-device copies.
+struct Prog16 {
+    std::vector<uint32_t> words;
+    uint32_t ngroups = 0;
+    int rows = 0, cols = 0;
+    std::mutex mu;
+    std::map<int, DevCopy> dev;
+    explicit Prog16(const Mat16 &A);
+    ~Prog16() { free_device_copies(dev); }
+};
+
+// Everything a GF(2^16) code object holds besides its parameters.
+struct Ctx16 {
+    Code16 m;
+    std::mutex mu;
+    std::unique_ptr<Prog16> enc;
+    std::map<int, std::unique_ptr<Prog16>> helper;
+    std::map<std::pair<int, std::vector<int>>, std::unique_ptr<Prog16>> newcomer;
+    std::map<std::vector<int>, std::unique_ptr<Prog16>> decode;
+};
+
+// The program of one operation (OPK_*), built on first use.  in_n / out_n:
+// the input and output block counts.
+int resolve16(Ctx16 &c, int op, uint32_t failed, const uint32_t *ids, Prog16 **pe, size_t *in_n, size_t *out_n);
+// Upload the program (and the field tables) to the current device and wait.
+int stage16(Prog16 &p);
+// out (out_n blocks) = A in (in_n blocks), s bytes per block (even).
+int launch16(Prog16 &p, const uint8_t *in, size_t in_ld, size_t in_n, uint8_t *out, size_t out_ld, size_t out_n,
+             size_t s, hipStream_t stream);
+
+}  // namespace w16
+}  // namespace pmrc

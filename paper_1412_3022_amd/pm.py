@@ -238,13 +238,15 @@ def _regions(t, rows):
 
 class Code:
     """A PM-MSR / PM-MBR / RS code; data calls take torch uint8 device tensors
-    shaped [blocks, >= block_bytes] (row stride = ld)."""
+    shaped [blocks, >= block_bytes] (row stride = ld).  w = 16 gives the sparse
+    PM-MSR code over GF(2^16), whose blocks hold little-endian 16-bit symbols
+    (block_bytes even); matrix() then returns uint16 arrays."""
 
-    def __init__(self, k, d, n, kind=PM_MSR, construction=PM_SPARSE, systematic=True, x=None):
-        st, h = pm_code_create(k, d, n, kind, construction, systematic, x)
+    def __init__(self, k, d, n, kind=PM_MSR, construction=PM_SPARSE, systematic=True, x=None, w=8):
+        st, h = pm_code_create(k, d, n, kind, construction, systematic, x, w)
         _check(st, "pm_code_create")
         self.h = h
-        self.k, self.n, self.kind = k, n, kind
+        self.k, self.n, self.kind, self.w = k, n, kind, w
         a, b, B, e = (ctypes.c_uint32() for _ in range(4))
         _check(_lib().pm_code_dims(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(B), ctypes.byref(e)),
                "pm_code_dims")
@@ -264,8 +266,8 @@ class Code:
         import numpy as np
         r, c = ctypes.c_uint32(), ctypes.c_uint32()
         _check(_lib().pm_code_matrix(self.h, which, None, 0, ctypes.byref(r), ctypes.byref(c)), "pm_code_matrix")
-        buf = np.zeros((r.value, c.value), np.uint8)
-        _check(_lib().pm_code_matrix(self.h, which, buf.ctypes.data, buf.size, None, None), "pm_code_matrix")
+        buf = np.zeros((r.value, c.value), np.uint16 if self.w == 16 else np.uint8)
+        _check(_lib().pm_code_matrix(self.h, which, buf.ctypes.data, buf.nbytes, None, None), "pm_code_matrix")
         return buf
 
     def node_map(self):

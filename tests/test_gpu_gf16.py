@@ -1,0 +1,180 @@
+"""GPU parity of the GF(2^16) codes (Section 3.3: the sparse PM-MSR code over
+GF(2^16), valid up to k = 64) through the C ABI, against the GF(2^16) oracle,
+symbol for symbol: encode, repair (helper and newcomer), decode, at block
+sizes from one symbol to several wave tiles with ragged tails, a code beyond
+GF(2^8)'s range (k = 40), a 64 MiB object sampled, and blocks past 4 GiB."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import device, out_regions, read, to_regions
+from oracle import gf16 as F
+from paper_1412_3022_amd import pm, synth
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [2, 6, 2048 + 6, 3 * 2048 + 10, 65536 + 2]   # bytes per block (even)
+
+
+def _data(rows, s, seed):
+    return synth.random_bytes(seed, rows * s).reshape(rows, s).copy()
+
+
+def _u16(a):
+    return np.ascontiguousarray(a).view(np.uint16)
+
+
+def _encode(c, X, s):
+    Xd = to_regions(X)
+    out = out_regions(c.enc_rows, s)
+    c.encode(Xd, out, s)
+    return read(out, s)
+
+
+def _nodes(o, X, P):
+    """Node contents (alpha x s bytes each) from the data and the encode output."""
+    Xu, Pu = _u16(X), _u16(P)
+    return {i: o.node_blocks(i, Xu, Pu).view(np.uint8) for i in range(o.n)}
+
+
+CODES = [(4, 8, True), (8, 16, True), (8, 16, False), (8, 15, True)]
+
+
+@pytest.mark.parametrize("k,n,sys_", CODES)
+@pytest.mark.parametrize("s", SIZES)
+def test_encode(k, n, sys_, s):
+    print("gf16 encode", k, n, sys_, s, flush=True)
+    c = pm.Code(k=k, d=2 * k - 2, n=n, systematic=sys_, w=16)
+    o = F.Code(k, n, systematic_form=sys_)
+    X = _data(c.B, s, 1600 + k * 10 + s % 97)
+    got = _encode(c, X, s)
+    assert np.array_equal(_u16(got), o.encode(_u16(X)))
+
+
+@pytest.mark.parametrize("k,n,sys_", [(4, 8, True), (8, 16, True), (8, 16, False)])
+@pytest.mark.parametrize("s", [6, 2048 + 6, 3 * 2048 + 10])
+def test_repair(k, n, sys_, s):
+    print("gf16 repair", k, n, sys_, s, flush=True)
+    c = pm.Code(k=k, d=2 * k - 2, n=n, systematic=sys_, w=16)
+    o = F.Code(k, n, systematic_form=sys_)
+    X = _data(c.B, s, 1700 + k + s % 89)
+    P = _u16(_encode(c, X, s)).view(np.uint8)
+    nodes = _nodes(o, X, P)
+    st = synth.Stream(1701 + k)
+    for f in sorted({0, c.alpha - 1, c.alpha, n - 1, st.below(n)}):
+        H = st.subset(n, c.d, exclude=[f])
+        recv = out_regions(c.d, s)
+        for j, h in enumerate(H):
+            c.repair_helper(f, to_regions(nodes[h]), recv[j:j + 1], s)
+        recv_h = read(recv, s)
+        want_h = np.stack([F.apply(o.helper_row(f), _u16(nodes[h]))[0] for h in H]).view(np.uint8)
+        assert np.array_equal(recv_h, want_h), (f, "helper")
+        out = out_regions(c.alpha, s)
+        c.repair_newcomer(f, H, to_regions(recv_h), out, s)
+        assert np.array_equal(read(out, s), nodes[f]), (f, H)
+
+
+@pytest.mark.parametrize("k,n,sys_", [(4, 8, True), (4, 8, False), (8, 16, True), (8, 16, False)])
+@pytest.mark.parametrize("s", [2, 2048 + 6, 3 * 2048 + 10])
+def test_decode(k, n, sys_, s):
+    print("gf16 decode", k, n, sys_, s, flush=True)
+    c = pm.Code(k=k, d=2 * k - 2, n=n, systematic=sys_, w=16)
+    o = F.Code(k, n, systematic_form=sys_)
+    X = _data(c.B, s, 1800 + k + s % 83)
+    P = _u16(_encode(c, X, s)).view(np.uint8)
+    nodes = _nodes(o, X, P)
+    st = synth.Stream(1801 + k)
+    sets = [list(range(k)), list(range(n - k, n)), st.subset(n, k)]
+    sets.append(list(reversed(st.subset(n, k))))   # node order as given, not sorted
+    for K in sets:
+        Y = np.concatenate([nodes[i] for i in K])
+        out = out_regions(c.B, s)
+        c.decode(K, to_regions(Y), out, s)
+        assert np.array_equal(read(out, s), X), K
+
+
+def test_prepare_stages_the_operation():
+    c = pm.Code(k=4, d=6, n=8, w=16)
+    assert c.prepare(pm.OP_ENCODE) is False          # no specialized kernel for GF(2^16)
+    assert c.prepare(pm.OP_DECODE, ids=[7, 5, 3, 1]) is False
+    o = F.Code(4, 8)
+    s = 4096
+    X = _data(c.B, s, 1901)
+    assert np.array_equal(_u16(_encode(c, X, s)), o.encode(_u16(X)))
+
+
+@pytest.mark.timeout(300)
+def test_k40_beyond_the_byte_field():
+    """k = 40, n = 79 (B = 1560; the construction fails over GF(2^8) here),
+    not systematic: encode every row at a ragged size, and repair one node."""
+    print("gf16 k40", flush=True)
+    k, n, s = 40, 79, 2048 + 14
+    c = pm.Code(k=k, d=2 * k - 2, n=n, systematic=False, w=16)
+    o = F.Code(k, n, systematic_form=False, check=False)
+    X = _data(c.B, s, 1940)
+    P = _encode(c, X, s)
+    assert np.array_equal(_u16(P), o.encode(_u16(X)))
+    nodes = _nodes(o, X, P)
+    f = 41
+    H = [i for i in range(n) if i != f]
+    recv = out_regions(c.d, s)
+    for j, h in enumerate(H):
+        c.repair_helper(f, to_regions(nodes[h]), recv[j:j + 1], s)
+    out = out_regions(c.alpha, s)
+    c.repair_newcomer(f, H, to_regions(read(recv, s)), out, s)
+    assert np.array_equal(read(out, s), nodes[f])
+
+
+@pytest.mark.timeout(300)
+def test_k8_64mib_object_sampled():
+    """Sparse systematic (8, 14, 16) over GF(2^16), a 64 MiB object (56 blocks
+    of 1 198 400 bytes), in the launch the benchmark times: sampled symbol
+    positions (the first, around each wave tile edge, the last) against the
+    oracle."""
+    print("gf16 64MiB", flush=True)
+    c = pm.Code(k=8, d=14, n=16, w=16)
+    o = F.Code(8, 16)
+    s = 1198400
+    X = synth.random_bytes_torch(0x16, c.B * s, device()).view(c.B, s)
+    out = torch.empty((c.enc_rows, s), dtype=torch.uint8, device=device())
+    c.encode(X, out, s)
+    torch.cuda.synchronize()
+    st = synth.Stream(0x17)
+    sym = sorted({0, 1, 1023, 1024, s // 2 - 1} | {st.below(s // 2) for _ in range(300)})
+    idx = torch.tensor([2 * p for p in sym] + [2 * p + 1 for p in sym], dtype=torch.int64, device=device())
+    xs = X.index_select(1, idx).cpu().numpy()
+    got = out.index_select(1, idx).cpu().numpy()
+    m = len(sym)
+    Xs = (xs[:, :m].astype(np.uint16) | xs[:, m:].astype(np.uint16) << 8)
+    want = o.encode(Xs)
+    assert np.array_equal(got[:, :m], (want & 0xFF).astype(np.uint8))
+    assert np.array_equal(got[:, m:], (want >> 8).astype(np.uint8))
+
+
+@pytest.mark.timeout(300)
+def test_blocks_larger_than_4_gib():
+    """Sparse systematic (3, 4, 5) over GF(2^16) with blocks of 4 GiB + 4112
+    bytes (6 blocks in, 4 out: 43 GB): symbols on both sides of byte 2^32."""
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    if free < 60 * 10**9:
+        pytest.skip("needs about 45 GB of free device memory")
+    print("gf16 blocks > 4 GiB", flush=True)
+    c = pm.Code(k=3, d=4, n=5, w=16)
+    o = F.Code(3, 5)
+    s = (1 << 32) + 4112
+    X = synth.random_bytes_torch(0x4616, c.B * s, device()).view(c.B, s)
+    out = torch.empty((c.enc_rows, s), dtype=torch.uint8, device=device())
+    out.fill_(0x5A)
+    c.encode(X, out, s)
+    torch.cuda.synchronize()
+    st = synth.Stream(0x4617)
+    sym = sorted({0, (1 << 31) - 1, 1 << 31, (1 << 31) + 1, s // 2 - 1} | {st.below(s // 2) for _ in range(100)})
+    idx = torch.tensor([2 * p for p in sym] + [2 * p + 1 for p in sym], dtype=torch.int64, device=device())
+    xs = X.index_select(1, idx).cpu().numpy()
+    got = out.index_select(1, idx).cpu().numpy()
+    m = len(sym)
+    want = o.encode(xs[:, :m].astype(np.uint16) | xs[:, m:].astype(np.uint16) << 8)
+    assert np.array_equal(got[:, :m], (want & 0xFF).astype(np.uint8))
+    assert np.array_equal(got[:, m:], (want >> 8).astype(np.uint8))
+    del X, out

@@ -81,7 +81,11 @@ def test_construction_matches_oracle(kw):
     (dict(k=8, d=14, n=14, kind=pm.PM_MSR, construction=pm.PM_SPARSE), pm.PM_EINVAL),
     (dict(k=8, d=14, n=300, kind=pm.PM_MSR, construction=pm.PM_VANILLA), pm.PM_EINVAL),
     (dict(k=8, d=7, n=16, kind=pm.PM_MBR), pm.PM_EINVAL),
-    (dict(k=8, d=14, n=16, kind=pm.PM_MSR, construction=pm.PM_SPARSE, w=16), pm.PM_EUNSUPPORTED),
+    (dict(k=8, d=14, n=16, kind=pm.PM_MSR, construction=pm.PM_SPARSE, w=12), pm.PM_EUNSUPPORTED),
+    (dict(k=8, d=14, n=16, kind=pm.PM_MBR, w=16), pm.PM_EUNSUPPORTED),
+    (dict(k=8, d=8, n=16, kind=pm.PM_RS, w=16), pm.PM_EUNSUPPORTED),
+    (dict(k=8, d=14, n=16, kind=pm.PM_MSR, construction=pm.PM_VANILLA, w=16), pm.PM_EUNSUPPORTED),
+    (dict(k=8, d=14, n=17, kind=pm.PM_MSR, construction=pm.PM_SPARSE, w=16), pm.PM_EUNSUPPORTED),
     (dict(k=3, d=4, n=6, kind=pm.PM_MSR, construction=pm.PM_VANILLA, x=[1, 2, 3, 4, 5, 5]), pm.PM_EINVAL),
 ])
 def test_create_errors(kw, status):
