@@ -289,19 +289,16 @@ namespace {
 // The split tables of every field element (layout in gf16k.hpp).
 const std::vector<uint32_t> &tables() {
     static const std::vector<uint32_t> t = [] {
+        static const uint32_t shift[6] = {0, 3, 6, 8, 11, 14}, values[6] = {8, 8, 4, 8, 8, 4};
         std::vector<uint32_t> w(static_cast<size_t>(65536) * kPm16TableWords, 0);
         for (uint32_t c = 0; c < 65536u; ++c) {
             uint32_t *e = &w[static_cast<size_t>(c) * kPm16TableWords];
-            for (uint32_t q = 0; q < 4; ++q)
-                for (uint32_t h = 0; h < 2; ++h) {
-                    uint32_t *slot = e + (2 * q + h) * 4;
-                    for (uint32_t v = 0; v < 8; ++v) {
-                        const uint32_t b = (mul(static_cast<uint16_t>(c), static_cast<uint16_t>(v << (4 * q))) >> (8 * h)) & 0xFFu;
-                        slot[v / 4] |= b << (8 * (v % 4));
+            for (uint32_t p = 0; p < 6; ++p)
+                for (uint32_t h = 0; h < 2; ++h)
+                    for (uint32_t v = 0; v < values[p]; ++v) {
+                        const uint32_t prod = mul(static_cast<uint16_t>(c), static_cast<uint16_t>(v << shift[p]));
+                        e[4 * p + 2 * h + v / 4] |= ((prod >> (8 * h)) & 0xFFu) << (8 * (v % 4));
                     }
-                    const uint32_t top = (mul(static_cast<uint16_t>(c), static_cast<uint16_t>(8u << (4 * q))) >> (8 * h)) & 0xFFu;
-                    slot[2] = top * 0x01010101u;
-                }
         }
         return w;
     }();

@@ -8,15 +8,13 @@
 // matrix as data, like the split-table kernels of the byte field, instead of
 // compiling it.
 //
-// Multiplication by a constant c is linear over GF(2).  A symbol x is split
-// into four nibbles x = n0 + n1 x^4 + n2 x^8 + n3 x^12, and c*x is the sum
-// of c*(n_q x^(4q)).  Each of those is one byte-lookup per output byte.  The
-// low three bits of a nibble pick from an 8-entry byte table with one
-// v_perm_b32, and its top bit adds the constant c*(8 x^(4q)) under a mask.
-// The tables of every field element sit in one 8 MiB array (32 dwords per
-// element) that the host fills once per device: per (q, output byte h) two
-// dwords of entries 0..7 and one dword holding the top-bit constant in all
-// four bytes.
+// Multiplication by a constant c is linear over GF(2).  Each byte of a
+// symbol x is split into pieces of 3, 3 and 2 bits, x = sum_p v_p x^(e_p)
+// with e_p = 0, 3, 6, 8, 11, 14, and c*x is the sum of c*(v_p x^(e_p)).  A
+// piece has at most 8 values, so each of those products is one v_perm_b32
+// lookup per output byte in an 8-byte table.  The tables of every field
+// element sit in one 8 MiB array (32 dwords per element) that the host fills
+// once per device.
 //
 // Data layout per lane: 8 bytes (4 symbols) per unit, U units 512 bytes
 // apart, so one load instruction of a wave covers 512 contiguous bytes and a
@@ -63,18 +61,16 @@ __device__ __forceinline__ void store_unit(uint8_t *p, uint64_t pos, uint64_t s,
             *reinterpret_cast<uint16_t *>(p + pos + 2u * t) = static_cast<uint16_t>(w[t / 2u] >> (16u * (t % 2u)));
 }
 
-// acc ^ (m & k)
-__device__ __forceinline__ uint32_t xor_and(uint32_t acc, uint32_t m, uint32_t k) {
-    return __builtin_amdgcn_bitop3_b32(acc, m, k, 0x78);
-}
-
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
 template <int R, int U>
 __global__ __launch_bounds__(64 * kWaves) void pm_apply16(PmkApply16 a) {
-    const uint32_t lane = threadIdx.x % 64u, wave = threadIdx.x / 64u;
+    // the wave index is the same in all lanes: made a scalar, so the work
+    // item, the program words and the coefficient tables are read with
+    // scalar loads into SGPRs
+    const uint32_t lane = threadIdx.x % 64u, wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64u);
     const uint32_t nwg = gridDim.x, b = blockIdx.x, per = nwg / 8u;
     const uint32_t wg = b < per * 8u ? (b % 8u) * per + b / 8u : b;
     const uint64_t item = static_cast<uint64_t>(wg) * kWaves + wave;
@@ -93,19 +89,19 @@ __global__ __launch_bounds__(64 * kWaves) void pm_apply16(PmkApply16 a) {
     for (uint32_t j = 0; j < ncols; ++j) {
         const uint32_t *rec = a.prog + off + j * (1u + R / 2);
         const uint8_t *src = a.in + static_cast<uint64_t>(rec[0]) * a.in_ld;
-        uint32_t sel[4][U], msk[4][U];
+        // the six 3/3/2-bit pieces of the 4 symbols of each unit, as byte selectors
+        uint32_t sel[6][U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint2 v = load_unit(src, base + u * 512u, a.s);
             const uint32_t lo = __builtin_amdgcn_perm(v.y, v.x, 0x06040200u);   // low bytes of 4 symbols
             const uint32_t hi = __builtin_amdgcn_perm(v.y, v.x, 0x07050301u);   // high bytes
-            const uint32_t nib[4] = {lo & 0x0F0F0F0Fu, (lo >> 4) & 0x0F0F0F0Fu, hi & 0x0F0F0F0Fu,
-                                     (hi >> 4) & 0x0F0F0F0Fu};
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                sel[q][u] = nib[q] & 0x07070707u;
-                msk[q][u] = ((nib[q] >> 3) & 0x01010101u) * 0xFFu;
-            }
+            sel[0][u] = lo & 0x07070707u;
+            sel[1][u] = (lo >> 3) & 0x07070707u;
+            sel[2][u] = (lo >> 6) & 0x03030303u;
+            sel[3][u] = hi & 0x07070707u;
+            sel[4][u] = (hi >> 3) & 0x07070707u;
+            sel[5][u] = (hi >> 6) & 0x03030303u;
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -114,21 +110,17 @@ __global__ __launch_bounds__(64 * kWaves) void pm_apply16(PmkApply16 a) {
             const uint32_t *t = a.tables + static_cast<uint64_t>(c) * kPm16TableWords;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
+                // piece p, output byte h: table dwords 4p + 2h, 4p + 2h + 1
                 uint32_t l = accL[r][u], h = accH[r][u];
-                l = xor3(l, __builtin_amdgcn_perm(t[1], t[0], sel[0][u]), __builtin_amdgcn_perm(t[9], t[8], sel[1][u]));
-                l = xor3(l, __builtin_amdgcn_perm(t[17], t[16], sel[2][u]),
-                         __builtin_amdgcn_perm(t[25], t[24], sel[3][u]));
-                l = xor_and(l, msk[0][u], t[2]);
-                l = xor_and(l, msk[1][u], t[10]);
-                l = xor_and(l, msk[2][u], t[18]);
-                l = xor_and(l, msk[3][u], t[26]);
-                h = xor3(h, __builtin_amdgcn_perm(t[5], t[4], sel[0][u]), __builtin_amdgcn_perm(t[13], t[12], sel[1][u]));
-                h = xor3(h, __builtin_amdgcn_perm(t[21], t[20], sel[2][u]),
-                         __builtin_amdgcn_perm(t[29], t[28], sel[3][u]));
-                h = xor_and(h, msk[0][u], t[6]);
-                h = xor_and(h, msk[1][u], t[14]);
-                h = xor_and(h, msk[2][u], t[22]);
-                h = xor_and(h, msk[3][u], t[30]);
+                l = xor3(l, __builtin_amdgcn_perm(t[1], t[0], sel[0][u]), __builtin_amdgcn_perm(t[5], t[4], sel[1][u]));
+                l = xor3(l, __builtin_amdgcn_perm(t[9], t[8], sel[2][u]), __builtin_amdgcn_perm(t[13], t[12], sel[3][u]));
+                l = xor3(l, __builtin_amdgcn_perm(t[17], t[16], sel[4][u]),
+                         __builtin_amdgcn_perm(t[21], t[20], sel[5][u]));
+                h = xor3(h, __builtin_amdgcn_perm(t[3], t[2], sel[0][u]), __builtin_amdgcn_perm(t[7], t[6], sel[1][u]));
+                h = xor3(h, __builtin_amdgcn_perm(t[11], t[10], sel[2][u]),
+                         __builtin_amdgcn_perm(t[15], t[14], sel[3][u]));
+                h = xor3(h, __builtin_amdgcn_perm(t[19], t[18], sel[4][u]),
+                         __builtin_amdgcn_perm(t[23], t[22], sel[5][u]));
                 accL[r][u] = l;
                 accH[r][u] = h;
             }

@@ -9,10 +9,10 @@
 // coefficients, two per word (slot 2i in the low half).
 //
 // Tables (device memory): kPm16TableWords dwords per field element c, in
-// element order.  For nibble position q (bits 4q .. 4q + 3 of a symbol) and
-// output byte h, the four dwords at (2q + h) * 4 hold byte h of c * (v x^(4q))
-// for v = 0..7 (two dwords), that byte for v = 8 in each of the four bytes,
-// and zero.
+// element order.  A symbol's bits are cut into six pieces starting at bits
+// e_p = 0, 3, 6, 8, 11, 14 (3, 3, 2, 3, 3, 2 bits).  For piece p and output
+// byte h, the two dwords at 4p + 2h hold byte h of c * (v x^(e_p)) for
+// v = 0..7 (zero for v >= 4 in the 2-bit pieces); dwords 24..31 are zero.
 #pragma once
 #include <hip/hip_runtime.h>
 

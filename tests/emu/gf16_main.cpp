@@ -43,6 +43,8 @@ static inline uint32_t __builtin_amdgcn_perm(uint32_t a, uint32_t b, uint32_t se
     }
     return r;
 }
+// every lane of a wave holds the same value where the kernel reads the first lane's
+static inline uint32_t __builtin_amdgcn_readfirstlane(uint32_t v) { return v; }
 // v_bitop3_b32: bit i of the result is bit (a_i << 2 | b_i << 1 | c_i) of imm
 static inline uint32_t __builtin_amdgcn_bitop3_b32(uint32_t a, uint32_t b, uint32_t c, unsigned imm) {
     uint32_t r = 0;

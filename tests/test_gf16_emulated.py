@@ -37,8 +37,9 @@ def exe(tmp_path_factory):
 
 @pytest.fixture(scope="module")
 def tables():
-    """Byte h of c * (v x^(4q)) for v < 8, and of c * (8 x^(4q)) in all four
-    bytes, per element c (the layout of gf16k.hpp), from the oracle's field."""
+    """Byte h of c * (v x^(e_p)) for the six 3/3/2-bit pieces p of a symbol
+    (e_p = 0, 3, 6, 8, 11, 14), per element c (the layout of gf16k.hpp), from
+    the oracle's field."""
     ex = np.array([F.gpow(e) for e in range(65535)], np.int64)
     lg = np.full(65536, -1, np.int64)
     lg[ex] = np.arange(65535)
@@ -52,14 +53,11 @@ def tables():
         return r
 
     t = np.zeros((65536, 32), np.uint32)
-    for q in range(4):
+    for p, (e, nv) in enumerate(zip((0, 3, 6, 8, 11, 14), (8, 8, 4, 8, 8, 4))):
         for h in range(2):
-            base = (2 * q + h) * 4
-            for v in range(8):
-                b = ((mul(v << (4 * q)) >> (8 * h)) & 0xFF).astype(np.uint32)
-                t[:, base + v // 4] |= b << (8 * (v % 4))
-            top = ((mul(8 << (4 * q)) >> (8 * h)) & 0xFF).astype(np.uint32)
-            t[:, base + 2] = top * 0x01010101
+            for v in range(nv):
+                b = ((mul(v << e) >> (8 * h)) & 0xFF).astype(np.uint32)
+                t[:, 4 * p + 2 * h + v // 4] |= b << (8 * (v % 4))
     return t
 
 
