@@ -362,7 +362,8 @@ def dense_config2(torch, pm, synth, S, steps, warmup):
 def gf16_cases(torch, pm, synth, steps, warmup):
     """Sparse PM-MSR over GF(2^16) (Section 3.3), 64 MiB objects: systematic
     encode at k = 8 (n = 16) and k = 16 (n = 32), non-systematic encode at
-    k = 40 (n = 79, beyond the byte field's range), and at k = 8 the repair of node 0 (helper and
+    k = 40 (n = 79, beyond the byte field's range) and k = 64 (n = 127, the
+    top of the paper's range), and at k = 8 the repair of node 0 (helper and
     newcomer) and the decode from the last k nodes, on the GF(2^16) region
     kernel.  GB/s of source bytes (node bytes for repair and decode)."""
     dev = torch.device("cuda:0")
@@ -380,7 +381,7 @@ def gf16_cases(torch, pm, synth, steps, warmup):
         out[key + "_kernel_us"] = ev / steps * 1e6
         out[key + "_hbm_gbps"] = (rows_in + rows_out) * s * steps / ev / 1e9
 
-    for k, n, sys_ in ((8, 16, True), (16, 32, True), (40, 79, False)):
+    for k, n, sys_ in ((8, 16, True), (16, 32, True), (40, 79, False), (64, 127, False)):
         code = pm.Code(k=k, d=2 * k - 2, n=n, systematic=sys_, w=16)
         s = synth.block_bytes_for(S, code.B)
         xs = [synth.random_bytes_torch(0x1600 + k + j, code.B * s, dev).view(code.B, s) for j in range(NBUF)]

@@ -104,18 +104,18 @@ def test_prepare_stages_the_operation():
 
 
 @pytest.mark.timeout(300)
-def test_k40_beyond_the_byte_field():
-    """k = 40, n = 79 (B = 1560; the construction fails over GF(2^8) here),
-    not systematic: encode every row at a ragged size, and repair one node."""
-    print("gf16 k40", flush=True)
-    k, n, s = 40, 79, 2048 + 14
+@pytest.mark.parametrize("k,n,s,f", [(40, 79, 2048 + 14, 41), (64, 127, 1024 + 6, 100)])
+def test_beyond_the_byte_field(k, n, s, f):
+    """k = 40 (B = 1560; the construction fails over GF(2^8) from here) and
+    k = 64 (B = 4032, the top of the paper's range), not systematic: encode
+    every row at a ragged size, and repair one node from all the others."""
+    print("gf16 beyond GF(2^8)", k, n, s, flush=True)
     c = pm.Code(k=k, d=2 * k - 2, n=n, systematic=False, w=16)
     o = F.Code(k, n, systematic_form=False, check=False)
-    X = _data(c.B, s, 1940)
+    X = _data(c.B, s, 1900 + k)
     P = _encode(c, X, s)
     assert np.array_equal(_u16(P), o.encode(_u16(X)))
     nodes = _nodes(o, X, P)
-    f = 41
     H = [i for i in range(n) if i != f]
     recv = out_regions(c.d, s)
     for j, h in enumerate(H):
