@@ -252,35 +252,45 @@ int decode_matrix(const Code16 &c, const std::vector<int> &K, Mat16 &D) {
     return invert(rows, D) ? ST_OK : ST_ESINGULAR;
 }
 
-// Groups of kPm16Rows consecutive rows, each with the columns any of its
-// rows reads, in increasing order.
+// Groups of kPm16Rows rows, each with the columns any of its rows reads,
+// in increasing order.  Rows are taken in the order of their supports (the
+// sorted lists of columns they read), so rows that read the same columns
+// share a group and its column records: in the linearized generator, the
+// rows alpha i + j of all nodes i read the message symbols of column j of
+// M.  This cuts the records of the k = 8 systematic encode from 392 to 98,
+// and of the k = 64 non-systematic one from 487 760 to 75 612.
 Prog16::Prog16(const Mat16 &A) : rows(A.rows), cols(A.cols) {
     const int R = static_cast<int>(kPm16Rows);
+    std::vector<std::vector<int>> sup(A.rows);
+    for (int r = 0; r < A.rows; ++r)
+        for (int c = 0; c < A.cols; ++c)
+            if (A.at(r, c)) sup[r].push_back(c);
+    std::vector<int> order(A.rows);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sup[a] < sup[b]; });
     ngroups = static_cast<uint32_t>((A.rows + R - 1) / R);
     words.assign(kPm16Header + static_cast<size_t>(ngroups) * (2 + R), 0);
     words[0] = ngroups;
+    std::vector<int> cols_of;
     for (uint32_t g = 0; g < ngroups; ++g) {
-        uint32_t *gd = &words[kPm16Header + static_cast<size_t>(g) * (2 + R)];
-        const int r0 = static_cast<int>(g) * R, r1 = std::min(A.rows, r0 + R);
-        std::vector<uint32_t> rec;
-        uint32_t ncols = 0;
-        for (int c = 0; c < A.cols; ++c) {
-            bool any = false;
-            for (int r = r0; r < r1; ++r) any |= A.at(r, c) != 0;
-            if (!any) continue;
-            rec.push_back(static_cast<uint32_t>(c));
+        const int i0 = static_cast<int>(g) * R, i1 = std::min(A.rows, i0 + R);
+        cols_of.clear();
+        for (int i = i0; i < i1; ++i) cols_of.insert(cols_of.end(), sup[order[i]].begin(), sup[order[i]].end());
+        std::sort(cols_of.begin(), cols_of.end());
+        cols_of.erase(std::unique(cols_of.begin(), cols_of.end()), cols_of.end());
+        const size_t first = words.size();
+        for (int c : cols_of) {
+            words.push_back(static_cast<uint32_t>(c));
             for (int i = 0; i < R; i += 2) {
-                const uint32_t lo = r0 + i < r1 ? A.at(r0 + i, c) : 0;
-                const uint32_t hi = r0 + i + 1 < r1 ? A.at(r0 + i + 1, c) : 0;
-                rec.push_back(lo | hi << 16);
+                const uint32_t lo = i0 + i < i1 ? A.at(order[i0 + i], c) : 0;
+                const uint32_t hi = i0 + i + 1 < i1 ? A.at(order[i0 + i + 1], c) : 0;
+                words.push_back(lo | hi << 16);
             }
-            ++ncols;
         }
-        gd[0] = static_cast<uint32_t>(words.size());
-        gd[1] = ncols;
-        for (int i = 0; i < R; ++i) gd[2 + i] = r0 + i < r1 ? static_cast<uint32_t>(r0 + i) : kPm16NoRow;
-        words.insert(words.end(), rec.begin(), rec.end());
-        // words may have moved: gd is not used after this point
+        uint32_t *gd = &words[kPm16Header + static_cast<size_t>(g) * (2 + R)];
+        gd[0] = static_cast<uint32_t>(first);
+        gd[1] = static_cast<uint32_t>(cols_of.size());
+        for (int i = 0; i < R; ++i) gd[2 + i] = i0 + i < i1 ? static_cast<uint32_t>(order[i0 + i]) : kPm16NoRow;
     }
 }
 
