@@ -96,8 +96,9 @@ int ProgEntry::device_ptr(hipStream_t user, const uint32_t **out) {
     return st;
 }
 
-int ProgEntry::device_ptr_sync(const uint32_t **out) {
-    int st = device_ptr(nullptr, out);
+int device_copy_sync(std::mutex &mu, std::map<int, DevCopy> &dev, const void *host, size_t bytes,
+                     const void **out) {
+    int st = device_copy(mu, dev, host, bytes, nullptr, out);
     if (st != ST_OK) return st;
     int devid = 0;
     hipError_t e = hipGetDevice(&devid);
@@ -109,6 +110,13 @@ int ProgEntry::device_ptr_sync(const uint32_t **out) {
         dc.done = true;
     }
     return ST_OK;
+}
+
+int ProgEntry::device_ptr_sync(const uint32_t **out) {
+    const void *p = nullptr;
+    int st = device_copy_sync(mu, dev, prog.blob.data(), prog.blob.size() * sizeof(uint32_t), &p);
+    if (st == ST_OK) *out = static_cast<const uint32_t *>(p);
+    return st;
 }
 
 std::shared_ptr<BsProgram> ProgEntry::bitslice() {

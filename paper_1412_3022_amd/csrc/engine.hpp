@@ -43,6 +43,10 @@ struct DevCopy {
 // wait for the upload until it is known to be complete.
 int device_copy(std::mutex &mu, std::map<int, DevCopy> &dev, const void *host, size_t bytes, hipStream_t user,
                 const void **out);
+// Same, but returns only once the copy has landed (for plans, graphs and
+// pm_prepare); no stream is made to wait.
+int device_copy_sync(std::mutex &mu, std::map<int, DevCopy> &dev, const void *host, size_t bytes,
+                     const void **out);
 void free_device_copies(std::map<int, DevCopy> &dev);
 
 // A program plus its per-device copies.  device_ptr() uploads on first use

@@ -396,12 +396,11 @@ int resolve16(Ctx16 &c, int op, uint32_t failed, const uint32_t *ids, Prog16 **p
 }
 
 int stage16(Prog16 &p) {
-    const uint32_t *d = nullptr;
-    int st = table_ptr(nullptr, &d);
-    if (st == ST_OK) st = prog_ptr(p, nullptr, &d);
-    if (st != ST_OK) return st;
-    hipError_t e = hipDeviceSynchronize();
-    return e == hipSuccess ? ST_OK : hip_fail(e);
+    const std::vector<uint32_t> &t = tables();
+    const void *d = nullptr;
+    int st = device_copy_sync(g_tab_mu, g_tab_dev, t.data(), t.size() * sizeof(uint32_t), &d);
+    if (st == ST_OK) st = device_copy_sync(p.mu, p.dev, p.words.data(), p.words.size() * sizeof(uint32_t), &d);
+    return st;
 }
 
 int launch16(Prog16 &p, const uint8_t *in, size_t in_ld, size_t in_n, uint8_t *out, size_t out_ld, size_t out_n,

@@ -75,7 +75,8 @@ struct Ctx16 {
 // The program of one operation (OPK_*), built on first use.  in_n / out_n:
 // the input and output block counts.
 int resolve16(Ctx16 &c, int op, uint32_t failed, const uint32_t *ids, Prog16 **pe, size_t *in_n, size_t *out_n);
-// Upload the program (and the field tables) to the current device and wait.
+// Upload the program (and the field tables) to the current device and wait
+// for those copies (no other work is waited for).
 int stage16(Prog16 &p);
 // out (out_n blocks) = A in (in_n blocks), s bytes per block (even).
 int launch16(Prog16 &p, const uint8_t *in, size_t in_ld, size_t in_n, uint8_t *out, size_t out_ld, size_t out_n,
