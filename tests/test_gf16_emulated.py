@@ -115,6 +115,9 @@ CASES = [
     (5, 7, 3, 1.0),
     (9, 6, 1024 + 3, 0.6),
     (20, 12, 3 * 1024 + 5, 0.4),
+    # dense: the first group reads every column with all 8 rows, the second
+    # holds the zero row
+    (16, 9, 1024 + 5, 1.0),
 ]
 
 
