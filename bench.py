@@ -405,6 +405,11 @@ def gf16_cases(torch, pm, synth, steps, warmup):
                                                   stream), code.d * s, code.d, code.alpha, s, "gf16_k8_newcomer")
             timed(lambda i: pm.pm_decode(code.h, K, Y.data_ptr(), s, xs[i % NBUF].data_ptr(), s, s, stream),
                   code.B * s, code.B, code.B, s, "gf16_k8_decode")
+            # half the nodes systematic: their blocks are copied, the lost half computed
+            Km = [0, 1, 2, 3, 12, 13, 14, 15]
+            code.prepare(pm.OP_DECODE, ids=Km)
+            timed(lambda i: pm.pm_decode(code.h, Km, Y.data_ptr(), s, xs[i % NBUF].data_ptr(), s, s, stream),
+                  code.B * s, code.B, code.B, s, "gf16_k8_decode_mixed")
         del xs, outs
     return out
 

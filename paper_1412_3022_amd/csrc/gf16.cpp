@@ -252,28 +252,34 @@ int decode_matrix(const Code16 &c, const std::vector<int> &K, Mat16 &D) {
     return invert(rows, D) ? ST_OK : ST_ESINGULAR;
 }
 
-// Groups of kPm16Rows rows, each with the columns any of its rows reads,
-// in increasing order.  Rows are taken in the order of their supports (the
-// sorted lists of columns they read), so rows that read the same columns
-// share a group and its column records: in the linearized generator, the
-// rows alpha i + j of all nodes i read the message symbols of column j of
-// M.  This cuts the records of the k = 8 systematic encode from 392 to 98,
-// and of the k = 64 non-systematic one from 487 760 to 75 612.
+// Rows that are one input block times 1 (a decode's blocks that the nodes
+// hold as they are: only the lost blocks are computed) form copy groups.
+// The other rows form groups of kPm16Rows, each with the columns any of its
+// rows reads, in increasing order.  Rows are taken in the order of their
+// supports (the sorted lists of columns they read), so rows that read the
+// same columns share a group and its column records: in the linearized
+// generator, the rows alpha i + j of all nodes i read the message symbols of
+// column j of M.  This cuts the records of the k = 8 systematic encode from
+// 392 to 98, and of the k = 64 non-systematic one from 487 760 to 75 612.
 Prog16::Prog16(const Mat16 &A) : rows(A.rows), cols(A.cols) {
     const int R = static_cast<int>(kPm16Rows);
     std::vector<std::vector<int>> sup(A.rows);
-    for (int r = 0; r < A.rows; ++r)
+    std::vector<int> order, copies;
+    for (int r = 0; r < A.rows; ++r) {
         for (int c = 0; c < A.cols; ++c)
             if (A.at(r, c)) sup[r].push_back(c);
-    std::vector<int> order(A.rows);
-    std::iota(order.begin(), order.end(), 0);
+        if (sup[r].size() == 1 && A.at(r, sup[r][0]) == 1) copies.push_back(r);
+        else order.push_back(r);
+    }
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sup[a] < sup[b]; });
-    ngroups = static_cast<uint32_t>((A.rows + R - 1) / R);
+    const int nt = static_cast<int>(order.size()), nc = static_cast<int>(copies.size());
+    const uint32_t ntable = static_cast<uint32_t>((nt + R - 1) / R), ncopy = static_cast<uint32_t>((nc + R - 1) / R);
+    ngroups = ntable + ncopy;
     words.assign(kPm16Header + static_cast<size_t>(ngroups) * (2 + R), 0);
     words[0] = ngroups;
     std::vector<int> cols_of;
-    for (uint32_t g = 0; g < ngroups; ++g) {
-        const int i0 = static_cast<int>(g) * R, i1 = std::min(A.rows, i0 + R);
+    for (uint32_t g = 0; g < ntable; ++g) {
+        const int i0 = static_cast<int>(g) * R, i1 = std::min(nt, i0 + R);
         cols_of.clear();
         for (int i = i0; i < i1; ++i) cols_of.insert(cols_of.end(), sup[order[i]].begin(), sup[order[i]].end());
         std::sort(cols_of.begin(), cols_of.end());
@@ -291,6 +297,15 @@ Prog16::Prog16(const Mat16 &A) : rows(A.rows), cols(A.cols) {
         gd[0] = static_cast<uint32_t>(first);
         gd[1] = static_cast<uint32_t>(cols_of.size());
         for (int i = 0; i < R; ++i) gd[2 + i] = i0 + i < i1 ? static_cast<uint32_t>(order[i0 + i]) : kPm16NoRow;
+    }
+    for (uint32_t q = 0; q < ncopy; ++q) {
+        const int i0 = static_cast<int>(q) * R, i1 = std::min(nc, i0 + R);
+        const size_t first = words.size();
+        for (int i = 0; i < R; ++i) words.push_back(i0 + i < i1 ? static_cast<uint32_t>(sup[copies[i0 + i]][0]) : 0u);
+        uint32_t *gd = &words[kPm16Header + static_cast<size_t>(ntable + q) * (2 + R)];
+        gd[0] = static_cast<uint32_t>(first);
+        gd[1] = kPm16CopyGroup;
+        for (int i = 0; i < R; ++i) gd[2 + i] = i0 + i < i1 ? static_cast<uint32_t>(copies[i0 + i]) : kPm16NoRow;
     }
 }
 

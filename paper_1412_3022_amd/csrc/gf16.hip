@@ -80,6 +80,22 @@ __global__ __launch_bounds__(64 * kWaves) void pm_apply16(PmkApply16 a) {
     const uint32_t off = gd[0], ncols = gd[1];
     const uint64_t base = static_cast<uint64_t>(tile) * (U * 512u) + lane * 8u;
 
+    if (ncols == kPm16CopyGroup) {   // rows that are input blocks as they are
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t row = gd[2 + r];
+            if (row == kPm16NoRow) continue;
+            const uint8_t *src = a.in + static_cast<uint64_t>(a.prog[off + r]) * a.in_ld;
+            uint8_t *dst = a.out + static_cast<uint64_t>(row) * a.out_ld;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint64_t pos = base + u * 512u;
+                if (pos < a.s) store_unit(dst, pos, a.s, load_unit(src, pos, a.s));
+            }
+        }
+        return;
+    }
+
     uint32_t accL[R][U], accH[R][U];
 #pragma unroll
     for (int r = 0; r < R; ++r)

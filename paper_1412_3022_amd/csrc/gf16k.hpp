@@ -6,7 +6,9 @@
 // record, its column count, and the output row of each of its kPm16Rows
 // slots (kPm16NoRow for an unused slot).  A column record is 1 +
 // kPm16Rows / 2 words: the input block, then the slots' 16-bit
-// coefficients, two per word (slot 2i in the low half).
+// coefficients, two per word (slot 2i in the low half).  A copy group
+// (rows that are one input block times 1) has kPm16CopyGroup for its column
+// count and one record of kPm16Rows words: the input block of each slot.
 //
 // Tables (device memory): kPm16TableWords dwords per field element c, in
 // element order.  A symbol's bits are cut into six pieces starting at bits
@@ -24,6 +26,7 @@ constexpr uint32_t kPm16TileBytes = kPm16Units * 512u;   // bytes of a block per
 constexpr uint32_t kPm16Header = 1;
 constexpr uint32_t kPm16TableWords = 32;
 constexpr uint32_t kPm16NoRow = 0xFFFFFFFFu;
+constexpr uint32_t kPm16CopyGroup = 0xFFFFFFFFu;
 
 struct PmkApply16 {
     const uint8_t *in;    // input block c at in + c * in_ld

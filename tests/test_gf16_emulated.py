@@ -62,28 +62,37 @@ def tables():
 
 
 def pack(A):
-    """Program words of matrix A (gf16k.hpp): groups of R consecutive rows."""
+    """Program words of matrix A (gf16k.hpp): rows that are one input block
+    times 1 in copy groups, the others in groups of R in row order."""
     rows, cols = A.shape
-    ng = (rows + R - 1) // R
+    unit = [r for r in range(rows) if (A[r] != 0).sum() == 1 and A[r].max() == 1]
+    rest = [r for r in range(rows) if r not in unit]
+    tgroups = [rest[i:i + R] for i in range(0, len(rest), R)]
+    cgroups = [unit[i:i + R] for i in range(0, len(unit), R)]
+    ng = len(tgroups) + len(cgroups)
     words = [ng] + [0] * (ng * (2 + R))
-    for g in range(ng):
-        r0, r1 = g * R, min(rows, g * R + R)
+    for g, rs in enumerate(tgroups):
         rec, n = [], 0
         for c in range(cols):
-            if not A[r0:r1, c].any():
+            if not A[rs, c].any():
                 continue
             rec.append(c)
             for i in range(0, R, 2):
-                lo = int(A[r0 + i, c]) if r0 + i < r1 else 0
-                hi = int(A[r0 + i + 1, c]) if r0 + i + 1 < r1 else 0
+                lo = int(A[rs[i], c]) if i < len(rs) else 0
+                hi = int(A[rs[i + 1], c]) if i + 1 < len(rs) else 0
                 rec.append(lo | hi << 16)
             n += 1
         gd = 1 + g * (2 + R)
-        words[gd] = len(words)
-        words[gd + 1] = n
+        words[gd], words[gd + 1] = len(words), n
         for i in range(R):
-            words[gd + 2 + i] = r0 + i if r0 + i < r1 else 0xFFFFFFFF
+            words[gd + 2 + i] = rs[i] if i < len(rs) else 0xFFFFFFFF
         words += rec
+    for q, rs in enumerate(cgroups):
+        gd = 1 + (len(tgroups) + q) * (2 + R)
+        words[gd], words[gd + 1] = len(words), 0xFFFFFFFF
+        for i in range(R):
+            words[gd + 2 + i] = rs[i] if i < len(rs) else 0xFFFFFFFF
+        words += [int(np.nonzero(A[r])[0][0]) for r in rs] + [0] * (R - len(rs))
     return np.array(words, np.uint32), ng
 
 
@@ -133,6 +142,25 @@ def test_random_matrices(exe, tmp_path, tables, rows, cols, nsym, dens):
     s = 2 * nsym
     ld = (s + 15) // 16 * 16 + 16
     got = run(exe, tmp_path, tables, A, X, ld, ld + 32)
+    assert np.array_equal(got, F.apply(A, X))
+
+
+def test_copy_groups(exe, tmp_path, tables):
+    """Rows that are an input block as it is (a decode's blocks held by the
+    nodes) go through copy groups; 11 of them fill one group and part of a
+    second, beside computed rows, at a ragged size."""
+    rng = np.random.default_rng(21)
+    rows, cols, nsym = 19, 13, 1024 + 7
+    A = rng.integers(1, 65536, (rows, cols), dtype=np.uint16)
+    A[rng.random((rows, cols)) > 0.5] = 0
+    for r, c in zip(range(0, rows, 2), rng.permutation(cols)):   # 10 unit rows
+        A[r] = 0
+        A[r, c] = 1
+    A[1] = 0
+    A[1, 3] = 1                                # 11th, the same block as another row may read
+    X = rng.integers(0, 65536, (cols, nsym), dtype=np.uint16)
+    ld = (2 * nsym + 15) // 16 * 16
+    got = run(exe, tmp_path, tables, A, X, ld, ld + 16)
     assert np.array_equal(got, F.apply(A, X))
 
 

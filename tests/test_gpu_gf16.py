@@ -178,3 +178,22 @@ def test_blocks_larger_than_4_gib():
     assert np.array_equal(got[:, :m], (want & 0xFF).astype(np.uint8))
     assert np.array_equal(got[:, m:], (want >> 8).astype(np.uint8))
     del X, out
+
+
+def test_batches_and_the_server_refuse_gf16_codes():
+    """Batched plans and the server take GF(2^8) codes only: a GF(2^16) code
+    is refused with PM_EUNSUPPORTED before any work is queued."""
+    c = pm.Code(k=4, d=6, n=8, w=16)
+    s = 4096
+    X = torch.zeros((c.B, s), dtype=torch.uint8, device=device())
+    out = torch.zeros((c.enc_rows, s), dtype=torch.uint8, device=device())
+    with pytest.raises(pm.PMError) as e:
+        pm.Batch([dict(code=c, op="encode", inp=X, out=out, block_bytes=s)], graph=False)
+    assert e.value.status == pm.PM_EUNSUPPORTED
+    srv = pm.Server(1 << 30, streams=1, max_batch=4, queue_cap=16)
+    try:
+        with pytest.raises(pm.PMError) as e:
+            srv.submit_encode(c, X, s)
+        assert e.value.status == pm.PM_EUNSUPPORTED
+    finally:
+        srv.close()
