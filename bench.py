@@ -364,8 +364,9 @@ def gf16_cases(torch, pm, synth, steps, warmup):
     encode at k = 8 (n = 16) and k = 16 (n = 32), non-systematic encode at
     k = 40 (n = 79, beyond the byte field's range) and k = 64 (n = 127, the
     top of the paper's range), and at k = 8 the repair of node 0 (helper and
-    newcomer) and the decode from the last k nodes, on the GF(2^16) region
-    kernel.  GB/s of source bytes (node bytes for repair and decode)."""
+    newcomer) and the decode from the last k nodes and from a half-systematic
+    node set (its held blocks copied), on the GF(2^16) region kernel.  GB/s
+    of source bytes (node bytes for repair and decode)."""
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream().cuda_stream
     S = 64 << 20
