@@ -55,6 +55,8 @@ def lib():
         L.or16_apply.restype = None
         L.or16_newcomer_matrix.argtypes = [u16p, u16p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, u16p]
         L.or16_decode_matrix.argtypes = [u16p, ctypes.c_int, ctypes.c_int, ip, ctypes.c_int, u16p]
+        L.or16_msr_specific_decode.argtypes = [u16p, u16p, ip, ctypes.c_int, ip, pp, ctypes.c_int, pp,
+                                               ctypes.c_size_t]
         L.or16_init()
         _lib = L
     return _lib
@@ -195,6 +197,26 @@ def decode_matrix(Gsys, B, alpha, K):
     return D
 
 
+def msr_specific_decode(psi, lam, L, k, K, Y, systematic_form=True):
+    """Specific PM-MSR decoding from the k nodes K (their k alpha blocks Y,
+    node-major, uint16 symbols); the B data blocks, or None if singular."""
+    K = list(K)
+    if len(K) != k:
+        raise ValueError("K must list k nodes")
+    Y = _c16(Y)
+    alpha = k - 1
+    if Y.shape[0] != k * alpha:
+        raise ValueError("Y must hold k alpha blocks")
+    B = alpha * (alpha + 1)
+    X = np.zeros((B, Y.shape[1]), np.uint16)
+    rc = lib().or16_msr_specific_decode(_u16(_c16(psi)), _u16(_c16(lam)), _i32(np.ascontiguousarray(L, np.int32)), k,
+                                        _i32(np.array(K, np.int32)), _ptrs(list(Y)), 1 if systematic_form else 0,
+                                        _ptrs(list(X)), Y.shape[1])
+    if rc == -2:
+        raise ValueError("Psi is not of the form [Phi, Lambda Phi]")
+    return None if rc != 0 else X
+
+
 class Code:
     """Sparse PM-MSR over GF(2^16) (Section 3.3), systematic (Section 3.2) or
     not.  Attributes as the GF(2^8) oracle's Code: psi, lam, L, G, Gsys, enc,
@@ -248,6 +270,9 @@ class Code:
 
     def decode_matrix(self, K):
         return decode_matrix(self.Gsys, self.B, self.alpha, list(K))
+
+    def decode_specific(self, K, Y):
+        return msr_specific_decode(self.psi, self.lam, self.L, self.k, K, Y, self.Gsys is not self.G)
 
     def decode(self, K, Y):
         D = self.decode_matrix(K)

@@ -10,7 +10,7 @@
  * construction and the data phase of the resulting codes over GF(2^16):
  * the field, dense linear algebra, the sparse Psi and Lambda with their
  * computational validity check, linearization, the systematic form, region
- * multiplication, repair and decode matrices.
+ * multiplication, repair and decode matrices, and the specific PM-MSR decoder.
  *
  * Conventions: matrices are row-major uint16_t arrays; a region holds 16-bit
  * symbols, symbol p in bytes 2p (low byte) and 2p + 1 (high byte).
@@ -318,4 +318,101 @@ int or16_decode_matrix(const uint16_t *Gsys, int B, int alpha, const int *K, int
     int rc = or16_invert(Sel, D, B);
     free(Sel);
     return rc;
+}
+
+/* Specific PM-MSR decoding over GF(2^16): the data collector of the
+ * product-matrix MSR code that Section 4.1 (decoding paragraph) compares with
+ * the linearized decode, symbol by symbol.  Reading (as for GF(2^8): the steps
+ * follow from Psi = [Phi, Lambda Phi], M = [S1; S2] with S1, S2 symmetric,
+ * node i storing phi_i^t S1 + lambda_i phi_i^t S2):
+ *  1. Z[i][j] = y_i . phi_j = P_ij + lambda_i Q_ij for the k nodes of K;
+ *  2. a pair i < j gives Q_ij = (Z[i][j] + Z[j][i]) / (lambda_i + lambda_j)
+ *     and P_ij = Z[i][j] + lambda_i Q_ij;
+ *  3. for each of the first alpha nodes i of K, the alpha values P_ij (j != i)
+ *     are phi_i^t S1 phi_j: an alpha x alpha system with rows phi_j^t gives
+ *     phi_i^t S1 (and phi_i^t S2 from Q);
+ *  4. those rows are Phi_A S1 and Phi_A S2: S1, S2 follow from inverse(Phi_A);
+ *  5. message symbol L[l][j] = M[l][j]; a systematic code stored G Z with
+ *     Z = inverse(G~) X, so X = G~ Z, the product-matrix encoding of Z by the
+ *     first k nodes.
+ * Y: the k alpha blocks of K, node-major; X receives B blocks of nsym symbols.
+ * Returns -1 when a system is singular or two lambda of K are equal, -2 when
+ * Psi does not have the [Phi, Lambda Phi] form. */
+int or16_msr_specific_decode(const uint16_t *psi, const uint16_t *lam, const int *L, int k, const int *K,
+                             const uint8_t *const *Y, int systematic, uint8_t *const *X, size_t nsym)
+{
+    const int alpha = k - 1, d = 2 * alpha, B = alpha * (alpha + 1);
+    for (int i = 0; i < k; i++)
+        for (int a = 0; a < alpha; a++)
+            if (psi[K[i] * d + alpha + a] != or16_mul(lam[K[i]], psi[K[i] * d + a])) return -2;
+    for (int i = 0; i < k; i++)
+        for (int j = i + 1; j < k; j++)
+            if (lam[K[i]] == lam[K[j]]) return -1;
+    size_t aa = (size_t)alpha * alpha;
+    uint16_t *Finv = (uint16_t *)malloc(sizeof(uint16_t) * aa * alpha), *F = (uint16_t *)malloc(sizeof(uint16_t) * aa);
+    uint16_t *PhiA = (uint16_t *)malloc(sizeof(uint16_t) * aa), *PhiAinv = (uint16_t *)malloc(sizeof(uint16_t) * aa);
+    int rc = 0;
+    for (int i = 0; i < alpha && rc == 0; i++) {
+        int r = 0;
+        for (int j = 0; j < k; j++) {
+            if (j == i) continue;
+            memcpy(F + (size_t)r * alpha, psi + (size_t)K[j] * d, sizeof(uint16_t) * alpha);
+            r++;
+        }
+        rc = or16_invert(F, Finv + (size_t)i * aa, alpha);
+    }
+    for (int i = 0; i < alpha; i++) memcpy(PhiA + (size_t)i * alpha, psi + (size_t)K[i] * d, sizeof(uint16_t) * alpha);
+    if (rc == 0) rc = or16_invert(PhiA, PhiAinv, alpha);
+    uint16_t *y = (uint16_t *)malloc(sizeof(uint16_t) * (size_t)k * alpha);
+    uint16_t *z = (uint16_t *)malloc(sizeof(uint16_t) * (size_t)k * k);
+    uint16_t *P = (uint16_t *)malloc(sizeof(uint16_t) * (size_t)k * k), *Q = (uint16_t *)malloc(sizeof(uint16_t) * (size_t)k * k);
+    uint16_t *U = (uint16_t *)malloc(sizeof(uint16_t) * aa), *V = (uint16_t *)malloc(sizeof(uint16_t) * aa);
+    uint16_t *S1 = (uint16_t *)malloc(sizeof(uint16_t) * aa), *S2 = (uint16_t *)malloc(sizeof(uint16_t) * aa);
+    uint16_t *Zm = (uint16_t *)malloc(sizeof(uint16_t) * (size_t)B);
+    uint16_t *pv = (uint16_t *)malloc(sizeof(uint16_t) * alpha), *qv = (uint16_t *)malloc(sizeof(uint16_t) * alpha);
+    for (size_t p = 0; p < nsym && rc == 0; p++) {
+        for (int t = 0; t < k * alpha; t++) y[t] = sym_get(Y[t], p);
+        for (int i = 0; i < k; i++)                                   /* step 1 */
+            for (int j = 0; j < k; j++) {
+                uint16_t acc = 0;
+                for (int a = 0; a < alpha; a++) acc ^= or16_mul(y[i * alpha + a], psi[K[j] * d + a]);
+                z[i * k + j] = acc;
+            }
+        for (int i = 0; i < k; i++)                                   /* step 2 */
+            for (int j = i + 1; j < k; j++) {
+                uint16_t q = or16_div(z[i * k + j] ^ z[j * k + i], lam[K[i]] ^ lam[K[j]]);
+                uint16_t pp = z[i * k + j] ^ or16_mul(lam[K[i]], q);
+                P[i * k + j] = P[j * k + i] = pp;
+                Q[i * k + j] = Q[j * k + i] = q;
+            }
+        for (int i = 0; i < alpha; i++) {                             /* step 3 */
+            int r = 0;
+            for (int j = 0; j < k; j++) {
+                if (j == i) continue;
+                pv[r] = P[i * k + j];
+                qv[r] = Q[i * k + j];
+                r++;
+            }
+            or16_matmul(Finv + (size_t)i * aa, pv, U + (size_t)i * alpha, alpha, alpha, 1);
+            or16_matmul(Finv + (size_t)i * aa, qv, V + (size_t)i * alpha, alpha, alpha, 1);
+        }
+        or16_matmul(PhiAinv, U, S1, alpha, alpha, alpha);             /* step 4 */
+        or16_matmul(PhiAinv, V, S2, alpha, alpha, alpha);
+        for (int l = 0; l < d; l++)                                   /* step 5 */
+            for (int j = 0; j < alpha; j++)
+                Zm[L[l * alpha + j]] = l < alpha ? S1[l * alpha + j] : S2[(l - alpha) * alpha + j];
+        if (!systematic) {
+            for (int m = 0; m < B; m++) sym_put(X[m], p, Zm[m]);
+        } else {
+            for (int i = 0; i < k; i++)
+                for (int j = 0; j < alpha; j++) {
+                    uint16_t acc = 0;
+                    for (int l = 0; l < d; l++) acc ^= or16_mul(psi[i * d + l], Zm[L[l * alpha + j]]);
+                    sym_put(X[i * alpha + j], p, acc);
+                }
+        }
+    }
+    free(Finv); free(F); free(PhiA); free(PhiAinv); free(y); free(z); free(P); free(Q);
+    free(U); free(V); free(S1); free(S2); free(Zm); free(pv); free(qv);
+    return rc == 0 ? 0 : -1;
 }
