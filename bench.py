@@ -365,8 +365,10 @@ def gf16_cases(torch, pm, synth, steps, warmup):
     k = 40 (n = 79, beyond the byte field's range) and k = 64 (n = 127, the
     top of the paper's range), and at k = 8 the repair of node 0 (helper and
     newcomer) and the decode from the last k nodes and from a half-systematic
-    node set (its held blocks copied), on the GF(2^16) region kernel.  GB/s
-    of source bytes (node bytes for repair and decode)."""
+    node set (its held blocks copied), and at k = 40 and 64 the specific
+    decode (and at k = 40 the linearized one) from the last k nodes, on the
+    GF(2^16) region kernel.  GB/s of source bytes (node bytes for repair and
+    decode); init times in seconds."""
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream().cuda_stream
     S = 64 << 20
@@ -411,6 +413,26 @@ def gf16_cases(torch, pm, synth, steps, warmup):
             code.prepare(pm.OP_DECODE, ids=Km)
             timed(lambda i: pm.pm_decode(code.h, Km, Y.data_ptr(), s, xs[i % NBUF].data_ptr(), s, s, stream),
                   code.B * s, code.B, code.B, s, "gf16_k8_decode_mixed")
+        if k >= 40:
+            # decode from the last k nodes: the specific decoder (Section 4.1;
+            # factors need only alpha x alpha inverses) and, at k = 40, the
+            # linearized one (a B x B inverse on the host, 2 s; 30 s at k = 64)
+            K = list(range(n - k, n))
+            Y = torch.empty((code.B, s), dtype=torch.uint8, device=dev)
+            ws = torch.empty(pm.pm_decode_specific_workspace(code.h, s), dtype=torch.uint8, device=dev)
+            t0 = time.time()
+            code.prepare(pm.OP_DECODE_SPECIFIC, ids=K)
+            out["gf16_k%d_specific_decode_init_s" % k] = time.time() - t0
+            timed(lambda i: pm.pm_decode_specific(code.h, K, Y.data_ptr(), s, xs[i % NBUF].data_ptr(), s, s,
+                                                  ws.data_ptr(), ws.numel(), stream),
+                  code.B * s, code.B, code.B, s, "gf16_k%d_specific_decode" % k)
+            if k == 40:
+                t0 = time.time()
+                code.prepare(pm.OP_DECODE, ids=K)
+                out["gf16_k40_linear_decode_init_s"] = time.time() - t0
+                timed(lambda i: pm.pm_decode(code.h, K, Y.data_ptr(), s, xs[i % NBUF].data_ptr(), s, s, stream),
+                      code.B * s, code.B, code.B, s, "gf16_k40_linear_decode")
+            del Y, ws
         del xs, outs
     return out
 

@@ -593,17 +593,20 @@ pm_status pm_set_variant(pm_code *c, int op, uint32_t rg, uint32_t vec) {
 
 pm_status pm_decode_specific_workspace(const pm_code *c, size_t s, size_t *bytes) {
     if (!c || !bytes || s == 0) return PM_EINVAL;
-    if (c->w16 || (c->m.kind != KIND_MSR && c->m.kind != KIND_MBR)) return PM_EUNSUPPORTED;
+    if (c->m.kind != KIND_MSR && c->m.kind != KIND_MBR) return PM_EUNSUPPORTED;
     *bytes = specific_ws_blocks(c->m) * ((s + 15) / 16 * 16);
     return PM_OK;
 }
 
 pm_status pm_decode_specific(const pm_code *cc, const uint32_t *nodes, const uint8_t *Y, size_t y_ld, uint8_t *X,
                              size_t x_ld, size_t s, uint8_t *workspace, size_t workspace_bytes, pm_stream stream) {
-    if (s == 0) return PM_EINVAL;
+    if (s == 0 || !cc) return PM_EINVAL;
     pm_code *c = const_cast<pm_code *>(cc);
+    // GF(2^8): programs of the region engine; GF(2^16): of the GF(2^16) kernel
     SpecificOps ops;
-    int st = resolve_specific(c, nodes, &ops);
+    w16::Prog16 *pe16[kSpecificPasses] = {};
+    int st = c->w16 ? w16::resolve_specific16(*c->w16, nodes, pe16, ops.rows, &ops.npass)
+                    : resolve_specific(c, nodes, &ops);
     if (st != ST_OK) return static_cast<pm_status>(st);
     const CodeMats &m = c->m;
     const size_t ld = (s + 15) / 16 * 16;
@@ -628,8 +631,9 @@ pm_status pm_decode_specific(const pm_code *cc, const uint32_t *nodes, const uin
         const bool last = p == ops.npass - 1;
         uint8_t *out = last ? X : slice;
         const size_t out_ld = last ? x_ld : ld;
-        if ((st = launch_program(*ops.pe[p], kVecAuto, in, in_ld, in_n, out, out_ld, ops.rows[p], s, h)) != ST_OK)
-            return static_cast<pm_status>(st);
+        st = c->w16 ? w16::launch16(*pe16[p], in, in_ld, in_n, out, out_ld, ops.rows[p], s, h)
+                    : launch_program(*ops.pe[p], kVecAuto, in, in_ld, in_n, out, out_ld, ops.rows[p], s, h);
+        if (st != ST_OK) return static_cast<pm_status>(st);
         in = out;
         in_ld = out_ld;
         in_n = static_cast<size_t>(ops.rows[p]);
@@ -640,8 +644,26 @@ pm_status pm_decode_specific(const pm_code *cc, const uint32_t *nodes, const uin
 
 pm_status pm_decode_specific_factor(const pm_code *cc, const uint32_t *nodes, int which, uint8_t *dst, size_t cap,
                                     uint32_t *rows, uint32_t *cols) {
-    if (which < 0 || which >= kSpecificPasses) return PM_EINVAL;
+    if (which < 0 || which >= kSpecificPasses || !cc) return PM_EINVAL;
     pm_code *c = const_cast<pm_code *>(cc);
+    if (c->w16) {   // two bytes per entry, little-endian
+        w16::Prog16 *pe16[kSpecificPasses];
+        int rows16[kSpecificPasses], npass = 0;
+        int st = w16::resolve_specific16(*c->w16, nodes, pe16, rows16, &npass);
+        if (st != ST_OK) return static_cast<pm_status>(st);
+        const w16::Mat16 *F = w16::specific_factor16(*c->w16, nodes, which);
+        if (!F) return PM_EINVAL;
+        if (rows) *rows = static_cast<uint32_t>(F->rows);
+        if (cols) *cols = static_cast<uint32_t>(F->cols);
+        if (dst) {
+            if (cap < 2 * F->v.size()) return PM_EINVAL;
+            for (size_t i = 0; i < F->v.size(); ++i) {
+                dst[2 * i] = static_cast<uint8_t>(F->v[i]);
+                dst[2 * i + 1] = static_cast<uint8_t>(F->v[i] >> 8);
+            }
+        }
+        return PM_OK;
+    }
     SpecificOps ops;
     int st = resolve_specific(c, nodes, &ops);
     if (st != ST_OK) return static_cast<pm_status>(st);
@@ -778,15 +800,16 @@ extern "C" {
 pm_status pm_prepare(pm_code *c, int op, uint32_t failed, const uint32_t *ids, uint32_t flags, int *specialized) {
     if (specialized) *specialized = 0;
     if (!c || op < 0 || op > 4 || (flags & ~static_cast<uint32_t>(PM_PREPARE_BATCHED))) return PM_EINVAL;
-    if (c->w16) {   // the matrix and its program, staged on the device; no specialized kernel
-        if (op == 4 || (flags & PM_PREPARE_BATCHED)) return PM_EUNSUPPORTED;
-        w16::Prog16 *pe = nullptr;
+    if (c->w16) {   // the matrices and their programs, staged on the device; no specialized kernel
+        if (flags & PM_PREPARE_BATCHED) return PM_EUNSUPPORTED;
+        w16::Prog16 *pe[kSpecificPasses] = {};
+        int rows[kSpecificPasses], npass = 1;
         size_t in_n = 0, out_n = 0;
-        int st = w16::resolve16(*c->w16, op, failed, ids, &pe, &in_n, &out_n);
-        if (st == ST_OK) {
-            int ndev = 0;
-            if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) st = w16::stage16(*pe);
-        }
+        int st = op == 4 ? w16::resolve_specific16(*c->w16, ids, pe, rows, &npass)
+                         : w16::resolve16(*c->w16, op, failed, ids, &pe[0], &in_n, &out_n);
+        int ndev = 0;
+        if (st == ST_OK && hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0)
+            for (int p = 0; p < npass && st == ST_OK; ++p) st = w16::stage16(*pe[p]);
         return static_cast<pm_status>(st);
     }
     if (op == 4) {   // the passes of the specific decode

@@ -252,6 +252,90 @@ int decode_matrix(const Code16 &c, const std::vector<int> &K, Mat16 &D) {
     return invert(rows, D) ? ST_OK : ST_ESINGULAR;
 }
 
+// The specific PM-MSR decode from the k nodes K as five factors over
+// GF(2^16), the same factorization as for GF(2^8) (construct.hpp):
+//   F[0] (k(k-1) x k alpha): Z_ij = y_i . phi_j, i != j, rows i-major;
+//   F[1] (B x k(k-1)): P_ij, then Q_ij, of every pair i < j;
+//   F[2] (2 alpha^2 x B): phi_i^t S1 and phi_i^t S2 for the first alpha nodes;
+//   F[3] (B x 2 alpha^2): the message symbols from inverse(Phi_A);
+//   F[4] (B x B): systematic codes only, X = G~ Z.
+int specific_factors(const Code16 &c, const std::vector<int> &K, Mat16 F[kSpecificPasses]) {
+    const int k = c.k, a = c.alpha, d = c.d, B = c.B;
+    if (static_cast<int>(K.size()) != k) return ST_EINVAL;
+    auto phi = [&](int i, int t) { return c.psi.at(K[i], t); };
+    auto lam = [&](int i) { return c.lambda[K[i]]; };
+    const int npairs = k * (k - 1) / 2;
+    std::vector<std::vector<int>> zrow(k, std::vector<int>(k, -1)), pair_of(k, std::vector<int>(k, -1));
+    Mat16 Zm(k * (k - 1), k * a);
+    int zr = 0;
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) {
+            if (j == i) continue;
+            zrow[i][j] = zr;
+            for (int t = 0; t < a; ++t) Zm.at(zr, i * a + t) = phi(j, t);
+            ++zr;
+        }
+    // Q_ij = cc (Z_ij + Z_ji), P_ij = lambda_j cc Z_ij + lambda_i cc Z_ji,
+    // cc = 1 / (lambda_i + lambda_j)
+    Mat16 A(B, k * (k - 1));
+    int q = 0;
+    for (int i = 0; i < k; ++i)
+        for (int j = i + 1; j < k; ++j, ++q) {
+            const uint16_t sum = lam(i) ^ lam(j);
+            if (!sum) return ST_ESINGULAR;
+            const uint16_t cc = inv(sum);
+            pair_of[i][j] = pair_of[j][i] = q;
+            A.at(q, zrow[i][j]) = mul(lam(j), cc);
+            A.at(q, zrow[j][i]) = mul(lam(i), cc);
+            A.at(npairs + q, zrow[i][j]) = cc;
+            A.at(npairs + q, zrow[j][i]) = cc;
+        }
+    // phi_i^t S1 (S2) from the alpha values P_ij (Q_ij), j != i in order
+    Mat16 Bm(2 * a * a, B);
+    for (int i = 0; i < a; ++i) {
+        Mat16 Fi(a, a), Fi_inv;
+        std::vector<int> js;
+        for (int j = 0; j < k; ++j)
+            if (j != i) js.push_back(j);
+        for (int r = 0; r < a; ++r)
+            for (int t = 0; t < a; ++t) Fi.at(r, t) = phi(js[r], t);
+        if (!invert(Fi, Fi_inv)) return ST_ESINGULAR;
+        for (int b = 0; b < a; ++b)
+            for (int r = 0; r < a; ++r) {
+                const int qp = pair_of[i][js[r]];
+                Bm.at(i * a + b, qp) = Fi_inv.at(b, r);
+                Bm.at(a * a + i * a + b, npairs + qp) = Fi_inv.at(b, r);
+            }
+    }
+    // S1 = inverse(Phi_A) U, S2 = inverse(Phi_A) V; symbol L[l][j] = M[l][j]
+    Mat16 PhiA(a, a), PhiA_inv;
+    for (int i = 0; i < a; ++i)
+        for (int t = 0; t < a; ++t) PhiA.at(i, t) = phi(i, t);
+    if (!invert(PhiA, PhiA_inv)) return ST_ESINGULAR;
+    Mat16 Cm(B, 2 * a * a);
+    std::vector<char> done(B, 0);
+    for (int l = 0; l < d; ++l)
+        for (int j = 0; j < a; ++j) {
+            const int m = c.L[l * a + j];
+            if (done[m]) continue;
+            done[m] = 1;
+            const int half = l < a ? 0 : 1, row = l % a;
+            for (int i = 0; i < a; ++i) Cm.at(m, half * a * a + i * a + j) = PhiA_inv.at(row, i);
+        }
+    F[0] = std::move(Zm);
+    F[1] = std::move(A);
+    F[2] = std::move(Bm);
+    F[3] = std::move(Cm);
+    if (c.systematic) {
+        Mat16 Gt(B, B);
+        std::copy(c.G.v.begin(), c.G.v.begin() + static_cast<long>(B) * B, Gt.v.begin());
+        F[4] = std::move(Gt);
+    } else {
+        F[4] = Mat16();
+    }
+    return ST_OK;
+}
+
 // Rows that are one input block times 1 (a decode's blocks that the nodes
 // hold as they are: only the lost blocks are computed) form copy groups.
 // The other rows form groups of kPm16Rows, each with the columns any of its
@@ -408,6 +492,43 @@ int resolve16(Ctx16 &c, int op, uint32_t failed, const uint32_t *ids, Prog16 **p
         default:
             return ST_EINVAL;
     }
+}
+
+int resolve_specific16(Ctx16 &c, const uint32_t *ids, Prog16 *pe[kSpecificPasses], int rows[kSpecificPasses],
+                       int *npass) {
+    const Code16 &m = c.m;
+    if (!ids) return ST_EINVAL;
+    std::vector<int> list(ids, ids + m.k), sorted = list;
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) return ST_EINVAL;
+    for (int v : list)
+        if (v < 0 || v >= m.n) return ST_EINVAL;
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.specific.find(list);
+    if (it == c.specific.end()) {
+        Mat16 F[kSpecificPasses];
+        int st = specific_factors(m, list, F);
+        if (st != ST_OK) return st;
+        Ctx16::Specific sp;
+        for (int p = 0; p < kSpecificPasses; ++p) {
+            sp.F[p] = std::move(F[p]);
+            if (sp.F[p].rows) sp.prog[p] = std::make_unique<Prog16>(sp.F[p]);
+        }
+        it = c.specific.emplace(list, std::move(sp)).first;
+    }
+    *npass = 0;
+    while (*npass < kSpecificPasses && it->second.F[*npass].rows) {
+        pe[*npass] = it->second.prog[*npass].get();
+        rows[*npass] = it->second.F[*npass].rows;
+        ++*npass;
+    }
+    return ST_OK;
+}
+
+const Mat16 *specific_factor16(Ctx16 &c, const uint32_t *ids, int which) {
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.specific.find(std::vector<int>(ids, ids + c.m.k));
+    return it == c.specific.end() ? nullptr : &it->second.F[which];
 }
 
 int stage16(Prog16 &p) {

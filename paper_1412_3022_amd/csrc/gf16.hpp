@@ -62,10 +62,20 @@ struct Prog16 {
     ~Prog16() { free_device_copies(dev); }
 };
 
+// The specific PM-MSR decode from the k nodes K as five factors (the
+// GF(2^16) counterpart of specific_decode_factors; F[4] empty for a
+// non-systematic code).
+int specific_factors(const Code16 &c, const std::vector<int> &K, Mat16 F[kSpecificPasses]);
+
 // Everything a GF(2^16) code object holds besides its parameters.
 struct Ctx16 {
     Code16 m;
     std::mutex mu;
+    struct Specific {
+        Mat16 F[kSpecificPasses];
+        std::unique_ptr<Prog16> prog[kSpecificPasses];
+    };
+    std::map<std::vector<int>, Specific> specific;
     std::unique_ptr<Prog16> enc;
     std::map<int, std::unique_ptr<Prog16>> helper;
     std::map<std::pair<int, std::vector<int>>, std::unique_ptr<Prog16>> newcomer;
@@ -75,6 +85,12 @@ struct Ctx16 {
 // The program of one operation (OPK_*), built on first use.  in_n / out_n:
 // the input and output block counts.
 int resolve16(Ctx16 &c, int op, uint32_t failed, const uint32_t *ids, Prog16 **pe, size_t *in_n, size_t *out_n);
+// The passes of the specific decode from the k nodes ids (factors and
+// programs built on first use): npass programs and their output rows.
+int resolve_specific16(Ctx16 &c, const uint32_t *ids, Prog16 *pe[kSpecificPasses], int rows[kSpecificPasses],
+                       int *npass);
+// Factor `which` of a node list already resolved, or nullptr.
+const Mat16 *specific_factor16(Ctx16 &c, const uint32_t *ids, int which);
 // Upload the program (and the field tables) to the current device and wait
 // for those copies (no other work is waited for).
 int stage16(Prog16 &p);

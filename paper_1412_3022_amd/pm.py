@@ -311,15 +311,16 @@ class Code:
                "pm_repair_newcomer")
 
     def specific_factor(self, nodes, which):
-        """Factor `which` (0..3) of the specific decode for nodes, as a numpy matrix."""
+        """Factor `which` (0..4) of the specific decode for nodes, as a numpy
+        matrix (uint16 for a GF(2^16) code)."""
         import numpy as np
         r, c = ctypes.c_uint32(), ctypes.c_uint32()
         _check(_lib().pm_decode_specific_factor(self.h, _u32arr(nodes), which, None, 0, ctypes.byref(r),
                                                 ctypes.byref(c)), "pm_decode_specific_factor")
-        m = np.zeros((r.value, c.value), np.uint8)
+        m = np.zeros((r.value, c.value), np.uint16 if self.w == 16 else np.uint8)
         if m.size:
-            _check(_lib().pm_decode_specific_factor(self.h, _u32arr(nodes), which, m.ctypes.data, m.size, None, None),
-                   "pm_decode_specific_factor")
+            _check(_lib().pm_decode_specific_factor(self.h, _u32arr(nodes), which, m.ctypes.data, m.nbytes, None,
+                                                    None), "pm_decode_specific_factor")
         return m
 
     def decode_specific(self, nodes, Y, X, block_bytes, workspace=None, stream=None):

@@ -197,3 +197,59 @@ def test_batches_and_the_server_refuse_gf16_codes():
         assert e.value.status == pm.PM_EUNSUPPORTED
     finally:
         srv.close()
+
+
+@pytest.mark.parametrize("k,n,sys_", [(4, 8, True), (4, 8, False), (8, 16, True), (8, 16, False), (16, 32, True)])
+@pytest.mark.parametrize("s", [2, 2048 + 6])
+def test_specific_decode(k, n, sys_, s):
+    """The specific PM-MSR decode over GF(2^16) (Section 4.1's decoder) in
+    four or five passes through the workspace: the object back from node
+    sets of every kind, against the oracle's specific decoder too."""
+    print("gf16 specific decode", k, n, sys_, s, flush=True)
+    c = pm.Code(k=k, d=2 * k - 2, n=n, systematic=sys_, w=16)
+    o = F.Code(k, n, systematic_form=sys_)
+    X = _data(c.B, s, 2000 + k + s % 79)
+    P = _encode(c, X, s)
+    nodes = _nodes(o, X, P)
+    st = synth.Stream(2001 + k)
+    for K in [list(range(k)), list(range(n - k, n)), st.subset(n, k), list(reversed(st.subset(n, k)))]:
+        Y = np.concatenate([nodes[i] for i in K])
+        out = out_regions(c.B, s)
+        c.decode_specific(K, to_regions(Y), out, s)
+        got = read(out, s)
+        assert np.array_equal(got, X), K
+        assert np.array_equal(_u16(got), o.decode_specific(K, _u16(Y))), K
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("k,n,sys_", [(40, 79, True), (64, 127, False)])
+def test_specific_decode_beyond_the_byte_field(k, n, sys_):
+    """k = 40 (systematic, B = 1560) and k = 64 (B = 4032): encode on the
+    GPU, then the specific decode from the last k nodes and from a mixed set
+    gives the object back (round trip; each piece is checked against the
+    oracle at smaller k, and the oracle's B x B inversion here would take
+    minutes)."""
+    print("gf16 specific decode", k, n, sys_, flush=True)
+    c = pm.Code(k=k, d=2 * k - 2, n=n, systematic=sys_, w=16)
+    s = 1024 + 10
+    X = _data(c.B, s, 2100 + k)
+    Xd = to_regions(X)
+    P = out_regions(c.enc_rows, s)
+    c.encode(Xd, P, s)
+    Ph = read(P, s)
+    a = c.alpha
+
+    def node(i):
+        rows = []
+        for t in range(i * a, (i + 1) * a):
+            # systematic: blocks t < B are data, the others encode rows t - B;
+            # otherwise every block t is encode row t
+            rows.append(X[t] if sys_ and t < c.B else Ph[t - c.B if sys_ else t])
+        return np.stack(rows)
+
+    st = synth.Stream(2101 + k)
+    for K in [list(range(n - k, n)), st.subset(n, k)]:
+        Y = np.concatenate([node(i) for i in K])
+        out = out_regions(c.B, s)
+        c.decode_specific(K, to_regions(Y), out, s)
+        assert np.array_equal(read(out, s), X), K

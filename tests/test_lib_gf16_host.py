@@ -45,10 +45,13 @@ def test_refusals_and_argument_errors_need_no_gpu():
     # GF(2^8)-only entry points
     assert pm.pm_set_variant(c.h, 0, 8, 4) == pm.PM_EUNSUPPORTED
     assert pm.lib().pm_decode_matrix(c.h, pm._u32arr([0, 1, 2, 3]), None, 0, None) == pm.PM_EUNSUPPORTED
-    n = ctypes.c_size_t()
-    assert pm.lib().pm_decode_specific_workspace(c.h, 4096, ctypes.byref(n)) == pm.PM_EUNSUPPORTED
-    assert pm.pm_prepare(c.h, 4, ids=[0, 1, 2, 3])[0] == pm.PM_EUNSUPPORTED
     assert pm.pm_prepare(c.h, pm.OP_ENCODE, flags=pm.PM_PREPARE_BATCHED)[0] == pm.PM_EUNSUPPORTED
+    # the specific decode: workspace of Z, the pairs, the phi^t S rows and Z
+    n = ctypes.c_size_t()
+    assert pm.lib().pm_decode_specific_workspace(c.h, 4096, ctypes.byref(n)) == pm.PM_OK
+    assert n.value == (4 * 3 + 12 + 2 * 9 + 12) * 4096
+    assert pm.pm_prepare(c.h, 4, ids=[0, 1, 2, 3]) == (pm.PM_OK, 0)
+    assert pm.pm_prepare(c.h, 4, ids=[0, 1, 2, 2])[0] == pm.PM_EINVAL
     # the matrices are built (and, with no device here, not staged)
     assert pm.pm_prepare(c.h, pm.OP_ENCODE) == (pm.PM_OK, 0)
     assert pm.pm_prepare(c.h, pm.OP_HELPER, failed=2) == (pm.PM_OK, 0)
@@ -64,3 +67,20 @@ def test_refusals_and_argument_errors_need_no_gpu():
     assert pm.pm_repair_newcomer(c.h, 0, [0, 2, 3, 4, 5, 6], 4096, 64, 1 << 20, 64, 64) == pm.PM_EINVAL
     assert pm.pm_decode(c.h, [0, 1, 2, 2], 4096, 64, 1 << 20, 64, 64) == pm.PM_EINVAL
     assert pm.pm_decode(c.h, [0, 1, 2, 9], 4096, 64, 1 << 20, 64, 64) == pm.PM_EINVAL
+
+
+@pytest.mark.parametrize("k,n,sys_,K", [(4, 8, True, [1, 4, 6, 7]), (4, 8, False, [7, 5, 3, 1]),
+                                         (8, 16, True, [0, 3, 8, 9, 11, 12, 14, 15]),
+                                         (16, 32, True, [0, 3, 9, 14, 15, 16, 17, 20, 22, 24, 25, 26, 28, 29, 30, 31])])
+def test_specific_decode_factors_multiply_to_the_decode_matrix(k, n, sys_, K):
+    """The library's five GF(2^16) factors of the specific decode (Section 4.1)
+    multiply to the oracle's linearized decode matrix for the same nodes."""
+    c = pm.Code(k=k, d=2 * k - 2, n=n, systematic=sys_, w=16)
+    o = F.Code(k, n, systematic_form=sys_)
+    Fs = [c.specific_factor(K, w) for w in range(5)]
+    prod = Fs[0]
+    for f in Fs[1:]:
+        if f.size:
+            prod = F.matmul(f, prod)
+    assert np.array_equal(prod, o.decode_matrix(K))
+    assert (Fs[4].size > 0) == sys_
