@@ -84,11 +84,15 @@ typedef struct {
  * and pm_decode run on the GF(2^16) region kernel with the same arguments
  * as for w = 8; pm_prepare builds the operation's matrix and stages it on the
  * device (*specialized = 0).  pm_code_matrix writes two bytes per entry,
- * little-endian (cap counts bytes).  The specific decode, pm_decode_matrix(es),
- * pm_set_variant, pm_autotune_encode, batches and the server take GF(2^8)
- * codes only: PM_EUNSUPPORTED.  Building a systematic code inverts a B x B
- * matrix (B = k(k-1)) on the host, as does each new decode node set: about
- * 0.5 s and 2 s at k = 40, 5 s and 30 s at k = 64. */
+ * little-endian (cap counts bytes).  pm_decode_specific (and its workspace,
+ * factor and pm_prepare forms) runs the specific PM-MSR decoder's passes on
+ * the GF(2^16) kernel; pm_decode_specific_factor writes two bytes per entry.
+ * pm_decode_matrix(es), pm_set_variant, pm_autotune_encode, batches and the
+ * server take GF(2^8) codes only: PM_EUNSUPPORTED.  Building a systematic
+ * code inverts a B x B matrix (B = k(k-1)) on the host, as does each new node
+ * set of pm_decode: about 0.5 s and 2 s at k = 40, 5 s and 30 s at k = 64;
+ * the specific decode's factors need only alpha x alpha inverses (0.1 s at
+ * k = 64). */
 
 typedef struct pm_code pm_code;
 
