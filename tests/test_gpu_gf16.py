@@ -225,8 +225,8 @@ def test_specific_decode(k, n, sys_, s):
 @pytest.mark.parametrize("k,n,sys_", [(40, 79, True), (64, 127, False)])
 def test_specific_decode_beyond_the_byte_field(k, n, sys_):
     """k = 40 (systematic, B = 1560) and k = 64 (B = 4032): encode on the
-    GPU, then the specific decode from the last k nodes and from a mixed set
-    gives the object back (round trip; each piece is checked against the
+    GPU, then the specific decode (and at k = 40 the linearized one) from
+    the last k nodes and from a mixed set gives the object back (round trip; each piece is checked against the
     oracle at smaller k, and the oracle's B x B inversion here would take
     minutes)."""
     print("gf16 specific decode", k, n, sys_, flush=True)
@@ -253,3 +253,7 @@ def test_specific_decode_beyond_the_byte_field(k, n, sys_):
         out = out_regions(c.B, s)
         c.decode_specific(K, to_regions(Y), out, s)
         assert np.array_equal(read(out, s), X), K
+        if k == 40:   # the linearized decode too (its B x B inverse takes seconds on the host)
+            out = out_regions(c.B, s)
+            c.decode(K, to_regions(Y), out, s)
+            assert np.array_equal(read(out, s), X), ("linearized", K)
