@@ -335,7 +335,8 @@ static int mbr_specific_factors(const CodeMats &c, const std::vector<int> &K, Ma
     // k*dk + i*k + j (renumbered below to the copies actually read)
     const int nT = k * dk, nv = nT + k * k;
     Mat F1(B, nv);
-    auto s_terms = [&](int l, int j) {
+    // terms of an S symbol taken from side l (row l of Phinv and of E)
+    auto s_terms = [&](int l) {
         int cnt = 0;
         for (int i = 0; i < k; ++i) cnt += Phinv.at(l, i) != 0;
         for (int t = 0; t < dk; ++t) cnt += E[static_cast<size_t>(l) * dk + t] != 0;
@@ -343,7 +344,7 @@ static int mbr_specific_factors(const CodeMats &c, const std::vector<int> &K, Ma
     };
     for (int a = 0; a < k; ++a) {
         for (int b = a; b < k; ++b) {
-            const int l = s_terms(a, b) <= s_terms(b, a) ? a : b, j = l == a ? b : a;
+            const int l = s_terms(a) <= s_terms(b) ? a : b, j = l == a ? b : a;
             const int m = c.L[a * d + b];
             for (int i = 0; i < k; ++i) F1.at(m, nT + i * k + j) ^= Phinv.at(l, i);
             for (int t = 0; t < dk; ++t) F1.at(m, j * dk + t) ^= E[static_cast<size_t>(l) * dk + t];
