@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 NBUF = 8
+PREWARM_S = 0.3   # untimed launches before the warmup steps of each encode case
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_msr_k8_sparse_encode_64MiB.txt")
 CSRC = os.path.join(ROOT, "paper_1412_3022_amd", "csrc")
 # the source a kernel's code comes from: the bit-sliced kernel is generated at
@@ -114,8 +115,21 @@ class Timer:
     def __init__(self, torch):
         self.torch = torch
 
-    def run(self, fn, steps, warmup):
+    def run(self, fn, steps, warmup, prewarm_s=0.0):
+        """prewarm_s: before the warmup steps, run steps for at least this
+        long (the shader clock ramps up from idle over some 100 ms, more
+        than a short --warmup covers)."""
         torch = self.torch
+        if prewarm_s > 0:
+            t0 = time.perf_counter()
+            i = 0
+            while True:
+                fn(i)
+                i += 1
+                if i % 64 == 0:
+                    torch.cuda.synchronize()
+                    if time.perf_counter() - t0 >= prewarm_s:
+                        break
         for i in range(warmup):
             fn(i)
         torch.cuda.synchronize()
@@ -161,7 +175,7 @@ def encode_case(torch, pm, synth, kw, S, seed, steps, warmup, nbuf=NBUF, tune=Tr
         if st != pm.PM_OK:
             raise pm.PMError(st, "pm_encode")
 
-    wall, ev = Timer(torch).run(step, steps, warmup)
+    wall, ev = Timer(torch).run(step, steps, warmup, prewarm_s=PREWARM_S)
     alg_bytes = (code.B + code.enc_rows) * s
     res = {"source_bytes": S, "block_bytes": s, "wall_s": wall, "event_s": ev,
            "gbps": S * steps / wall / 1e9, "kernel_us": ev / steps * 1e6,
@@ -180,6 +194,54 @@ def prepare_all(code, pm, f, H, K):
     code.prepare(pm.OP_NEWCOMER, failed=f, ids=H)
     code.prepare(pm.OP_DECODE, ids=K)
     return time.perf_counter() - t0
+
+
+def repair_case(torch, pm, code, node, f, H, reps, prefix, nsets=3):
+    """Repair of node f from helpers H, after its init phase: pm_repair (the
+    d projections as one multi-set launch, then the newcomer) against one
+    pm_repair_helper call per helper and the newcomer, each timed with HIP
+    events over `reps` repairs rotating over `nsets` copies of the helper
+    blocks (about 160 MB each for the k=8 codes, so the 256 MB Infinity
+    Cache cannot serve the next repair's inputs).  GB/s of repaired bytes
+    (alpha blocks per repair)."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream().cuda_stream
+    s = node(H[0]).shape[1]
+    t0 = time.perf_counter()
+    ready = code.prepare(pm.OP_REPAIR, failed=f, ids=H)
+    init_s = time.perf_counter() - t0
+    sets = [[node(h).clone() for h in H] for _ in range(nsets)]
+    outs = [torch.empty((code.alpha, s), dtype=torch.uint8, device=dev) for _ in range(nsets)]
+    ws_bytes = pm.pm_repair_workspace(code.h, s)
+    wss = [torch.empty(ws_bytes, dtype=torch.uint8, device=dev) for _ in range(nsets)]
+    ptrs = [[t.data_ptr() for t in st] for st in sets]
+
+    def two(i):
+        j = i % nsets
+        st = pm.pm_repair(code.h, f, H, ptrs[j], s, wss[j].data_ptr(), ws_bytes, outs[j].data_ptr(), s, s, stream)
+        if st != pm.PM_OK:
+            raise pm.PMError(st, "pm_repair")
+
+    _, ev = Timer(torch).run(two, reps, 4)
+    res = {prefix + "_repair_gbps": code.alpha * s * reps / ev / 1e9,
+           prefix + "_repair_us": ev / reps * 1e6,
+           prefix + "_repair_init_s": init_s,
+           prefix + "_repair_one_launch_projections": bool(ready)}
+    torch.cuda.synchronize()
+    want = node(f)
+    res[prefix + "_repair_equal"] = all(bool(torch.equal(o, want)) for o in outs)
+    recv = torch.empty((code.d, s), dtype=torch.uint8, device=dev)
+
+    def per_helper(i):
+        j = i % nsets
+        for q in range(len(H)):
+            pm.pm_repair_helper(code.h, f, ptrs[j][q], s, recv[q].data_ptr(), s, stream)
+        pm.pm_repair_newcomer(code.h, f, H, recv.data_ptr(), s, outs[j].data_ptr(), s, s, stream)
+
+    _, ev = Timer(torch).run(per_helper, reps, 4)
+    res[prefix + "_repair_per_helper_gbps"] = code.alpha * s * reps / ev / 1e9
+    del sets, outs, wss
+    return res
 
 
 def mbr_cases(torch, pm, synth, steps, warmup):
@@ -209,23 +271,15 @@ def mbr_cases(torch, pm, synth, steps, warmup):
     wall, ev = Timer(torch).run(lambda i: pm.pm_encode(code.h, x.data_ptr(), s, P2.data_ptr(), s, s, stream),
                                 steps, warmup)
     out["mbr_encode_gbps"] = S * steps / wall / 1e9
-    nodes = [node(h) for h in H]
-    recv = torch.empty((code.d, s), dtype=torch.uint8, device=dev)
-    rout = torch.empty((code.alpha, s), dtype=torch.uint8, device=dev)
-
-    def repair(i):
-        for j, h in enumerate(H):
-            pm.pm_repair_helper(code.h, f, nodes[j].data_ptr(), s, recv[j].data_ptr(), s, stream)
-        pm.pm_repair_newcomer(code.h, f, H, recv.data_ptr(), s, rout.data_ptr(), s, s, stream)
-
-    wall, ev = Timer(torch).run(repair, max(1, steps // 4), max(1, warmup // 4))
-    out["mbr_repair_gbps"] = code.alpha * s * max(1, steps // 4) / wall / 1e9   # repaired bytes
-    Y = torch.cat([node(i) for i in K])
-    xo = torch.empty_like(x)
-    wall, ev = Timer(torch).run(lambda i: pm.pm_decode(code.h, K, Y.data_ptr(), s, xo.data_ptr(), s, s, stream),
-                                max(1, steps // 4), max(1, warmup // 4))
-    out["mbr_decode_gbps"] = S * max(1, steps // 4) / wall / 1e9
+    out.update(repair_case(torch, pm, code, node, f, H, max(20, steps // 20), "mbr"))
+    n = max(20, steps // 20)
+    Ys = [torch.cat([node(i) for i in K]) for _ in range(2)]
+    xos = [torch.empty_like(x) for _ in range(2)]
+    _, ev = Timer(torch).run(lambda i: pm.pm_decode(code.h, K, Ys[i % 2].data_ptr(), s, xos[i % 2].data_ptr(), s, s,
+                                                    stream), n, 4)
+    out["mbr_decode_gbps"] = S * n / ev / 1e9
     out["mbr_decode_nodes"] = K
+    xo = xos[0]
     # the specific PM-MBR decode (pm_decode_specific: T, then S) from the same
     # nodes and, beside the linearized decode, from the 8 parity nodes (every
     # data block lost); its init (kernels of both passes) is reported apart
@@ -237,21 +291,20 @@ def mbr_cases(torch, pm, synth, steps, warmup):
     out["mbr_specific_all_passes_bitsliced"] = bool(ready)
     ws_bytes = pm.pm_decode_specific_workspace(code.h, s)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
-    n = max(1, steps // 4)
     equal = True
     for tag, KK in (("", K), ("_parity", Kp)):
         Y = torch.cat([node(i) for i in KK])
         if tag:
-            wall, _ = Timer(torch).run(
+            _, ev = Timer(torch).run(
                 lambda i: pm.pm_decode(code.h, KK, Y.data_ptr(), s, xo.data_ptr(), s, s, stream), n, 2)
-            out["mbr_decode%s_linear_gbps" % tag] = S * n / wall / 1e9
+            out["mbr_decode%s_linear_gbps" % tag] = S * n / ev / 1e9
             torch.cuda.synchronize()
             equal = equal and bool(torch.equal(xo, x))
         xo.zero_()
-        wall, _ = Timer(torch).run(
+        _, ev = Timer(torch).run(
             lambda i: pm.pm_decode_specific(code.h, KK, Y.data_ptr(), s, xo.data_ptr(), s, s, ws.data_ptr(),
                                             ws_bytes, stream), n, 2)
-        out["mbr_decode%s_specific_gbps" % tag] = S * n / wall / 1e9
+        out["mbr_decode%s_specific_gbps" % tag] = S * n / ev / 1e9
         torch.cuda.synchronize()
         equal = equal and bool(torch.equal(xo, x))
     out["mbr_decode_results_equal"] = equal
@@ -279,24 +332,16 @@ def msr_repair_decode(torch, pm, synth, steps, warmup):
     H = [i for i in range(code.n) if i != f][:code.d]
     K = synth.Stream(synth.CONFIG_SEED + 1).subset(code.n, code.k)
     out["msr_init_s"] = prepare_all(code, pm, f, H, K)
-    nodes = [node(h) for h in H]
-    recv = torch.empty((code.d, s), dtype=torch.uint8, device=dev)
-    rout = torch.empty((code.alpha, s), dtype=torch.uint8, device=dev)
-
-    def repair(i):
-        for j, h in enumerate(H):
-            pm.pm_repair_helper(code.h, f, nodes[j].data_ptr(), s, recv[j].data_ptr(), s, stream)
-        pm.pm_repair_newcomer(code.h, f, H, recv.data_ptr(), s, rout.data_ptr(), s, s, stream)
-
-    n = max(1, steps // 4)
-    wall, ev = Timer(torch).run(repair, n, max(1, warmup // 4))
-    out["msr_repair_gbps"] = code.alpha * s * n / wall / 1e9
-    Y = torch.cat([node(i) for i in K])
-    xo = torch.empty_like(x)
-    wall, ev = Timer(torch).run(lambda i: pm.pm_decode(code.h, K, Y.data_ptr(), s, xo.data_ptr(), s, s, stream),
-                                n, max(1, warmup // 4))
-    out["msr_decode_gbps"] = S * n / wall / 1e9
+    out.update(repair_case(torch, pm, code, node, f, H, max(20, steps // 20), "msr"))
+    n = max(20, steps // 20)
+    Ys = [torch.cat([node(i) for i in K]) for _ in range(3)]
+    xos = [torch.empty_like(x) for _ in range(3)]
+    _, ev = Timer(torch).run(lambda i: pm.pm_decode(code.h, K, Ys[i % 3].data_ptr(), s, xos[i % 3].data_ptr(), s, s,
+                                                    stream), n, 4)
+    out["msr_decode_gbps"] = S * n / ev / 1e9
     out["msr_decode_nodes"] = K
+    torch.cuda.synchronize()
+    out["msr_decode_equal"] = all(bool(torch.equal(xo, x)) for xo in xos)
     return out
 
 
@@ -321,10 +366,10 @@ def msr16_decode_case(torch, pm, synth, steps, warmup):
     stream = torch.cuda.current_stream().cuda_stream
     out = {}
     xl = torch.empty_like(x)
-    n = max(5, steps // 10)
-    wall, _ = Timer(torch).run(lambda i: pm.pm_decode(code.h, K, Y.data_ptr(), ld, xl.data_ptr(), ld, s, stream),
-                               n, 2)
-    out["msr16_decode_linear_gbps"] = S * n / wall / 1e9
+    n = max(20, steps // 20)
+    _, ev = Timer(torch).run(lambda i: pm.pm_decode(code.h, K, Y.data_ptr(), ld, xl.data_ptr(), ld, s, stream),
+                             n, 2)
+    out["msr16_decode_linear_gbps"] = S * n / ev / 1e9
     t0 = time.perf_counter()
     ready = code.prepare(pm.OP_DECODE_SPECIFIC, ids=K)
     out["msr16_specific_init_s"] = time.perf_counter() - t0
@@ -332,9 +377,9 @@ def msr16_decode_case(torch, pm, synth, steps, warmup):
     ws_bytes = pm.pm_decode_specific_workspace(code.h, s)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     xs = torch.empty_like(x)
-    wall, _ = Timer(torch).run(lambda i: pm.pm_decode_specific(code.h, K, Y.data_ptr(), ld, xs.data_ptr(), ld, s,
-                                                               ws.data_ptr(), ws_bytes, stream), n, 2)
-    out["msr16_decode_specific_gbps"] = S * n / wall / 1e9
+    _, ev = Timer(torch).run(lambda i: pm.pm_decode_specific(code.h, K, Y.data_ptr(), ld, xs.data_ptr(), ld, s,
+                                                             ws.data_ptr(), ws_bytes, stream), n, 2)
+    out["msr16_decode_specific_gbps"] = S * n / ev / 1e9
     torch.cuda.synchronize()
     out["msr16_decode_results_equal"] = bool(torch.equal(xs[:, :s], xl[:, :s]) and torch.equal(xs[:, :s], x[:, :s]))
     del x, P, Y, xl, xs, ws
@@ -605,39 +650,56 @@ def served_case(torch, pm, synth, nreq=20000, rho=0.8):
             "bytes_counted": "encode and decode: object bytes; repair: the alpha repaired blocks"}
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(synth, budget_s=12.0):
     """The oracle (plain log/antilog C) on the host cores: the same encode on
     a bounded sample -- the first `w` bytes of every sub-block of the
-    configuration-2 object -- doubled until it runs for a few seconds."""
+    configuration-2 object -- with one thread (the paper measures one core)
+    and with every host thread (at most 16), each repeated to about
+    budget_s / 2 of CPU time."""
     import numpy as np
     import oracle as O
-    threads = min(os.cpu_count() or 1, 16)
     code = O.Code(O.MSR, 8, 14, 16, O.SPARSE)
     X, s = synth.split_object(64 << 20, code.B, synth.CONFIG_SEED + 1)
-    w = 4096
-    while True:
-        sample = np.ascontiguousarray(X[:, :w])
-        t0 = time.perf_counter()
-        O.apply(code.enc, sample, nthreads=threads)
-        dt = time.perf_counter() - t0
-        if dt > budget_s / 4 or w >= s:
-            break
-        w = min(s, w * 2)
-    # repeat the sample until about budget_s of CPU time has been spent
-    reps = 1
-    while dt * threads < budget_s and reps < 64:
-        t0 = time.perf_counter()
-        for _ in range(reps):
+
+    def run(threads, budget):
+        w = 4096
+        while True:
+            sample = np.ascontiguousarray(X[:, :w])
+            t0 = time.perf_counter()
             O.apply(code.enc, sample, nthreads=threads)
-        dt = time.perf_counter() - t0
-        if dt * threads >= budget_s:
-            break
-        reps *= 2
-    src = code.B * w * reps
-    return {"value": src / dt / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
+            dt = time.perf_counter() - t0
+            if dt * threads > budget / 8 or w >= s:
+                break
+            w = min(s, w * 2)
+        reps = 1
+        while dt * threads < budget and reps < 64:
+            reps *= 2
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                O.apply(code.enc, sample, nthreads=threads)
+            dt = time.perf_counter() - t0
+        return code.B * w * reps / dt / 1e9, w, reps, dt
+
+    threads = min(os.cpu_count() or 1, 16)
+    one, w1, r1, t1 = run(1, budget_s / 2)
+    allc, w, reps, dt = run(threads, budget_s / 2)
+    return {"value": allc, "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "one_thread_value": one, "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
             "sample": "first %d B of each of the 56 sub-blocks of the 64 MiB object, encoded %d times "
-                      "(%d source bytes), sparse systematic k=8 encode, %.2f s wall on %d threads"
-                      % (w, reps, src, dt, threads)}
+                      "(%d source bytes), sparse systematic k=8 encode, %.2f s wall on %d threads; "
+                      "one thread: first %d B x 56, %d times, %.2f s"
+                      % (w, reps, code.B * w * reps, dt, threads, w1, r1, t1)}
 
 
 def main():

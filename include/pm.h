@@ -47,7 +47,8 @@ typedef enum {
     PM_ESINGULAR = -3,     /* helper set / node set cannot repair / decode */
     PM_ENOMEM = -4,        /* host or device allocation failed */
     PM_EHIP = -5,          /* a HIP runtime call failed */
-    PM_EBUSY = -6          /* a queue is full; retry later */
+    PM_EBUSY = -6,         /* a queue is full; retry later */
+    PM_ENOTREADY = -7      /* the operation has not been prepared on this device */
 } pm_status;
 
 typedef enum {
@@ -100,8 +101,9 @@ typedef struct pm_code pm_code;
  * G' (Section 3.2), the validity check of Section 3.3 (distinct Lambda, every
  * d rows of Psi independent).  Host only: touches no GPU.  *out receives a
  * handle owned by the caller (free with pm_code_destroy).
- * Errors: PM_EINVAL (NULL, w != 8, shape), PM_EUNSUPPORTED (construction
- * invalid for these parameters), PM_ESINGULAR, PM_ENOMEM. */
+ * Errors: PM_EINVAL (NULL, shape, unknown kind), PM_EUNSUPPORTED (w other
+ * than 8 and 16, or a construction invalid for these parameters),
+ * PM_ESINGULAR, PM_ENOMEM. */
 pm_status pm_code_create(const pm_params *params, pm_code **out);
 
 /* Free a code and its device tables.  The caller must make sure no stream is
@@ -152,6 +154,28 @@ pm_status pm_repair_helper(const pm_code *code, uint32_t failed, const uint8_t *
 pm_status pm_repair_newcomer(const pm_code *code, uint32_t failed, const uint32_t *helpers,
                              const uint8_t *recv, size_t recv_ld, uint8_t *out,
                              size_t out_ld, size_t block_bytes, pm_stream stream);
+
+/* Repair of node `failed` in two steps on one stream (Section 2: each of
+ * the d helpers sends beta = 1 block, the newcomer solves for its alpha
+ * blocks): the d helper projections as one launch of the multi-set
+ * bit-sliced kernel over all helpers, then the newcomer's solve.
+ * helper_nodes: host array of d device pointers, helper j's alpha blocks at
+ * helper_nodes[j] + a * node_ld, in the order of helpers[] (d distinct node
+ * ids != failed, host).  workspace (device, 16-byte aligned, at least
+ * pm_repair_workspace bytes, not overlapping any other region) receives the
+ * d helper blocks -- the bytes the helpers would send over the network --
+ * followed by the projections' launch list, which a small kernel writes
+ * there in stream order.  out: the alpha rebuilt blocks.  The one-launch
+ * projection needs the helper vector's multi-set kernel (pm_prepare op 5,
+ * which also prepares the newcomer) and blocks of at least 2048 bytes;
+ * otherwise each projection is its own launch.  Same bytes as
+ * pm_repair_helper for every helper followed by pm_repair_newcomer; same
+ * errors. */
+pm_status pm_repair_workspace(const pm_code *code, size_t block_bytes, size_t *bytes);
+pm_status pm_repair(const pm_code *code, uint32_t failed, const uint32_t *helpers,
+                    const uint8_t *const *helper_nodes, size_t node_ld, uint8_t *workspace,
+                    size_t workspace_bytes, uint8_t *out, size_t out_ld, size_t block_bytes,
+                    pm_stream stream);
 
 /* Decode (Section 2: X = inverse(G~) Y~): from k distinct nodes (host array
  * `nodes`) whose k alpha blocks are in Y (node-major, in the order of
@@ -265,8 +289,9 @@ pm_status pm_set_variant(pm_code *code, int op, uint32_t rows_per_group,
 /* Init phase of one operation, kept apart from the data phase as the
  * paper's evaluation separates them (Section 4): builds the operation's
  * matrix (op 0 encode, 1 repair helper, 2 repair newcomer, 3 decode, 4 the
- * passes of pm_decode_specific; failed and ids as for those calls, ids on the
- * host) and, under the default or the
+ * passes of pm_decode_specific, 5 both steps of pm_repair -- the helper
+ * projection's multi-set kernel and the newcomer's; failed and ids as for
+ * those calls, ids on the host) and, under the default or the
  * bit-sliced variant, generates its bit-sliced kernel and compiles it with
  * hipRTC (seconds; no GPU needed; a no-op when already compiled): the
  * single-set form that the calls above use, or with PM_PREPARE_BATCHED in
@@ -386,22 +411,39 @@ typedef struct {
 } pm_completion;
 
 typedef struct {
-    uint64_t hbm_budget_bytes;  /* arena size: admitted results + repair scratch */
+    uint64_t hbm_budget_bytes;  /* device bytes for the arena (admitted results +
+                                   repair scratch) and the kernel tables */
     uint32_t streams;           /* micro-batches in flight at once (1..16) */
     uint32_t max_batch;         /* requests per micro-batch */
     uint32_t queue_cap;         /* pending requests before submit returns PM_EBUSY */
     uint32_t dwords_per_lane;   /* tile width of the work lists: 2 or 4 (0 = 2) */
+    uint64_t table_reserve_bytes;  /* part of the budget kept for the device
+                                      copies of kernel tables (pm_table_bytes);
+                                      0 = budget / 32, at least 16 MiB.  The
+                                      arena is the rest. */
 } pm_server_cfg;
 
 typedef struct {
     uint64_t completed, batches, pending, arena_used, arena_high_water;
     uint32_t max_concurrent_batches;   /* most micro-batches in flight at once */
+    uint32_t pad;
+    uint64_t failed;                   /* requests completed with an error status */
+    uint64_t arena_bytes;              /* arena size (budget minus the table reserve) */
+    uint64_t table_reserve_bytes;
+    uint64_t table_bytes_high;         /* most table bytes seen after a micro-batch's
+                                          uploads (pm_table_bytes, all codes) */
 } pm_server_stat;
 
 typedef struct pm_server pm_server;
 
 /* Allocate the arena, streams and staging buffers; start the scheduler
- * thread (on the calling thread's current device). */
+ * thread (on the calling thread's current device).  Kernel tables that the
+ * work lists read count against the budget: before a micro-batch uploads
+ * tables that would take pm_table_bytes() past the reserve, the scheduler
+ * evicts least recently used failure patterns not in use (a device-wide
+ * synchronization); if the tables its own requests need still do not fit,
+ * those requests complete with PM_ENOMEM.  PM_EINVAL when the reserve
+ * leaves no arena. */
 pm_status pm_server_create(const pm_server_cfg *cfg, pm_server **out);
 
 /* Queue a request (thread-safe).  Resolves its matrices (building a repair or
@@ -429,6 +471,35 @@ pm_status pm_server_replay(pm_server *srv, const pm_request *reqs, const uint64_
 
 /* Stop the scheduler after the micro-batches in flight finish; free all. */
 void pm_server_destroy(pm_server *srv);
+
+/* ---- Caches of per-failure-pattern state ----------------------------------
+ * The initialization phase of a repair or decode (Section 4: built once per
+ * failure pattern) is cached in the code object: the helper, newcomer and
+ * decode matrices, the specific-decode factors, their kernel programs, the
+ * device copies of their tables and their compiled kernels.  Each of these
+ * caches holds at most `entries` patterns (default 256); beyond that the
+ * least recently used pattern not in use (by a batch plan, a queued server
+ * request or a call in progress) is evicted.  An evicted pattern's device
+ * memory is freed only once no launch can still read it: after a
+ * device-wide synchronization, which the library runs when evicted patterns
+ * hold more than 64 MiB, and in pm_cache_release.  The pm_apply cache (keyed
+ * by matrix content, all codes) holds 256 matrices the same way.
+ * PM_EINVAL for entries == 0. */
+pm_status pm_code_set_cache_limit(pm_code *code, uint32_t entries);
+
+/* Synchronize the device and free every evicted pattern that nothing still
+ * uses.  Must not be called while a stream of this thread is being
+ * captured into a graph. */
+pm_status pm_cache_release(void);
+
+/* Device bytes held by kernel tables of every code on every device (evicted
+ * patterns not yet freed included); the server keeps this within its table
+ * reserve. */
+size_t pm_table_bytes(void);
+
+/* Failure injection for tests of the error paths: the next `count` uploads
+ * of kernel tables to the device fail with PM_ENOMEM, before allocating. */
+pm_status pm_debug_fail_uploads(uint32_t count);
 
 /* Message of the last failing HIP call on this thread ("" if none). */
 const char *pm_last_hip_error(void);

@@ -66,6 +66,9 @@ struct BsClass {
 }  // namespace
 
 struct pm_batch {
+    // programs whose device tables the work lists point to: kept alive (and
+    // out of reach of cache eviction) for the life of the plan
+    std::vector<std::shared_ptr<ProgEntry>> keep;
     std::vector<SizeClass> classes;
     std::vector<BsClass> bs_classes;
     uint32_t *d_counters = nullptr;   // 8 queue heads per class, 64 B apart
@@ -214,6 +217,7 @@ pm_status pm_batch_plan(const pm_batch_item *items, size_t n, uint32_t flags, pm
         }
         const uint32_t *dprog = nullptr;
         if ((st = r.pe->device_ptr_sync(&dprog)) != ST_OK) return static_cast<pm_status>(st);
+        if (b->keep.empty() || b->keep.back() != r.pe) b->keep.push_back(r.pe);
         auto cls = by_rg.find(r.pe->prog.rg);
         if (cls == by_rg.end()) {
             cls = by_rg.emplace(r.pe->prog.rg, b->classes.size()).first;

@@ -78,9 +78,10 @@ BsItem bs_item(const uint8_t *in, uint64_t in_ld, uint8_t *out, uint64_t out_ld,
 int bs_load(BsProgram &bp, BsKind kind);
 // Run the kernel over bytes [0, s) of every block, s >= kBsTileBytes (else
 // ST_EINVAL).  Bases 16-byte aligned, ld multiples of 16 (as checked by the
-// entry points).
+// entry points).  resident_only: compile and load nothing; ST_ENOTREADY
+// unless the kernel is already loaded on the current device.
 int bs_launch(BsProgram &bp, const uint8_t *in, uint64_t in_ld, uint8_t *out, uint64_t out_ld, uint64_t s,
-              hipStream_t st);
+              hipStream_t st, bool resident_only = false);
 // One launch of the multi-set kernel over nitems items in device memory
 // (d_items, sorted by tile0, tiles numbered back to back, ntiles in all,
 // every item s >= kBsTileBytes), all for this program.

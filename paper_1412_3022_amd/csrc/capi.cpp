@@ -4,10 +4,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -16,6 +18,7 @@
 #include "engine.hpp"
 #include "gf16.hpp"
 #include "gj.hpp"
+#include "put.hpp"
 #include "pm.h"
 #include "program.hpp"
 
@@ -50,6 +53,22 @@ static int upload_stream(int dev, hipStream_t *out) {
 
 ProgEntry::~ProgEntry() { free_device_copies(dev); }
 
+static std::atomic<size_t> g_table_bytes{0};
+static std::atomic<uint32_t> g_fail_uploads{0};
+
+size_t device_table_bytes() { return g_table_bytes.load(); }
+void fail_next_uploads(uint32_t n) { g_fail_uploads.store(n); }
+
+// Undo a partly made copy (the upload failed after the allocation).
+static void drop_copy(DevCopy &dc) {
+    if (dc.ready) (void)hipEventDestroy(dc.ready);
+    if (dc.ptr) {
+        (void)hipFree(dc.ptr);
+        g_table_bytes -= dc.bytes;
+    }
+    dc = DevCopy{};
+}
+
 int device_copy(std::mutex &mu, std::map<int, DevCopy> &dev, const void *host, size_t bytes, hipStream_t user,
                 const void **out) {
     int devid = 0;
@@ -58,14 +77,26 @@ int device_copy(std::mutex &mu, std::map<int, DevCopy> &dev, const void *host, s
     std::lock_guard<std::mutex> lk(mu);
     DevCopy &dc = dev[devid];
     if (!dc.ptr) {
+        for (uint32_t n = g_fail_uploads.load(); n > 0;)
+            if (g_fail_uploads.compare_exchange_weak(n, n - 1)) return ST_ENOMEM;
         hipStream_t up = nullptr;
         int st = upload_stream(devid, &up);
         if (st != ST_OK) return st;
-        if ((e = hipMalloc(&dc.ptr, bytes)) != hipSuccess) { dc.ptr = nullptr; return hip_fail(e); }
-        if ((e = hipMemcpyAsync(dc.ptr, host, bytes, hipMemcpyHostToDevice, up)) != hipSuccess)
+        if ((e = hipMalloc(&dc.ptr, bytes)) != hipSuccess) {
+            dc.ptr = nullptr;
+            return e == hipErrorOutOfMemory ? ST_ENOMEM : hip_fail(e);
+        }
+        dc.bytes = bytes;
+        g_table_bytes += bytes;
+        if ((e = hipMemcpyAsync(dc.ptr, host, bytes, hipMemcpyHostToDevice, up)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&dc.ready, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventRecord(dc.ready, up)) != hipSuccess) {
+            // a failed copy must not be taken for a good one by the next call;
+            // the upload stream is drained so the memory is not freed under it
+            (void)hipStreamSynchronize(up);
+            drop_copy(dc);
             return hip_fail(e);
-        if ((e = hipEventCreateWithFlags(&dc.ready, hipEventDisableTiming)) != hipSuccess) return hip_fail(e);
-        if ((e = hipEventRecord(dc.ready, up)) != hipSuccess) return hip_fail(e);
+        }
     }
     if (!dc.done) {
         e = hipEventQuery(dc.ready);
@@ -82,10 +113,7 @@ int device_copy(std::mutex &mu, std::map<int, DevCopy> &dev, const void *host, s
 }
 
 void free_device_copies(std::map<int, DevCopy> &dev) {
-    for (auto &kv : dev) {
-        if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
-        if (kv.second.ptr) (void)hipFree(kv.second.ptr);
-    }
+    for (auto &kv : dev) drop_copy(kv.second);
     dev.clear();
 }
 
@@ -109,6 +137,36 @@ int device_copy_sync(std::mutex &mu, std::map<int, DevCopy> &dev, const void *ho
         if ((e = hipEventSynchronize(dc.ready)) != hipSuccess) return hip_fail(e);
         dc.done = true;
     }
+    return ST_OK;
+}
+
+size_t ProgEntry::upload_bytes() {
+    int devid = 0;
+    if (hipGetDevice(&devid) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = dev.find(devid);
+    return it != dev.end() && it->second.ptr ? 0 : prog.blob.size() * sizeof(uint32_t);
+}
+
+int ProgEntry::device_ptr_resident(hipStream_t user, const uint32_t **out) {
+    int devid = 0;
+    hipError_t e = hipGetDevice(&devid);
+    if (e != hipSuccess) return hip_fail(e);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = dev.find(devid);
+    if (it == dev.end() || !it->second.ptr) return ST_ENOTREADY;
+    DevCopy &dc = it->second;
+    if (!dc.done) {
+        e = hipEventQuery(dc.ready);
+        if (e == hipSuccess) {
+            dc.done = true;
+        } else if (e == hipErrorNotReady) {
+            if ((e = hipStreamWaitEvent(user, dc.ready, 0)) != hipSuccess) return hip_fail(e);
+        } else {
+            return hip_fail(e);
+        }
+    }
+    *out = static_cast<const uint32_t *>(dc.ptr);
     return ST_OK;
 }
 
@@ -179,37 +237,125 @@ bool overlaps(const void *a, size_t a_ld, size_t a_n, const void *b, size_t b_ld
 }
 
 int launch_program(ProgEntry &pe, int vec, const uint8_t *in, size_t in_ld, size_t in_n, uint8_t *out,
-                   size_t out_ld, size_t out_n, size_t s, hipStream_t stream) {
+                   size_t out_ld, size_t out_n, size_t s, hipStream_t stream, bool resident_only) {
     if (s == 0) return ST_EINVAL;
     int st;
     if ((st = check_regions(in, in_ld, in_n, s)) != ST_OK) return st;
     if ((st = check_regions(out, out_ld, out_n, s)) != ST_OK) return st;
     if (overlaps(in, in_ld, in_n, out, out_ld, out_n, s)) return ST_EINVAL;
     if (pe.prog.ngroups == 0) return ST_OK;
-    if (vec == kVecBitslice) {
+    if (vec == kVecBitslice && !resident_only) {
         // blocks shorter than one tile, and matrices too large for a
         // specialized kernel, run on the table kernel
         if (s >= kBsTileBytes)
             if (std::shared_ptr<BsProgram> bp = pe.bitslice()) return bs_launch(*bp, in, in_ld, out, out_ld, s, stream);
         vec = 4;
-    } else if (vec == kVecAuto) {
+    } else if (vec == kVecAuto || vec == kVecBitslice) {
         if (s >= kBsTileBytes)
-            if (std::shared_ptr<BsProgram> bp = pe.bitslice_if_compiled(BS_SINGLE))
-                return bs_launch(*bp, in, in_ld, out, out_ld, s, stream);
-        vec = kVecTable;
+            if (std::shared_ptr<BsProgram> bp = pe.bitslice_if_compiled(BS_SINGLE)) {
+                st = bs_launch(*bp, in, in_ld, out, out_ld, s, stream, resident_only);
+                // compiled but not loaded on this device: the table kernel
+                // may still be resident
+                if (st != ST_ENOTREADY) return st;
+            }
+        vec = vec == kVecBitslice ? 4 : kVecTable;
     }
     const uint32_t *dprog = nullptr;
-    if ((st = pe.device_ptr(stream, &dprog)) != ST_OK) return st;
+    if ((st = resident_only ? pe.device_ptr_resident(stream, &dprog) : pe.device_ptr(stream, &dprog)) != ST_OK)
+        return st;
     PmkApply a{in, in_ld, out, out_ld, s, dprog, static_cast<uint32_t>(pe.prog.ngroups)};
     hipError_t e = pmk_apply(pe.prog.rg, vec, &a, stream);
     if (e != hipSuccess) return hip_fail(e);
     return ST_OK;
 }
 
+// ---- retired cache entries ---------------------------------------------------------
+static std::mutex g_grave_mu;
+static std::vector<std::shared_ptr<ProgEntry>> &g_grave = *new std::vector<std::shared_ptr<ProgEntry>>();
+constexpr size_t kGraveBytes = size_t(64) << 20;   // device bytes of retired entries before a reap
+constexpr size_t kGraveEntries = 256;
+
+static size_t entry_device_bytes(ProgEntry &pe) {
+    std::lock_guard<std::mutex> lk(pe.mu);
+    size_t b = 0;
+    for (auto &kv : pe.dev) b += kv.second.bytes;
+    if (pe.bs) b += 1;   // a loaded kernel module: device memory of unknown size
+    return b;
+}
+
+void reap_retired(bool sync) {
+    std::vector<std::shared_ptr<ProgEntry>> go;
+    {
+        std::lock_guard<std::mutex> lk(g_grave_mu);
+        // entries nobody else holds can no longer be launched again; those
+        // with device memory still wait for the launches already enqueued
+        for (auto it = g_grave.begin(); it != g_grave.end();) {
+            if (it->use_count() == 1 && (sync || entry_device_bytes(**it) == 0)) {
+                go.push_back(std::move(*it));
+                it = g_grave.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    }
+    if (go.empty()) return;
+    if (sync) {
+        int n = 0;
+        if (hipGetDeviceCount(&n) == hipSuccess && n > 0) {
+            int cur = 0;
+            (void)hipGetDevice(&cur);
+            // another thread's stream capture must not forbid this wait
+            hipStreamCaptureMode mode = hipStreamCaptureModeRelaxed;
+            (void)hipThreadExchangeStreamCaptureMode(&mode);
+            for (int d = 0; d < n; ++d)
+                if (hipSetDevice(d) == hipSuccess) (void)hipDeviceSynchronize();
+            (void)hipSetDevice(cur);
+            (void)hipThreadExchangeStreamCaptureMode(&mode);
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+    go.clear();   // frees device copies and unloads kernels
+}
+
+void retire(std::shared_ptr<ProgEntry> pe) {
+    if (!pe) return;
+    size_t bytes = 0, entries = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_grave_mu);
+        g_grave.push_back(std::move(pe));
+        for (auto &e : g_grave) bytes += entry_device_bytes(*e);
+        entries = g_grave.size();
+    }
+    if (bytes == 0 || entries > kGraveEntries) reap_retired(false);
+    if (bytes > kGraveBytes || entries > kGraveEntries) reap_retired(true);
+}
+
+// Drop the least recently used entries of a cache once it holds more than
+// cap: a quarter of cap at a time, entries for which busy() holds kept.
+// Each dropped value goes to drop().
+template <class Map, class Tick, class Busy, class Drop>
+void lru_trim(Map &m, size_t cap, Tick tick, Busy busy, Drop drop) {
+    if (m.size() <= cap) return;
+    std::vector<std::pair<uint64_t, typename Map::iterator>> order;
+    for (auto it = m.begin(); it != m.end(); ++it)
+        if (!busy(it->second)) order.emplace_back(tick(it->second), it);
+    std::sort(order.begin(), order.end(),
+              [](const auto &a, const auto &b) { return a.first < b.first; });
+    const size_t target = cap - cap / 4;
+    for (auto &o : order) {
+        if (m.size() <= target) break;
+        drop(o.second->second);
+        m.erase(o.second);
+    }
+}
+
 // ---- pm_apply: programs cached by matrix content ----------------------------------
+constexpr size_t kApplyCap = 256;
 static std::mutex g_apply_mu;
-static std::map<std::tuple<int, int, std::vector<uint8_t>, int>, std::unique_ptr<ProgEntry>> &g_apply =
-    *new std::map<std::tuple<int, int, std::vector<uint8_t>, int>, std::unique_ptr<ProgEntry>>();
+static uint64_t g_apply_tick = 0;
+static std::map<std::tuple<int, int, std::vector<uint8_t>, int>, std::shared_ptr<ProgEntry>> &g_apply =
+    *new std::map<std::tuple<int, int, std::vector<uint8_t>, int>, std::shared_ptr<ProgEntry>>();
 static Variant g_apply_var;
 
 void set_apply_variant(int rg, int vec) {
@@ -218,41 +364,67 @@ void set_apply_variant(int rg, int vec) {
     g_apply_var.vec = vec;
 }
 
-ProgEntry *apply_program(const Mat &A, int *vec) {
-    std::lock_guard<std::mutex> lk(g_apply_mu);
-    const int rg = g_apply_var.rg ? g_apply_var.rg : Variant::pick_rg(A);
-    *vec = g_apply_var.vec;
-    auto key = std::make_tuple(A.rows, A.cols, A.v, rg);
-    auto it = g_apply.find(key);
-    if (it != g_apply.end()) return it->second.get();
-    auto pe = std::make_unique<ProgEntry>();
-    pe->prog = build_program(A, rg);
-    pe->A = A;
-    ProgEntry *raw = pe.get();
-    g_apply.emplace(std::move(key), std::move(pe));
-    return raw;
+std::shared_ptr<ProgEntry> apply_program(const Mat &A, int *vec) {
+    std::vector<std::shared_ptr<ProgEntry>> evicted;
+    std::shared_ptr<ProgEntry> out;
+    {
+        std::lock_guard<std::mutex> lk(g_apply_mu);
+        const int rg = g_apply_var.rg ? g_apply_var.rg : Variant::pick_rg(A);
+        *vec = g_apply_var.vec;
+        auto key = std::make_tuple(A.rows, A.cols, A.v, rg);
+        auto it = g_apply.find(key);
+        if (it == g_apply.end()) {
+            auto pe = std::make_shared<ProgEntry>();
+            pe->prog = build_program(A, rg);
+            pe->A = A;
+            it = g_apply.emplace(std::move(key), std::move(pe)).first;
+        }
+        it->second->tick = ++g_apply_tick;
+        out = it->second;
+        lru_trim(
+            g_apply, kApplyCap, [](const std::shared_ptr<ProgEntry> &p) { return p->tick; },
+            [&](const std::shared_ptr<ProgEntry> &p) { return p == out; },
+            [&](std::shared_ptr<ProgEntry> &p) { evicted.push_back(std::move(p)); });
+    }
+    for (auto &p : evicted) retire(std::move(p));
+    return out;
 }
 
 }  // namespace pmrc
 
 // ---- the code object -------------------------------------------------------------
+// Per-failure-pattern caches hold at most this many entries each (helper,
+// newcomer and decode patterns, specific-decode node lists) unless
+// pm_code_set_cache_limit says otherwise; beyond it the least recently used
+// are evicted (and their device memory retired).
+constexpr size_t kPatternCap = 256;
+
+template <class V>
+struct Aged {
+    V v;
+    uint64_t tick = 0;
+};
+
 struct pm_code {
     CodeMats m;
     // GF(2^16) codes keep everything here (m holds only k, d, n, alpha, B)
     std::unique_ptr<w16::Ctx16> w16;
     std::mutex mu;
     Variant var[4];
-    std::map<std::tuple<int>, std::unique_ptr<ProgEntry>> enc;                      // rg
-    std::map<std::pair<int, int>, std::unique_ptr<ProgEntry>> helper;              // failed, rg
-    std::map<std::tuple<int, std::vector<int>, int>, std::unique_ptr<ProgEntry>> newcomer;
-    std::map<std::pair<std::vector<int>, int>, std::unique_ptr<ProgEntry>> decode;  // nodes, rg
-    std::map<int, Mat> helper_mat;
-    std::map<std::pair<int, std::vector<int>>, Mat> newcomer_mat;
-    std::map<std::vector<int>, std::pair<Mat, std::vector<int>>> decode_mat;
+    uint64_t tick = 0;            // use counter of the caches below
+    size_t cap = kPatternCap;     // entries per per-pattern cache
+    std::map<std::tuple<int>, std::shared_ptr<ProgEntry>> enc;                      // rg
+    std::map<std::pair<int, int>, std::shared_ptr<ProgEntry>> helper;              // failed, rg
+    std::map<std::tuple<int, std::vector<int>, int>, std::shared_ptr<ProgEntry>> newcomer;
+    std::map<std::pair<std::vector<int>, int>, std::shared_ptr<ProgEntry>> decode;  // nodes, rg
+    std::map<int, Aged<Mat>> helper_mat;
+    std::map<std::pair<int, std::vector<int>>, Aged<Mat>> newcomer_mat;
+    std::map<std::vector<int>, Aged<std::pair<Mat, std::vector<int>>>> decode_mat;
     // specific PM-MSR decode per node list: its factors and their programs
     struct Specific {
         Mat F[kSpecificPasses];
-        std::map<int, std::unique_ptr<ProgEntry>> progs[kSpecificPasses];   // by rg
+        std::map<int, std::shared_ptr<ProgEntry>> progs[kSpecificPasses];   // by rg
+        uint64_t tick = 0;
     };
     std::map<std::vector<int>, Specific> specific;
     // device copies of the generator the node contents follow (Gsys), for
@@ -264,20 +436,48 @@ struct pm_code {
 
 namespace {
 
-// Find or build the program for matrix A under variant v (rg chosen once per
-// matrix when v.rg == 0).  Caller holds code->mu.
+// Find or build the program for matrix A (key ends with the row-group size),
+// marked used now; evicts the map's least recently used entries beyond the
+// code's cap into `evicted`.  Caller holds code->mu.
 template <class Map, class Key>
-ProgEntry *get_prog(Map &map, const Key &key_prefix_rg, const Mat &A, const std::vector<int> &in_map) {
+std::shared_ptr<ProgEntry> get_prog(pm_code *c, Map &map, const Key &key_prefix_rg, const Mat &A,
+                                    const std::vector<int> &in_map,
+                                    std::vector<std::shared_ptr<ProgEntry>> &evicted) {
     auto it = map.find(key_prefix_rg);
-    if (it != map.end()) return it->second.get();
-    auto pe = std::make_unique<ProgEntry>();
-    int rg = std::get<std::tuple_size<Key>::value - 1>(key_prefix_rg);
-    pe->prog = build_program(A, rg, in_map);
-    pe->A = A;
-    pe->in_map = in_map;
-    ProgEntry *raw = pe.get();
-    map.emplace(key_prefix_rg, std::move(pe));
-    return raw;
+    if (it == map.end()) {
+        auto pe = std::make_shared<ProgEntry>();
+        int rg = std::get<std::tuple_size<Key>::value - 1>(key_prefix_rg);
+        pe->prog = build_program(A, rg, in_map);
+        pe->A = A;
+        pe->in_map = in_map;
+        it = map.emplace(key_prefix_rg, std::move(pe)).first;
+    }
+    it->second->tick = ++c->tick;
+    std::shared_ptr<ProgEntry> out = it->second;
+    lru_trim(
+        map, c->cap, [](const std::shared_ptr<ProgEntry> &p) { return p->tick; },
+        // held by a batch plan, a queued request or a call in progress
+        [](const std::shared_ptr<ProgEntry> &p) { return p.use_count() > 1; },
+        [&](std::shared_ptr<ProgEntry> &p) { evicted.push_back(std::move(p)); });
+    return out;
+}
+
+// Find or build a per-pattern matrix, marked used now; trims the map.
+template <class Map, class Key, class Build>
+int get_mat(pm_code *c, Map &map, const Key &key, Build build, typename Map::mapped_type **out) {
+    auto it = map.find(key);
+    if (it == map.end()) {
+        typename Map::mapped_type a;
+        int st = build(a.v);
+        if (st != ST_OK) return st;
+        it = map.emplace(key, std::move(a)).first;
+    }
+    it->second.tick = ++c->tick;
+    lru_trim(
+        map, c->cap, [](const typename Map::mapped_type &a) { return a.tick; },
+        [&](const typename Map::mapped_type &a) { return &a == &it->second; }, [](typename Map::mapped_type &) {});
+    *out = &it->second;
+    return ST_OK;
 }
 
 int resolve_rg(Variant &v, const Mat &A, std::map<std::vector<uint8_t>, int> *memo = nullptr) {
@@ -287,7 +487,10 @@ int resolve_rg(Variant &v, const Mat &A, std::map<std::vector<uint8_t>, int> *me
         if (it != memo->end()) return it->second;
     }
     int rg = Variant::pick_rg(A);
-    if (memo) (*memo)[A.v] = rg;
+    if (memo) {
+        if (memo->size() >= 4096) memo->clear();   // a cost-model memo: cheap to rebuild
+        (*memo)[A.v] = rg;
+    }
     return rg;
 }
 
@@ -325,60 +528,63 @@ int resolve_op(pm_code *c, int op, uint32_t failed, const uint32_t *ids, Resolve
         for (int v : list)
             if (v < 0 || v >= m.n || (op == OPK_NEWCOMER && v == static_cast<int>(failed))) return ST_EINVAL;
     }
-    std::lock_guard<std::mutex> lk(c->mu);
-    const Variant &var = c->var[op];
-    r->vec = var.vec;
-    switch (op) {
-        case OPK_ENCODE: {
-            const int rg = pick_rg_cached(c->var[0], m.enc);
-            r->pe = get_prog(c->enc, std::make_tuple(rg), m.enc, {});
-            r->in_n = static_cast<size_t>(m.B);
-            r->out_n = static_cast<size_t>(m.enc.rows);
-            return ST_OK;
-        }
-        case OPK_HELPER: {
-            auto it = c->helper_mat.find(static_cast<int>(failed));
-            if (it == c->helper_mat.end())
-                it = c->helper_mat.emplace(static_cast<int>(failed), helper_row(m, static_cast<int>(failed))).first;
-            const int rg = var.rg ? var.rg : 4;
-            r->pe = get_prog(c->helper, std::make_pair(static_cast<int>(failed), rg), it->second, {});
-            r->in_n = static_cast<size_t>(m.kind == KIND_RS ? 1 : m.alpha);
-            r->out_n = 1;
-            return ST_OK;
-        }
-        case OPK_NEWCOMER: {
-            auto key = std::make_pair(static_cast<int>(failed), list);
-            auto it = c->newcomer_mat.find(key);
-            if (it == c->newcomer_mat.end()) {
-                Mat R;
-                int st = newcomer_matrix(m, static_cast<int>(failed), list, R);
-                if (st != ST_OK) return st;
-                it = c->newcomer_mat.emplace(key, std::move(R)).first;
+    std::vector<std::shared_ptr<ProgEntry>> evicted;
+    int st = ST_OK;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        const Variant &var = c->var[op];
+        r->vec = var.vec;
+        switch (op) {
+            case OPK_ENCODE: {
+                const int rg = pick_rg_cached(c->var[0], m.enc);
+                r->pe = get_prog(c, c->enc, std::make_tuple(rg), m.enc, {}, evicted);
+                r->in_n = static_cast<size_t>(m.B);
+                r->out_n = static_cast<size_t>(m.enc.rows);
+                break;
             }
-            const int rg = pick_rg_cached(c->var[2], it->second);
-            r->pe = get_prog(c->newcomer, std::make_tuple(static_cast<int>(failed), list, rg), it->second, {});
-            r->in_n = static_cast<size_t>(m.d);
-            r->out_n = static_cast<size_t>(it->second.rows);
-            return ST_OK;
-        }
-        case OPK_DECODE: {
-            auto it = c->decode_mat.find(list);
-            if (it == c->decode_mat.end()) {
-                Mat D;
-                std::vector<int> used;
-                int st = decode_matrix(m, list, D, used);
-                if (st != ST_OK) return st;
-                it = c->decode_mat.emplace(list, std::make_pair(std::move(D), std::move(used))).first;
+            case OPK_HELPER: {
+                Aged<Mat> *hm = nullptr;
+                st = get_mat(c, c->helper_mat, static_cast<int>(failed),
+                             [&](Mat &out) { out = helper_row(m, static_cast<int>(failed)); return ST_OK; }, &hm);
+                if (st != ST_OK) break;
+                const int rg = var.rg ? var.rg : 4;
+                r->pe = get_prog(c, c->helper, std::make_pair(static_cast<int>(failed), rg), hm->v, {}, evicted);
+                r->in_n = static_cast<size_t>(m.kind == KIND_RS ? 1 : m.alpha);
+                r->out_n = 1;
+                break;
             }
-            const int rg = pick_rg_cached(c->var[3], it->second.first);
-            r->pe = get_prog(c->decode, std::make_pair(list, rg), it->second.first, it->second.second);
-            r->in_n = static_cast<size_t>(m.k) * static_cast<size_t>(m.alpha);
-            r->out_n = static_cast<size_t>(m.B);
-            return ST_OK;
+            case OPK_NEWCOMER: {
+                Aged<Mat> *nm = nullptr;
+                st = get_mat(c, c->newcomer_mat, std::make_pair(static_cast<int>(failed), list),
+                             [&](Mat &out) { return newcomer_matrix(m, static_cast<int>(failed), list, out); }, &nm);
+                if (st != ST_OK) break;
+                const int rg = pick_rg_cached(c->var[2], nm->v);
+                r->pe = get_prog(c, c->newcomer, std::make_tuple(static_cast<int>(failed), list, rg), nm->v, {},
+                                 evicted);
+                r->in_n = static_cast<size_t>(m.d);
+                r->out_n = static_cast<size_t>(nm->v.rows);
+                break;
+            }
+            case OPK_DECODE: {
+                Aged<std::pair<Mat, std::vector<int>>> *dm = nullptr;
+                st = get_mat(c, c->decode_mat, list,
+                             [&](std::pair<Mat, std::vector<int>> &out) {
+                                 return decode_matrix(m, list, out.first, out.second);
+                             },
+                             &dm);
+                if (st != ST_OK) break;
+                const int rg = pick_rg_cached(c->var[3], dm->v.first);
+                r->pe = get_prog(c, c->decode, std::make_pair(list, rg), dm->v.first, dm->v.second, evicted);
+                r->in_n = static_cast<size_t>(m.k) * static_cast<size_t>(m.alpha);
+                r->out_n = static_cast<size_t>(m.B);
+                break;
+            }
+            default:
+                st = ST_EINVAL;
         }
-        default:
-            return ST_EINVAL;
     }
+    for (auto &p : evicted) retire(std::move(p));
+    return st;
 }
 
 }  // namespace pmrc
@@ -389,12 +595,14 @@ namespace {
 // program of each pass.  The passes are the leading factors with rows: all
 // five for systematic PM-MSR, four without the re-encoding, two for PM-MBR.
 struct SpecificOps {
-    ProgEntry *pe[kSpecificPasses] = {};
+    std::shared_ptr<ProgEntry> pe[kSpecificPasses];
     int npass = 0;
     int rows[kSpecificPasses] = {};
 };
 
-int resolve_specific(pm_code *c, const uint32_t *ids, SpecificOps *out) {
+// lookup_only: build nothing (no factors, no programs); ST_ENOTREADY when the
+// node list has not been resolved before.
+int resolve_specific(pm_code *c, const uint32_t *ids, SpecificOps *out, bool lookup_only = false) {
     if (!c || !ids) return ST_EINVAL;
     if (c->w16) return ST_EUNSUPPORTED;
     const CodeMats &m = c->m;
@@ -405,32 +613,147 @@ int resolve_specific(pm_code *c, const uint32_t *ids, SpecificOps *out) {
     if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) return ST_EINVAL;
     for (int v : list)
         if (v < 0 || v >= m.n) return ST_EINVAL;
-    std::lock_guard<std::mutex> lk(c->mu);
-    auto it = c->specific.find(list);
-    if (it == c->specific.end()) {
-        pm_code::Specific sp;
-        int st = specific_decode_factors(m, list, sp.F);
-        if (st != ST_OK) return st;
-        it = c->specific.emplace(list, std::move(sp)).first;
-    }
-    pm_code::Specific &sp = it->second;
-    out->npass = 0;
-    while (out->npass < kSpecificPasses && sp.F[out->npass].rows) ++out->npass;
-    for (int p = 0; p < out->npass; ++p) {
-        const Mat &F = sp.F[p];
-        const int rg = pick_rg_cached(c->var[3], F);
-        auto &map = sp.progs[p];
-        auto pit = map.find(rg);
-        if (pit == map.end()) {
-            auto pe = std::make_unique<ProgEntry>();
-            pe->prog = build_program(F, rg);
-            pe->A = F;
-            pit = map.emplace(rg, std::move(pe)).first;
+    std::vector<std::shared_ptr<ProgEntry>> evicted;
+    int st = ST_OK;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        auto it = c->specific.find(list);
+        if (it == c->specific.end()) {
+            if (lookup_only) return ST_ENOTREADY;
+            pm_code::Specific sp;
+            st = specific_decode_factors(m, list, sp.F);
+            if (st != ST_OK) return st;
+            it = c->specific.emplace(list, std::move(sp)).first;
         }
-        out->pe[p] = pit->second.get();
-        out->rows[p] = F.rows;
+        pm_code::Specific &sp = it->second;
+        sp.tick = ++c->tick;
+        out->npass = 0;
+        while (out->npass < kSpecificPasses && sp.F[out->npass].rows) ++out->npass;
+        for (int p = 0; p < out->npass && st == ST_OK; ++p) {
+            const Mat &F = sp.F[p];
+            const int rg = pick_rg_cached(c->var[3], F);
+            auto &map = sp.progs[p];
+            auto pit = map.find(rg);
+            if (pit == map.end()) {
+                if (lookup_only) {
+                    st = ST_ENOTREADY;
+                    break;
+                }
+                auto pe = std::make_shared<ProgEntry>();
+                pe->prog = build_program(F, rg);
+                pe->A = F;
+                pit = map.emplace(rg, std::move(pe)).first;
+            }
+            out->pe[p] = pit->second;
+            out->rows[p] = F.rows;
+        }
+        const pm_code::Specific *cur = &it->second;
+        lru_trim(
+            c->specific, c->cap, [](const pm_code::Specific &x) { return x.tick; },
+            [&](const pm_code::Specific &x) {
+                if (&x == cur) return true;
+                for (auto &mp : x.progs)
+                    for (auto &kv : mp)
+                        if (kv.second.use_count() > 1) return true;
+                return false;
+            },
+            [&](pm_code::Specific &x) {
+                for (auto &mp : x.progs)
+                    for (auto &kv : mp) evicted.push_back(std::move(kv.second));
+            });
     }
-    return ST_OK;
+    for (auto &p : evicted) retire(std::move(p));
+    return st;
+}
+
+// Live GF(2^8) codes, for trims of the table caches across codes.
+std::mutex g_codes_mu;
+std::set<pm_code *> &g_codes = *new std::set<pm_code *>();
+
+void register_code(pm_code *c) {
+    std::lock_guard<std::mutex> lk(g_codes_mu);
+    g_codes.insert(c);
+}
+
+void unregister_code(pm_code *c) {
+    std::lock_guard<std::mutex> lk(g_codes_mu);
+    g_codes.erase(c);
+}
+
+// Evict the least recently used per-pattern entries of a code beyond `keep`
+// per cache (entries in use stay).  Caller holds c->mu.
+void trim_code_locked(pm_code *c, size_t keep, std::vector<std::shared_ptr<ProgEntry>> &evicted) {
+    auto tick = [](const std::shared_ptr<ProgEntry> &p) { return p->tick; };
+    auto busy = [](const std::shared_ptr<ProgEntry> &p) { return p.use_count() > 1; };
+    auto drop = [&](std::shared_ptr<ProgEntry> &p) { evicted.push_back(std::move(p)); };
+    lru_trim(c->helper, keep, tick, busy, drop);
+    lru_trim(c->newcomer, keep, tick, busy, drop);
+    lru_trim(c->decode, keep, tick, busy, drop);
+    auto none = [](auto &) {};
+    auto mtick = [](const auto &a) { return a.tick; };
+    auto mbusy = [](const auto &) { return false; };
+    lru_trim(c->helper_mat, keep, mtick, mbusy, none);
+    lru_trim(c->newcomer_mat, keep, mtick, mbusy, none);
+    lru_trim(c->decode_mat, keep, mtick, mbusy, none);
+    lru_trim(
+        c->specific, keep, [](const pm_code::Specific &x) { return x.tick; },
+        [](const pm_code::Specific &x) {
+            for (auto &mp : x.progs)
+                for (auto &kv : mp)
+                    if (kv.second.use_count() > 1) return true;
+            return false;
+        },
+        [&](pm_code::Specific &x) {
+            for (auto &mp : x.progs)
+                for (auto &kv : mp) evicted.push_back(std::move(kv.second));
+        });
+}
+
+}  // namespace
+
+namespace pmrc {
+
+void trim_tables(size_t target) {
+    for (int round = 0; round < 6 && device_table_bytes() > target; ++round) {
+        std::vector<std::shared_ptr<ProgEntry>> evicted;
+        {
+            std::lock_guard<std::mutex> lk(g_codes_mu);
+            for (pm_code *c : g_codes) {
+                std::lock_guard<std::mutex> lc(c->mu);
+                // halve every per-pattern cache, oldest entries first
+                size_t most = std::max({c->helper.size(), c->newcomer.size(), c->decode.size(),
+                                        c->specific.size()});
+                trim_code_locked(c, most / 2, evicted);
+            }
+        }
+        for (auto &p : evicted) retire(std::move(p));
+        reap_retired(true);
+        {
+            std::lock_guard<std::mutex> lk(g_apply_mu);
+            if (round >= 2) {   // the pm_apply cache last
+                std::vector<std::shared_ptr<ProgEntry>> ev2;
+                lru_trim(
+                    g_apply, g_apply.size() / 2, [](const std::shared_ptr<ProgEntry> &p) { return p->tick; },
+                    [](const std::shared_ptr<ProgEntry> &p) { return p.use_count() > 1; },
+                    [&](std::shared_ptr<ProgEntry> &p) { ev2.push_back(std::move(p)); });
+                evicted.swap(ev2);
+            }
+        }
+        for (auto &p : evicted) retire(std::move(p));
+    }
+    reap_retired(true);
+}
+
+}  // namespace pmrc
+
+namespace {
+
+// Workspace of pm_repair: the d helper blocks (what the helpers send), then
+// the launch list of the projections (d multi-set items), 16-byte aligned.
+size_t repair_ws_bytes(const CodeMats &m, size_t s) {
+    const size_t d = static_cast<size_t>(m.kind == KIND_RS ? m.k : m.d);
+    const size_t ld = (s + 15) / 16 * 16;
+    return d * ld + (d * sizeof(BsItem) + 15) / 16 * 16;
 }
 
 // Workspace blocks of a specific decode: the outputs of every pass but the
@@ -456,6 +779,7 @@ const char *pm_status_string(pm_status st) {
         case PM_ENOMEM: return "out of memory";
         case PM_EHIP: return "HIP runtime error";
         case PM_EBUSY: return "busy";
+        case PM_ENOTREADY: return "not prepared on this device (call pm_prepare first)";
     }
     return "unknown status";
 }
@@ -495,6 +819,7 @@ pm_status pm_code_create(const pm_params *p, pm_code **out) {
         }
         int st = build_code(spec, c->m);
         if (st != ST_OK) return static_cast<pm_status>(st);
+        register_code(c.get());
         *out = c.release();
         return PM_OK;
     } catch (const std::bad_alloc &) {
@@ -502,7 +827,36 @@ pm_status pm_code_create(const pm_params *p, pm_code **out) {
     }
 }
 
-void pm_code_destroy(pm_code *code) { delete code; }
+void pm_code_destroy(pm_code *code) {
+    if (!code) return;
+    unregister_code(code);
+    delete code;
+    reap_retired(false);
+}
+
+pm_status pm_code_set_cache_limit(pm_code *c, uint32_t entries) {
+    if (!c || entries == 0) return PM_EINVAL;
+    std::vector<std::shared_ptr<ProgEntry>> evicted;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        c->cap = entries;
+        trim_code_locked(c, entries, evicted);
+    }
+    for (auto &p : evicted) retire(std::move(p));
+    return PM_OK;
+}
+
+pm_status pm_cache_release(void) {
+    reap_retired(true);
+    return PM_OK;
+}
+
+size_t pm_table_bytes(void) { return device_table_bytes(); }
+
+pm_status pm_debug_fail_uploads(uint32_t count) {
+    fail_next_uploads(count);
+    return PM_OK;
+}
 
 pm_status pm_code_dims(const pm_code *c, uint32_t *alpha, uint32_t *beta, uint32_t *B, uint32_t *enc_rows) {
     if (!c) return PM_EINVAL;
@@ -598,6 +952,50 @@ pm_status pm_decode_specific_workspace(const pm_code *c, size_t s, size_t *bytes
     return PM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// The passes of a specific decode over a workspace of at least
+// specific_ws_blocks(m) blocks of ld bytes (checked by the callers).
+// resident_only: launch only kernels and tables already on the device.
+pm_status run_specific(pm_code *c, const SpecificOps &ops, w16::Prog16 *const *pe16, const uint8_t *Y, size_t y_ld,
+                       uint8_t *X, size_t x_ld, size_t s, uint8_t *workspace, hipStream_t h, bool resident_only) {
+    const CodeMats &m = c->m;
+    const size_t ld = (s + 15) / 16 * 16;
+    // the workspace must not overlap the caller's regions
+    const uintptr_t w0 = reinterpret_cast<uintptr_t>(workspace), w1 = w0 + specific_ws_blocks(m) * ld;
+    auto clear = [&](const uint8_t *base, size_t rld, size_t rows) {
+        const uintptr_t b0 = reinterpret_cast<uintptr_t>(base), b1 = b0 + (rows - 1) * rld + s;
+        return b1 <= w0 || w1 <= b0;
+    };
+    if (!clear(Y, y_ld, static_cast<size_t>(m.k) * m.alpha) || !clear(X, x_ld, static_cast<size_t>(m.B)))
+        return PM_EINVAL;
+    // pass p reads the previous pass's output (the node blocks for p = 0) and
+    // writes the next workspace slice (X for the last pass)
+    const uint8_t *in = Y;
+    size_t in_ld = y_ld, in_n = static_cast<size_t>(m.k) * m.alpha;
+    uint8_t *slice = workspace;
+    for (int p = 0; p < ops.npass; ++p) {
+        const bool last = p == ops.npass - 1;
+        uint8_t *out = last ? X : slice;
+        const size_t out_ld = last ? x_ld : ld;
+        const int st = c->w16 ? w16::launch16(*pe16[p], in, in_ld, in_n, out, out_ld, ops.rows[p], s, h)
+                              : launch_program(*ops.pe[p], kVecAuto, in, in_ld, in_n, out, out_ld, ops.rows[p], s, h,
+                                               resident_only);
+        if (st != ST_OK) return static_cast<pm_status>(st);
+        in = out;
+        in_ld = out_ld;
+        in_n = static_cast<size_t>(ops.rows[p]);
+        slice += static_cast<size_t>(ops.rows[p]) * ld;
+    }
+    return PM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 pm_status pm_decode_specific(const pm_code *cc, const uint32_t *nodes, const uint8_t *Y, size_t y_ld, uint8_t *X,
                              size_t x_ld, size_t s, uint8_t *workspace, size_t workspace_bytes, pm_stream stream) {
     if (s == 0 || !cc) return PM_EINVAL;
@@ -608,38 +1006,11 @@ pm_status pm_decode_specific(const pm_code *cc, const uint32_t *nodes, const uin
     int st = c->w16 ? w16::resolve_specific16(*c->w16, nodes, pe16, ops.rows, &ops.npass)
                     : resolve_specific(c, nodes, &ops);
     if (st != ST_OK) return static_cast<pm_status>(st);
-    const CodeMats &m = c->m;
     const size_t ld = (s + 15) / 16 * 16;
     if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 15u) ||
-        workspace_bytes < specific_ws_blocks(m) * ld)
+        workspace_bytes < specific_ws_blocks(c->m) * ld)
         return PM_EINVAL;
-    // the workspace must not overlap the caller's regions
-    const uintptr_t w0 = reinterpret_cast<uintptr_t>(workspace), w1 = w0 + specific_ws_blocks(m) * ld;
-    auto clear = [&](const uint8_t *base, size_t rld, size_t rows) {
-        const uintptr_t b0 = reinterpret_cast<uintptr_t>(base), b1 = b0 + (rows - 1) * rld + s;
-        return b1 <= w0 || w1 <= b0;
-    };
-    if (!clear(Y, y_ld, static_cast<size_t>(m.k) * m.alpha) || !clear(X, x_ld, static_cast<size_t>(m.B)))
-        return PM_EINVAL;
-    hipStream_t h = reinterpret_cast<hipStream_t>(stream);
-    // pass p reads the previous pass's output (the node blocks for p = 0) and
-    // writes the next workspace slice (X for the last pass)
-    const uint8_t *in = Y;
-    size_t in_ld = y_ld, in_n = static_cast<size_t>(m.k) * m.alpha;
-    uint8_t *slice = workspace;
-    for (int p = 0; p < ops.npass; ++p) {
-        const bool last = p == ops.npass - 1;
-        uint8_t *out = last ? X : slice;
-        const size_t out_ld = last ? x_ld : ld;
-        st = c->w16 ? w16::launch16(*pe16[p], in, in_ld, in_n, out, out_ld, ops.rows[p], s, h)
-                    : launch_program(*ops.pe[p], kVecAuto, in, in_ld, in_n, out, out_ld, ops.rows[p], s, h);
-        if (st != ST_OK) return static_cast<pm_status>(st);
-        in = out;
-        in_ld = out_ld;
-        in_n = static_cast<size_t>(ops.rows[p]);
-        slice += static_cast<size_t>(ops.rows[p]) * ld;
-    }
-    return PM_OK;
+    return run_specific(c, ops, pe16, Y, y_ld, X, x_ld, s, workspace, reinterpret_cast<hipStream_t>(stream), false);
 }
 
 pm_status pm_decode_specific_factor(const pm_code *cc, const uint32_t *nodes, int which, uint8_t *dst, size_t cap,
@@ -664,11 +1035,21 @@ pm_status pm_decode_specific_factor(const pm_code *cc, const uint32_t *nodes, in
         }
         return PM_OK;
     }
-    SpecificOps ops;
-    int st = resolve_specific(c, nodes, &ops);
-    if (st != ST_OK) return static_cast<pm_status>(st);
-    std::lock_guard<std::mutex> lk(c->mu);
-    const Mat &F = c->specific.find(std::vector<int>(nodes, nodes + c->m.k))->second.F[which];
+    // resolve, then read the factor under the lock; another thread's use
+    // of the cache may evict the entry in between, hence the retry
+    Mat F;
+    for (int attempt = 0;; ++attempt) {
+        SpecificOps ops;
+        int st = resolve_specific(c, nodes, &ops);
+        if (st != ST_OK) return static_cast<pm_status>(st);
+        std::lock_guard<std::mutex> lk(c->mu);
+        auto it = c->specific.find(std::vector<int>(nodes, nodes + c->m.k));
+        if (it != c->specific.end()) {
+            F = it->second.F[which];
+            break;
+        }
+        if (attempt >= 8) return PM_EBUSY;
+    }
     if (rows) *rows = static_cast<uint32_t>(F.rows);
     if (cols) *cols = static_cast<uint32_t>(F.cols);
     if (dst) {
@@ -711,17 +1092,14 @@ pm_status pm_decode_matrix(const pm_code *cc, const uint32_t *nodes, uint8_t *D,
         if (v < 0 || v >= m.n) return PM_EINVAL;
     if (D && cap < static_cast<size_t>(m.B) * m.B) return PM_EINVAL;
     std::lock_guard<std::mutex> lk(c->mu);
-    auto it = c->decode_mat.find(list);
-    if (it == c->decode_mat.end()) {
-        Mat Dm;
-        std::vector<int> used;
-        int st = decode_matrix(m, list, Dm, used);
-        if (st != ST_OK) return static_cast<pm_status>(st);
-        it = c->decode_mat.emplace(list, std::make_pair(std::move(Dm), std::move(used))).first;
-    }
-    if (D) std::copy(it->second.first.v.begin(), it->second.first.v.end(), D);
+    Aged<std::pair<Mat, std::vector<int>>> *dm = nullptr;
+    int st = get_mat(c, c->decode_mat, list,
+                     [&](std::pair<Mat, std::vector<int>> &out) { return decode_matrix(m, list, out.first, out.second); },
+                     &dm);
+    if (st != ST_OK) return static_cast<pm_status>(st);
+    if (D) std::copy(dm->v.first.v.begin(), dm->v.first.v.end(), D);
     if (kept)
-        for (size_t q = 0; q < it->second.second.size(); ++q) kept[q] = static_cast<uint32_t>(it->second.second[q]);
+        for (size_t q = 0; q < dm->v.second.size(); ++q) kept[q] = static_cast<uint32_t>(dm->v.second[q]);
     return PM_OK;
 }
 
@@ -799,7 +1177,15 @@ extern "C" {
 
 pm_status pm_prepare(pm_code *c, int op, uint32_t failed, const uint32_t *ids, uint32_t flags, int *specialized) {
     if (specialized) *specialized = 0;
-    if (!c || op < 0 || op > 4 || (flags & ~static_cast<uint32_t>(PM_PREPARE_BATCHED))) return PM_EINVAL;
+    if (!c || op < 0 || op > 5 || (flags & ~static_cast<uint32_t>(PM_PREPARE_BATCHED))) return PM_EINVAL;
+    if (op == 5) {   // pm_repair: the projections as one multi-set launch, then the newcomer
+        if (c->w16) return pm_prepare(c, 2, failed, ids, 0, specialized);
+        int s1 = 0, s2 = 0;
+        pm_status st = pm_prepare(c, 1, failed, nullptr, PM_PREPARE_BATCHED, &s1);
+        if (st == PM_OK) st = pm_prepare(c, 2, failed, ids, flags, &s2);
+        if (specialized) *specialized = s1 && s2;
+        return st;
+    }
     if (c->w16) {   // the matrices and their programs, staged on the device; no specialized kernel
         if (flags & PM_PREPARE_BATCHED) return PM_EUNSUPPORTED;
         w16::Prog16 *pe[kSpecificPasses] = {};
@@ -862,6 +1248,73 @@ pm_status pm_repair_helper(const pm_code *cc, uint32_t failed, const uint8_t *no
                                                  reinterpret_cast<hipStream_t>(stream)));
 }
 
+pm_status pm_repair_workspace(const pm_code *c, size_t s, size_t *bytes) {
+    if (!c || !bytes || s == 0) return PM_EINVAL;
+    *bytes = repair_ws_bytes(c->m, s);
+    return PM_OK;
+}
+
+pm_status pm_repair(const pm_code *cc, uint32_t failed, const uint32_t *helpers, const uint8_t *const *helper_nodes,
+                    size_t node_ld, uint8_t *workspace, size_t workspace_bytes, uint8_t *out, size_t out_ld, size_t s,
+                    pm_stream stream) {
+    if (!cc || s == 0 || !helpers || !helper_nodes) return PM_EINVAL;
+    pm_code *c = const_cast<pm_code *>(cc);
+    const CodeMats &m = c->m;
+    const size_t d = static_cast<size_t>(m.kind == KIND_RS ? m.k : m.d);
+    const size_t ld = (s + 15) / 16 * 16;
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 15u) || workspace_bytes < repair_ws_bytes(m, s))
+        return PM_EINVAL;
+    hipStream_t h = reinterpret_cast<hipStream_t>(stream);
+    uint8_t *recv = workspace;
+    const size_t node_blocks = static_cast<size_t>(m.kind == KIND_RS ? 1 : m.alpha);
+    // no output may overlap an input or the other output
+    for (size_t j = 0; j < d; ++j) {
+        int st = check_regions(helper_nodes[j], node_ld, node_blocks, s);
+        if (st != ST_OK) return static_cast<pm_status>(st);
+        if (overlaps(helper_nodes[j], node_ld, node_blocks, recv, ld, d, s) ||
+            overlaps(helper_nodes[j], node_ld, node_blocks, out, out_ld, static_cast<size_t>(m.alpha), s))
+            return PM_EINVAL;
+    }
+    if (overlaps(recv, ld, d, out, out_ld, static_cast<size_t>(m.alpha), s)) return PM_EINVAL;
+    if (c->w16) {   // the GF(2^16) kernel: one projection call per helper
+        for (size_t j = 0; j < d; ++j) {
+            pm_status st = run16(cc, OPK_HELPER, failed, nullptr, helper_nodes[j], node_ld, recv + j * ld, ld, s, stream);
+            if (st != PM_OK) return st;
+        }
+        return run16(cc, OPK_NEWCOMER, failed, helpers, recv, ld, out, out_ld, s, stream);
+    }
+    Resolved hr, nr;
+    int st = resolve_op(c, OPK_HELPER, failed, nullptr, &hr);
+    if (st == ST_OK) st = resolve_op(c, OPK_NEWCOMER, failed, helpers, &nr);
+    if (st != ST_OK) return static_cast<pm_status>(st);
+    // 1. the d projections, one launch of the multi-set kernel when the
+    // helper vector's is compiled (its launch list goes to the workspace
+    // tail in stream order), else one launch per helper
+    std::shared_ptr<BsProgram> bp;
+    if (s >= kBsTileBytes && (hr.vec == kVecAuto || hr.vec == kVecBitslice) && hr.pe->prog.ngroups > 0)
+        bp = hr.pe->bitslice_if_compiled(BS_MULTI);
+    if (bp && d * sizeof(BsItem) / 4 > kPutWords) bp = nullptr;   // d > 68: list too long for one put
+    if (bp) {
+        std::vector<BsItem> items;
+        uint32_t tile = 0;
+        for (size_t j = 0; j < d; ++j) {
+            items.push_back(bs_item(helper_nodes[j], node_ld, recv + j * ld, ld, s, tile));
+            tile += items.back().ntiles;
+        }
+        uint32_t *list = reinterpret_cast<uint32_t *>(workspace + d * ld);
+        const uint32_t words = static_cast<uint32_t>(items.size() * sizeof(BsItem) / 4);
+        hipError_t e = pmk_put(list, reinterpret_cast<const uint32_t *>(items.data()), words, h);
+        if (e != hipSuccess) return static_cast<pm_status>(hip_fail(e));
+        st = bs_launch_items(*bp, reinterpret_cast<const BsItem *>(list), static_cast<uint32_t>(d), tile, h);
+    } else {
+        for (size_t j = 0; j < d && st == ST_OK; ++j)
+            st = launch_program(*hr.pe, hr.vec, helper_nodes[j], node_ld, hr.in_n, recv + j * ld, ld, 1, s, h);
+    }
+    if (st != ST_OK) return static_cast<pm_status>(st);
+    // 2. the newcomer's solve over the d received blocks
+    return static_cast<pm_status>(launch_program(*nr.pe, nr.vec, recv, ld, nr.in_n, out, out_ld, nr.out_n, s, h));
+}
+
 pm_status pm_repair_newcomer(const pm_code *cc, uint32_t failed, const uint32_t *helpers, const uint8_t *recv,
                              size_t recv_ld, uint8_t *out, size_t out_ld, size_t s, pm_stream stream) {
     if (s == 0) return PM_EINVAL;
@@ -890,7 +1343,7 @@ pm_status pm_apply(const uint8_t *A, uint32_t rows, uint32_t cols, const uint8_t
     Mat M(static_cast<int>(rows), static_cast<int>(cols));
     std::memcpy(M.v.data(), A, M.v.size());
     int vec = 0;
-    ProgEntry *pe = apply_program(M, &vec);
+    std::shared_ptr<ProgEntry> pe = apply_program(M, &vec);
     return static_cast<pm_status>(launch_program(*pe, vec, in, in_ld, cols, out, out_ld, rows, s,
                                                  reinterpret_cast<hipStream_t>(stream)));
 }

@@ -295,6 +295,11 @@ int decode_matrix(const CodeMats &c, const std::vector<int> &K, Mat &D, std::vec
         for (int j = 0; j < a; ++j)
             std::copy(c.Gsys.row(K[i] * a + j), c.Gsys.row(K[i] * a + j) + c.B,
                       rows.v.begin() + static_cast<long>(i * a + j) * c.B);
+    if (rows.rows == c.B) {   // MSR and RS: exactly B received blocks, all of them used
+        used.resize(c.B);
+        for (int r = 0; r < c.B; ++r) used[r] = r;
+        return invert(rows, D) ? ST_OK : ST_ESINGULAR;
+    }
     used = independent_rows(rows, c.B);
     if (static_cast<int>(used.size()) != c.B) return ST_ESINGULAR;
     if (!invert(select_rows(rows, used), D)) return ST_ESINGULAR;

@@ -34,7 +34,7 @@ struct CodeMats {
 // Status codes shared with the C ABI.
 enum {
     ST_OK = 0, ST_EINVAL = -1, ST_EUNSUPPORTED = -2, ST_ESINGULAR = -3,
-    ST_ENOMEM = -4, ST_EHIP = -5, ST_EBUSY = -6,
+    ST_ENOMEM = -4, ST_EHIP = -5, ST_EBUSY = -6, ST_ENOTREADY = -7, ST_ELIMIT = -8,
 };
 
 int build_code(const CodeSpec &spec, CodeMats &out);

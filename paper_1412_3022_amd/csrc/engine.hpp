@@ -34,9 +34,16 @@ int hip_fail(hipError_t e);
 
 struct DevCopy {
     void *ptr = nullptr;
+    size_t bytes = 0;
     hipEvent_t ready = nullptr;
     bool done = false;
 };
+
+// Device bytes held by table copies (all codes, devices and caches, evicted
+// entries that still wait to be freed included).
+size_t device_table_bytes();
+// Test hook: the next n table uploads fail with ST_ENOMEM before allocating.
+void fail_next_uploads(uint32_t n);
 
 // The copy of `bytes` host bytes on the current device in `dev` (guarded by
 // mu), uploaded on first use there on an internal stream; `user` is made to
@@ -53,6 +60,7 @@ void free_device_copies(std::map<int, DevCopy> &dev);
 // on the current device (on an internal stream) and makes `user` wait for
 // the upload until it is known to be complete.
 struct ProgEntry {
+    uint64_t tick = 0;          // last use, for the least-recently-used caches
     Program prog;
     Mat A;                      // the matrix (for specialized kernels)
     std::vector<int> in_map;
@@ -70,6 +78,13 @@ struct ProgEntry {
     int device_ptr(hipStream_t user, const uint32_t **out);
     // Same, but returns only once the copy has landed (for plans and graphs).
     int device_ptr_sync(const uint32_t **out);
+    // The copy on the current device if it has already been made (`user`
+    // then waits for its upload if that may still be in flight); allocates
+    // and uploads nothing: ST_ENOTREADY when there is no copy yet.
+    int device_ptr_resident(hipStream_t user, const uint32_t **out);
+    // Bytes a device_ptr call would upload on the current device (0 when
+    // the copy is there).
+    size_t upload_bytes();
 };
 
 constexpr int kVecBitslice = 32;   // variant code of the bit-sliced specialization
@@ -90,10 +105,28 @@ int check_regions(const void *base, size_t ld, size_t nblocks, size_t s);
 // Whether two region sets (a_n blocks at a with stride a_ld, b_n at b) of s
 // bytes per block share a byte range.
 bool overlaps(const void *a, size_t a_ld, size_t a_n, const void *b, size_t b_ld, size_t b_n, size_t s);
+// resident_only: use only kernels and tables already on the device (compile,
+// load, allocate and upload nothing); ST_ENOTREADY otherwise.
 int launch_program(ProgEntry &pe, int vec, const uint8_t *in, size_t in_ld, size_t in_n, uint8_t *out,
-                   size_t out_ld, size_t out_n, size_t s, hipStream_t stream);
+                   size_t out_ld, size_t out_n, size_t s, hipStream_t stream, bool resident_only = false);
 
-ProgEntry *apply_program(const Mat &A, int *vec);
+std::shared_ptr<ProgEntry> apply_program(const Mat &A, int *vec);
+
+// Evicted cache entries.  An entry leaves its cache at once but keeps its
+// device memory (tables, loaded kernels) until no launch can still read it:
+// retired entries are freed after a device-wide synchronization, and only
+// when nothing else (a batch plan, a queued request, a call in progress)
+// holds them.  That happens when retired entries hold more than a few MiB
+// of device memory (not from a thread whose stream is being captured), in
+// pm_cache_trim and at pm_code_destroy.
+void retire(std::shared_ptr<ProgEntry> pe);
+// Free what can be freed now.  sync: synchronize the device first (else
+// only entries without device memory go).
+void reap_retired(bool sync);
+// Evict least recently used per-pattern entries of every live code (and of
+// the pm_apply cache) and free them until the device bytes of tables are at
+// most `target` or nothing more can go.  Synchronizes the device.
+void trim_tables(size_t target);
 void set_apply_variant(int rg, int vec);
 
 enum OpKind { OPK_ENCODE = 0, OPK_HELPER = 1, OPK_NEWCOMER = 2, OPK_DECODE = 3 };
@@ -101,7 +134,7 @@ enum OpKind { OPK_ENCODE = 0, OPK_HELPER = 1, OPK_NEWCOMER = 2, OPK_DECODE = 3 }
 // Program and region counts of one operation of a code.  ids: d helper ids
 // (newcomer) or k node ids (decode); failed: the failed node (repair).
 struct Resolved {
-    ProgEntry *pe = nullptr;
+    std::shared_ptr<ProgEntry> pe;
     size_t in_n = 0, out_n = 0;
     int vec = kVecAuto;
 };

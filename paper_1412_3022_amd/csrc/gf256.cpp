@@ -72,13 +72,18 @@ bool invert(const Mat &A, Mat &out) {
             std::swap_ranges(out.v.begin() + static_cast<long>(p) * n, out.v.begin() + static_cast<long>(p + 1) * n,
                              out.v.begin() + static_cast<long>(c) * n);
         }
+        // columns left of c of W are already unit columns: only j >= c change
         const uint8_t *scale = gf.mul_t[gf.inv_t[W.at(c, c)]];
-        for (int j = 0; j < n; ++j) { W.at(c, j) = scale[W.at(c, j)]; out.at(c, j) = scale[out.at(c, j)]; }
+        uint8_t *wc = W.row(c), *oc = out.row(c);
+        for (int j = c; j < n; ++j) wc[j] = scale[wc[j]];
+        for (int j = 0; j < n; ++j) oc[j] = scale[oc[j]];
         for (int r = 0; r < n; ++r) {
-            uint8_t f = W.at(r, c);
+            uint8_t *wr = W.row(r), *orow = out.row(r);
+            const uint8_t f = wr[c];
             if (r == c || !f) continue;
             const uint8_t *fm = gf.mul_t[f];
-            for (int j = 0; j < n; ++j) { W.at(r, j) ^= fm[W.at(c, j)]; out.at(r, j) ^= fm[out.at(c, j)]; }
+            for (int j = c; j < n; ++j) wr[j] ^= fm[wc[j]];
+            for (int j = 0; j < n; ++j) orow[j] ^= fm[oc[j]];
         }
     }
     return true;

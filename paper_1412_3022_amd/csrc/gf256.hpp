@@ -34,6 +34,7 @@ struct Mat {
     uint8_t &at(int r, int c) { return v[static_cast<size_t>(r) * cols + c]; }
     uint8_t at(int r, int c) const { return v[static_cast<size_t>(r) * cols + c]; }
     const uint8_t *row(int r) const { return v.data() + static_cast<size_t>(r) * cols; }
+    uint8_t *row(int r) { return v.data() + static_cast<size_t>(r) * cols; }
     static Mat identity(int n);
 };
 

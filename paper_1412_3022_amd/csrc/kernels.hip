@@ -16,6 +16,12 @@
 //  - LDS: the work-group stages the group's tables in LDS once per unit and
 //    every wave reads them as VGPRs; no scalar-cache misses, no copies.
 #include <hip/hip_runtime.h>
+
+#include "put.hpp"
+
+#include <map>
+#include <mutex>
+#include <utility>
 #include <stdint.h>
 
 namespace {
@@ -538,22 +544,29 @@ struct PmkApply {
     uint32_t ngroups;
 };
 
-// Resident work-groups per CU of one kernel, and the CU count, per device.
+// Resident work-groups per CU of one kernel, and the CU count, per device:
+// measured once per (kernel, device) and kept under a lock (kernels of the
+// same signature differ in occupancy, and launches come from user threads
+// and the server's scheduler at once).
+static std::mutex g_resident_mu;
+static std::map<std::pair<const void *, int>, std::pair<int, int>> &g_resident =
+    *new std::map<std::pair<const void *, int>, std::pair<int, int>>();
+
 template <class K>
 static uint32_t resident_groups(K kernel, int *ncu_out) {
-    static int cached_dev = -1, blocks = 0, ncu = 0;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-    if (dev != cached_dev) {
+    const auto key = std::make_pair(reinterpret_cast<const void *>(kernel), dev);
+    std::lock_guard<std::mutex> lk(g_resident_mu);
+    auto it = g_resident.find(key);
+    if (it == g_resident.end()) {
         int b = 0, n = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, kThreads, 0) != hipSuccess || b < 1) b = 1;
         if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
-        blocks = b;
-        ncu = n;
-        cached_dev = dev;
+        it = g_resident.emplace(key, std::make_pair(b, n)).first;
     }
-    *ncu_out = ncu;
-    return static_cast<uint32_t>(blocks);
+    *ncu_out = it->second.second;
+    return static_cast<uint32_t>(it->second.first);
 }
 
 template <int RG, int VEC, int KIND>   // KIND: 0 scalar, 1 LDS, 2 pipelined (<= 16 columns)
@@ -648,4 +661,25 @@ extern "C" hipError_t pmk_apply(int rg, int vec, const PmkApply *h, hipStream_t 
         case 1624: return launch_apply<16, 4, 2>(*h, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+// Small device writes as a kernel: the words travel in the kernel arguments
+// (copied at launch, also under graph capture), so a launch list can be
+// placed in a caller's workspace in stream order with no host staging.
+struct PutArgs {
+    uint32_t *dst;
+    uint32_t n, pad;
+    uint32_t w[kPutWords];
+};
+
+extern "C" __global__ __launch_bounds__(256) void pm_put_words(PutArgs a) {
+    for (uint32_t i = threadIdx.x; i < a.n; i += 256u) a.dst[i] = a.w[i];
+}
+
+extern "C" hipError_t pmk_put(uint32_t *dst, const uint32_t *words, uint32_t n, hipStream_t st) {
+    if (n > kPutWords) return hipErrorInvalidValue;
+    PutArgs a{dst, n, 0, {}};
+    for (uint32_t i = 0; i < n; ++i) a.w[i] = words[i];
+    hipLaunchKernelGGL(pm_put_words, dim3(1), dim3(256), 0, st, a);
+    return hipGetLastError();
 }

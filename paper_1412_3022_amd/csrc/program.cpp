@@ -1,6 +1,7 @@
 #include "program.hpp"
 
 #include <algorithm>
+#include <array>
 #include <map>
 
 namespace pmrc {
@@ -100,7 +101,12 @@ Program build_program(const Mat &A, int rg, const std::vector<int> &in_map) {
     }
     P.ngroups = static_cast<int>(groups.size());
 
-    // Layout.
+    // Layout.  The tables of every coefficient value, packed once.
+    static const std::vector<std::array<uint32_t, kTabWords>> packed = [] {
+        std::vector<std::array<uint32_t, kTabWords>> t(256);
+        for (int c = 0; c < 256; ++c) pack_tables(static_cast<uint8_t>(c), t[c].data());
+        return t;
+    }();
     std::vector<uint32_t> rec, rowids, colids, tab4, tab1;
     auto in_col = [&](int c) { return static_cast<uint32_t>(in_map.empty() ? c : in_map[c]); };
     for (const Grp &g : groups) {
@@ -127,9 +133,8 @@ Program build_program(const Mat &A, int rg, const std::vector<int> &in_map) {
             for (size_t ci = 0; ci < cols.size(); ++ci) {
                 colids.push_back(in_col(cols[ci]));
                 for (int r = 0; r < rg; ++r) {
-                    uint32_t t[kTabWords];
                     uint8_t coef = r < static_cast<int>(g.rows.size()) ? A.at(g.rows[r], cols[ci]) : 0;
-                    pack_tables(coef, t);
+                    const uint32_t *t = packed[coef].data();
                     tab4.insert(tab4.end(), t, t + 4);
                     tab1.push_back(t[4]);
                 }

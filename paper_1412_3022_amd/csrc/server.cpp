@@ -148,7 +148,8 @@ struct pm_server {
     std::thread sched;
     int device = 0;
     // statistics
-    uint64_t batches = 0, completed = 0;
+    uint64_t batches = 0, completed = 0, failed = 0, table_high = 0;
+    uint64_t reserve = 0;             // budget part for kernel tables
     uint32_t max_busy = 0;
     int error = PM_OK;
 
@@ -188,7 +189,11 @@ struct pm_server {
     }
 
     // Pack the slot's requests into per-phase, per-class work lists, upload
-    // them and launch.
+    // them and launch.  Everything that can fail on the host (resolving
+    // device tables, list capacity) happens before anything is enqueued; if
+    // an enqueue fails part way, the stream is drained before returning, so
+    // no kernel of a failed micro-batch is still running when its requests
+    // are completed with the error.
     int launch(Slot &sl) {
         std::vector<HostItem> lists[kPhases][kClasses];
         // items whose matrix has a compiled multi-set bit-sliced kernel, per
@@ -197,35 +202,45 @@ struct pm_server {
         const int vec = static_cast<int>(cfg.dwords_per_lane ? cfg.dwords_per_lane : 2);
         const uint64_t wave_bytes = static_cast<uint64_t>(pmk_wave_bytes(vec));
         auto add = [&](int phase, const Resolved &rs, const uint8_t *in, uint64_t in_ld, uint8_t *out,
-                       uint64_t out_ld, uint64_t s) {
+                       uint64_t out_ld, uint64_t s) -> int {
             const Program &p = rs.pe->prog;
-            if (p.ngroups == 0) return;
+            if (p.ngroups == 0) return ST_OK;
             if (s >= kBsTileBytes && (rs.vec == kVecAuto || rs.vec == kVecBitslice))
                 if (std::shared_ptr<BsProgram> bp = rs.pe->bitslice_if_compiled(BS_MULTI)) {
                     auto &e = bs_lists[phase][bp.get()];
                     e.first = bp;
                     e.second.push_back(bs_item(in, in_ld, out, out_ld, s, 0));
-                    return;
+                    return ST_OK;
                 }
+            // a table not yet on the device counts against the reserve
+            const size_t need = rs.pe->upload_bytes();
+            if (need && device_table_bytes() + need > reserve) {
+                trim_tables(reserve > need ? reserve - need : 0);
+                if (device_table_bytes() + need > reserve) return ST_ENOMEM;
+            }
             const uint32_t *dprog = nullptr;
-            if (rs.pe->device_ptr_sync(&dprog) != ST_OK) return;
+            const int st = rs.pe->device_ptr_sync(&dprog);
+            if (st != ST_OK) return st;
             const uint64_t ntiles = (s + wave_bytes - 1) / wave_bytes;
             lists[phase][class_of(p.rg)].push_back(HostItem{dprog, in, out, in_ld, out_ld, s,
                                                             static_cast<uint32_t>(p.ngroups),
                                                             static_cast<uint32_t>(ntiles), 0, 0});
+            return ST_OK;
         };
         for (Req *q : sl.reqs) {
             const pm_request &r = q->r;
             uint8_t *out = arena_base + q->out_off;
             const uint64_t s = r.block_bytes;
+            int st = ST_OK;
             if (r.op == PM_REQ_REPAIR) {
                 uint8_t *scratch = out + static_cast<uint64_t>(q->out_blocks) * q->out_ld;
-                for (size_t j = 0; j < q->helpers.size(); ++j)
-                    add(0, q->helper, q->helpers[j], r.node_ld, scratch + j * q->out_ld, q->out_ld, s);
-                add(1, q->main, scratch, q->out_ld, out, q->out_ld, s);
+                for (size_t j = 0; j < q->helpers.size() && st == ST_OK; ++j)
+                    st = add(0, q->helper, q->helpers[j], r.node_ld, scratch + j * q->out_ld, q->out_ld, s);
+                if (st == ST_OK) st = add(1, q->main, scratch, q->out_ld, out, q->out_ld, s);
             } else {
-                add(0, q->main, r.in, r.in_ld, out, q->out_ld, s);
+                st = add(0, q->main, r.in, r.in_ld, out, q->out_ld, s);
             }
+            if (st != ST_OK) return st;   // nothing enqueued yet
         }
         // Number units and stage [phase][class] lists back to back.
         uint32_t pos = 0;
@@ -265,28 +280,62 @@ struct pm_server {
                                                    static_cast<uint32_t>(tile)});
                 bpos += static_cast<uint32_t>(v.size());
             }
+        // from here on work is enqueued: a failure drains the stream first
+        auto drain = [&](int st) {
+            (void)hipStreamSynchronize(sl.stream);
+            return st;
+        };
         hipError_t e;
         if (pos && (e = hipMemcpyAsync(sl.d_items, sl.h_items, pos * sizeof(HostItem), hipMemcpyHostToDevice,
                                        sl.stream)) != hipSuccess)
-            return hip_fail(e);
+            return drain(hip_fail(e));
         if (bpos && (e = hipMemcpyAsync(sl.d_bs, sl.h_bs, bpos * sizeof(BsItem), hipMemcpyHostToDevice,
                                         sl.stream)) != hipSuccess)
-            return hip_fail(e);
+            return drain(hip_fail(e));
         for (int ph = 0; ph < kPhases; ++ph) {
             for (const BsLaunch &l : bs_launches[ph]) {
                 int rc = bs_launch_items(*l.bp, sl.d_bs + l.start, l.n, l.ntiles, sl.stream);
-                if (rc != ST_OK) return rc;
+                if (rc != ST_OK) return drain(rc);
             }
             for (int c = 0; c < kClasses; ++c) {
                 if (!units[ph][c]) continue;
                 PmkBatch h{static_cast<HostItem *>(sl.d_items) + start[ph][c],
                            static_cast<uint32_t>(lists[ph][c].size()), units[ph][c],
                            sl.d_counters + (ph * kClasses + c) * 8 * 16};
-                if ((e = pmk_batch(rg_of(c), vec, &h, sl.stream)) != hipSuccess) return hip_fail(e);
+                if ((e = pmk_batch(rg_of(c), vec, &h, sl.stream)) != hipSuccess) return drain(hip_fail(e));
             }
         }
-        if ((e = hipEventRecord(sl.done, sl.stream)) != hipSuccess) return hip_fail(e);
+        if ((e = hipEventRecord(sl.done, sl.stream)) != hipSuccess) return drain(hip_fail(e));
+        const uint64_t tb = device_table_bytes();
+        std::lock_guard<std::mutex> lk(mu);
+        table_high = std::max(table_high, tb);
         return ST_OK;
+    }
+
+    // Hand a slot's requests to the client as completed with status st (or,
+    // for st == PM_OK, with the status of the slot's event).
+    void complete(Slot &sl, int st) {
+        const uint64_t t = now_ns();
+        std::lock_guard<std::mutex> lk(mu);
+        for (Req *q : sl.reqs) {
+            pm_completion c{};
+            c.ticket = q->ticket;
+            c.tag = q->r.tag;
+            c.status = st;
+            c.out = arena_base + q->out_off;
+            c.out_ld = q->out_ld;
+            c.out_blocks = q->out_blocks;
+            c.t_submit_ns = q->t_submit;
+            c.t_admit_ns = q->t_admit;
+            c.t_done_ns = t;
+            live[q->ticket] = {q->out_off, q->bytes};
+            done.push_back(c);
+            ++completed;
+            if (st != PM_OK) ++failed;
+            delete q;
+        }
+        sl.reqs.clear();
+        sl.busy = false;
     }
 
     void run() {
@@ -299,26 +348,7 @@ struct pm_server {
                 if (!sl.busy) continue;
                 hipError_t e = hipEventQuery(sl.done);
                 if (e == hipErrorNotReady) continue;
-                const uint64_t t = now_ns();
-                std::lock_guard<std::mutex> lk(mu);
-                for (Req *q : sl.reqs) {
-                    pm_completion c{};
-                    c.ticket = q->ticket;
-                    c.tag = q->r.tag;
-                    c.status = e == hipSuccess ? PM_OK : PM_EHIP;
-                    c.out = arena_base + q->out_off;
-                    c.out_ld = q->out_ld;
-                    c.out_blocks = q->out_blocks;
-                    c.t_submit_ns = q->t_submit;
-                    c.t_admit_ns = q->t_admit;
-                    c.t_done_ns = t;
-                    live[q->ticket] = {q->out_off, q->bytes};
-                    done.push_back(c);
-                    ++completed;
-                    delete q;
-                }
-                sl.reqs.clear();
-                sl.busy = false;
+                complete(sl, e == hipSuccess ? PM_OK : PM_EHIP);
                 progressed = true;
             }
             // 2. releases and admission
@@ -346,12 +376,18 @@ struct pm_server {
             }
             if (!admitted.empty()) {
                 free_slot->reqs = std::move(admitted);
-                int st = launch(*free_slot);
+                const int st = launch(*free_slot);
                 if (st != ST_OK) {
-                    std::lock_guard<std::mutex> lk(mu);
-                    error = st;
+                    // nothing of this micro-batch is on the GPU any more: its
+                    // requests complete now, with the error
+                    complete(*free_slot, st);
+                    if (st == ST_EHIP) {   // the stream may be unusable
+                        std::lock_guard<std::mutex> lk(mu);
+                        error = st;
+                    }
+                } else {
+                    free_slot->busy = true;
                 }
-                free_slot->busy = true;
                 uint32_t now_busy = 0;
                 for (const Slot &sl : slots) now_busy += sl.busy ? 1u : 0u;
                 std::lock_guard<std::mutex> lk(mu);
@@ -383,12 +419,16 @@ pm_status pm_server_create(const pm_server_cfg *cfg, pm_server **out) {
     std::unique_ptr<pm_server> s(new pm_server());
     s->cfg = *cfg;
     hipError_t e;
+    s->reserve = cfg->table_reserve_bytes ? cfg->table_reserve_bytes
+                                          : std::max<uint64_t>(cfg->hbm_budget_bytes / 32, uint64_t(16) << 20);
+    if (s->reserve + kAlign > cfg->hbm_budget_bytes) return PM_EINVAL;
+    const uint64_t arena_bytes = (cfg->hbm_budget_bytes - s->reserve) / kAlign * kAlign;
     if ((e = hipGetDevice(&s->device)) != hipSuccess) return static_cast<pm_status>(hip_fail(e));
-    if ((e = hipMalloc(reinterpret_cast<void **>(&s->arena_base), cfg->hbm_budget_bytes)) != hipSuccess) {
+    if ((e = hipMalloc(reinterpret_cast<void **>(&s->arena_base), arena_bytes)) != hipSuccess) {
         s->arena_base = nullptr;
         return e == hipErrorOutOfMemory ? PM_ENOMEM : static_cast<pm_status>(hip_fail(e));
     }
-    s->arena.init(cfg->hbm_budget_bytes);
+    s->arena.init(arena_bytes);
     s->item_cap = cfg->max_batch * 32u + 64u;
     s->slots.resize(cfg->streams);
     for (Slot &sl : s->slots) {
@@ -449,7 +489,7 @@ pm_status pm_server_submit(pm_server *s, const pm_request *req, uint64_t *ticket
         if (s->pending.size() >= s->cfg.queue_cap) return PM_EBUSY;
         const uint64_t ld = (req->block_bytes + 15) / 16 * 16;
         const uint64_t need = (q->main.out_n + (req->op == PM_REQ_REPAIR ? q->main.in_n : 0)) * ld;
-        if ((need + kAlign - 1) / kAlign * kAlign > s->cfg.hbm_budget_bytes) return PM_ENOMEM;
+        if ((need + kAlign - 1) / kAlign * kAlign > s->arena.size) return PM_ENOMEM;
         q->ticket = s->next_ticket++;
         if (ticket) *ticket = q->ticket;
         s->pending.push_back(q.release());
@@ -492,6 +532,11 @@ pm_status pm_server_stats(pm_server *s, pm_server_stat *st) {
     st->arena_used = s->arena.used;
     st->arena_high_water = s->arena.high;
     st->max_concurrent_batches = s->max_busy;
+    st->pad = 0;
+    st->failed = s->failed;
+    st->arena_bytes = s->arena.size;
+    st->table_reserve_bytes = s->reserve;
+    st->table_bytes_high = s->table_high;
     return static_cast<pm_status>(s->error);
 }
 

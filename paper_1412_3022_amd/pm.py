@@ -18,11 +18,13 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "_lib", "libpmrc.so")
 
 PM_OK, PM_EINVAL, PM_EUNSUPPORTED, PM_ESINGULAR, PM_ENOMEM, PM_EHIP, PM_EBUSY = 0, -1, -2, -3, -4, -5, -6
+PM_ENOTREADY = -7
 PM_MSR, PM_MBR, PM_RS = 0, 1, 2
 PM_VANILLA, PM_SPARSE = 0, 1
 MAT_PSI, MAT_LAMBDA, MAT_G, MAT_GSYS, MAT_ENC = 0, 1, 2, 3, 4
 OP_ENCODE, OP_HELPER, OP_NEWCOMER, OP_DECODE, OP_APPLY = 0, 1, 2, 3, 4
 OP_DECODE_SPECIFIC = 4   # pm_prepare only: the passes of pm_decode_specific
+OP_REPAIR = 5            # pm_prepare only: both steps of pm_repair
 
 
 class PMError(RuntimeError):
@@ -77,6 +79,13 @@ def _lib():
         L.pm_prepare.argtypes = [vp, i32, u32, u32p, u32, ctypes.POINTER(ctypes.c_int)]
         L.pm_decode_specific_workspace.argtypes = [vp, sz, ctypes.POINTER(ctypes.c_size_t)]
         L.pm_decode_specific.argtypes = [vp, u32p, vp, sz, vp, sz, sz, vp, sz, vp]
+        L.pm_repair_workspace.argtypes = [vp, sz, ctypes.POINTER(ctypes.c_size_t)]
+        L.pm_repair.argtypes = [vp, u32, u32p, ctypes.POINTER(vp), sz, vp, sz, vp, sz, sz, vp]
+        L.pm_code_set_cache_limit.argtypes = [vp, u32]
+        L.pm_cache_release.argtypes = []
+        L.pm_table_bytes.argtypes = []
+        L.pm_table_bytes.restype = ctypes.c_size_t
+        L.pm_debug_fail_uploads.argtypes = [u32]
         L.pm_decode_specific_factor.argtypes = [vp, u32p, i32, vp, sz, u32p, u32p]
         L.pm_decode_matrix.argtypes = [vp, u32p, vp, sz, u32p]
         L.pm_decode_matrices.argtypes = [vp, vp, u32, vp, sz, vp, vp, vp]
@@ -186,6 +195,30 @@ def pm_decode_specific(h, nodes, y_ptr, y_ld, x_ptr, x_ld, block_bytes, ws_ptr, 
                                      stream or None)
 
 
+def pm_repair_workspace(h, block_bytes):
+    n = ctypes.c_size_t()
+    _check(_lib().pm_repair_workspace(h, block_bytes, ctypes.byref(n)), "pm_repair_workspace")
+    return n.value
+
+
+def pm_repair(h, failed, helpers, node_ptrs, node_ld, ws_ptr, ws_bytes, out_ptr, out_ld, block_bytes, stream=0):
+    ptrs = (ctypes.c_void_p * len(node_ptrs))(*node_ptrs)
+    return _lib().pm_repair(h, failed, _u32arr(helpers), ptrs, node_ld, ws_ptr, ws_bytes, out_ptr, out_ld,
+                            block_bytes, stream or None)
+
+
+def cache_release():
+    _check(_lib().pm_cache_release(), "pm_cache_release")
+
+
+def table_bytes():
+    return int(_lib().pm_table_bytes())
+
+
+def debug_fail_uploads(count):
+    _check(_lib().pm_debug_fail_uploads(count), "pm_debug_fail_uploads")
+
+
 def pm_decode_matrices(h, sets_ptr, count, d_ptr, d_stride, kept_ptr, status_ptr, stream=0):
     return _lib().pm_decode_matrices(h, sets_ptr, count, d_ptr, d_stride, kept_ptr or None, status_ptr,
                                      stream or None)
@@ -226,14 +259,28 @@ def _stream_handle(stream):
     return stream.cuda_stream
 
 
-def _regions(t, rows):
-    """(pointer, ld) of a 2-D uint8 region tensor with at least `rows` rows."""
+def _regions(t, rows, block_bytes=None):
+    """(pointer, ld) of a 2-D uint8 region tensor with at least `rows` rows
+    (and rows of at least block_bytes bytes when given): the C ABI cannot
+    see allocation sizes, so the extents are checked here."""
     import torch
     if t.dtype != torch.uint8 or t.dim() != 2 or not t.is_cuda:
         raise ValueError("regions must be a 2-D torch.uint8 device tensor")
     if t.stride(1) != 1 or t.shape[0] < rows:
         raise ValueError("regions must be row-contiguous with %d rows" % rows)
+    if block_bytes is not None and t.shape[1] < block_bytes:
+        raise ValueError("region rows are %d bytes, block_bytes is %d" % (t.shape[1], block_bytes))
     return t.data_ptr(), t.stride(0)
+
+
+def _block(t, block_bytes):
+    """Pointer of a 1-D uint8 device tensor of at least block_bytes bytes."""
+    import torch
+    if t.dtype != torch.uint8 or t.dim() != 1 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("a block must be a contiguous 1-D torch.uint8 device tensor")
+    if t.numel() < block_bytes:
+        raise ValueError("block of %d bytes, block_bytes is %d" % (t.numel(), block_bytes))
+    return t.data_ptr()
 
 
 class Code:
@@ -276,8 +323,27 @@ class Code:
         _check(_lib().pm_code_node_map(self.h, m.ctypes.data, m.size), "pm_code_node_map")
         return m
 
+    def op_rows(self, op, ids=None):
+        """(input blocks, output blocks) of one operation (op 0 encode,
+        1 repair helper, 2 repair newcomer, 3 decode)."""
+        node_blocks = 1 if self.kind == PM_RS else self.alpha
+        if op == OP_ENCODE:
+            return self.B, self.enc_rows
+        if op == OP_HELPER:
+            return node_blocks, 1
+        if op == OP_NEWCOMER:
+            return (len(ids) if ids is not None else self.d), node_blocks
+        if op == OP_DECODE:
+            return (len(ids) if ids is not None else self.k) * node_blocks, self.B
+        raise ValueError("unknown operation %r" % (op,))
+
     def set_variant(self, op, rows_per_group, dwords_per_lane):
         _check(pm_set_variant(self.h, op, rows_per_group, dwords_per_lane), "pm_set_variant")
+
+    def set_cache_limit(self, entries):
+        """Patterns kept per cache of failure-pattern state (least recently
+        used evicted beyond it)."""
+        _check(_lib().pm_code_set_cache_limit(self.h, entries), "pm_code_set_cache_limit")
 
     def prepare(self, op, failed=0, ids=None, batched=False):
         """Build the operation's matrix and compile its bit-sliced kernel: the
@@ -289,26 +355,49 @@ class Code:
         return bool(spec)
 
     def encode(self, X, out, block_bytes, stream=None):
-        xp, xld = _regions(X, self.B)
-        op, old = _regions(out, self.enc_rows)
+        xp, xld = _regions(X, self.B, block_bytes)
+        op, old = _regions(out, self.enc_rows, block_bytes)
         _check(pm_encode(self.h, xp, xld, op, old, block_bytes, _stream_handle(stream)), "pm_encode")
 
     def repair_helper(self, failed, node, out, block_bytes, stream=None):
         nrows = 1 if self.kind == PM_RS else self.alpha
-        np_, nld = _regions(node, nrows)
+        np_, nld = _regions(node, nrows, block_bytes)
         if out.dim() == 2:
-            out_ptr = _regions(out, 1)[0]
+            out_ptr = _regions(out, 1, block_bytes)[0]
         else:
-            out_ptr = out.data_ptr()
+            out_ptr = _block(out, block_bytes)
         _check(pm_repair_helper(self.h, failed, np_, nld, out_ptr, block_bytes, _stream_handle(stream)),
                "pm_repair_helper")
 
     def repair_newcomer(self, failed, helpers, recv, out, block_bytes, stream=None):
-        rp, rld = _regions(recv, len(helpers))
+        rp, rld = _regions(recv, len(helpers), block_bytes)
         orows = 1 if self.kind == PM_RS else self.alpha
-        op, old = _regions(out, orows)
+        op, old = _regions(out, orows, block_bytes)
         _check(pm_repair_newcomer(self.h, failed, helpers, rp, rld, op, old, block_bytes, _stream_handle(stream)),
                "pm_repair_newcomer")
+
+    def repair(self, failed, helpers, helper_nodes, out, block_bytes, workspace=None, stream=None):
+        """Both repair steps (pm_repair): helper_nodes are d device tensors
+        of alpha blocks (rows of equal stride), in the order of helpers;
+        workspace (allocated here when None) receives the d helper blocks
+        first.  Returns the workspace."""
+        import torch
+        node_blocks = 1 if self.kind == PM_RS else self.alpha
+        strides = set()
+        for t in helper_nodes:
+            strides.add(_regions(t, node_blocks, block_bytes)[1])
+        if len(strides) != 1:
+            raise ValueError("helper node tensors must share one row stride")
+        op_, old = _regions(out, self.alpha, block_bytes)
+        need = pm_repair_workspace(self.h, block_bytes)
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=out.device)
+        if workspace.numel() < need:
+            raise ValueError("workspace smaller than pm_repair_workspace")
+        _check(pm_repair(self.h, failed, helpers, [t.data_ptr() for t in helper_nodes], strides.pop(),
+                         workspace.data_ptr(), workspace.numel(), op_, old, block_bytes, _stream_handle(stream)),
+               "pm_repair")
+        return workspace
 
     def specific_factor(self, nodes, which):
         """Factor `which` (0..4) of the specific decode for nodes, as a numpy
@@ -327,8 +416,8 @@ class Code:
         """Specific PM-MSR decode; workspace: a device uint8 tensor of at least
         pm_decode_specific_workspace bytes (allocated here when None)."""
         import torch
-        yp, yld = _regions(Y, self.k * self.alpha)
-        xp, xld = _regions(X, self.B)
+        yp, yld = _regions(Y, self.k * self.alpha, block_bytes)
+        xp, xld = _regions(X, self.B, block_bytes)
         need = pm_decode_specific_workspace(self.h, block_bytes)
         if workspace is None:
             workspace = torch.empty(need, dtype=torch.uint8, device=Y.device)
@@ -364,14 +453,14 @@ class Code:
         return D, kept, status
 
     def decode(self, nodes, Y, X, block_bytes, stream=None):
-        yp, yld = _regions(Y, len(nodes) * self.alpha)
-        xp, xld = _regions(X, self.B)
+        yp, yld = _regions(Y, len(nodes) * self.alpha, block_bytes)
+        xp, xld = _regions(X, self.B, block_bytes)
         _check(pm_decode(self.h, nodes, yp, yld, xp, xld, block_bytes, _stream_handle(stream)), "pm_decode")
 
 
 def apply(A, inp, out, block_bytes, stream=None):
-    ip, ild = _regions(inp, A.shape[1])
-    op, old = _regions(out, A.shape[0])
+    ip, ild = _regions(inp, A.shape[1], block_bytes)
+    op, old = _regions(out, A.shape[0], block_bytes)
     _check(pm_apply(A, ip, ild, op, old, block_bytes, _stream_handle(stream)), "pm_apply")
 
 
@@ -401,9 +490,14 @@ class Batch:
                 keep.append(a)
                 e.ids = ctypes.cast(a, ctypes.POINTER(ctypes.c_uint32))
             inp, out = it["inp"], it["out"]
-            e.in_, e.in_ld = inp.data_ptr(), inp.stride(0)
-            e.out, e.out_ld = out.data_ptr(), (out.stride(0) if out.dim() == 2 else 16)
-            e.block_bytes = int(it["block_bytes"])
+            bb = int(it["block_bytes"])
+            in_n, out_n = code.op_rows(e.op, ids)
+            e.in_, e.in_ld = _regions(inp, in_n, bb)
+            if out.dim() == 2:
+                e.out, e.out_ld = _regions(out, out_n, bb)
+            else:
+                e.out, e.out_ld = _block(out, bb), 16
+            e.block_bytes = bb
         h = ctypes.c_void_p()
         flags = (PM_BATCH_GRAPH if graph else 0) | (PM_BATCH_SPECIALIZE if specialize else 0)
         _check(_lib().pm_batch_plan(arr, len(items), flags, ctypes.byref(h)), "pm_batch_plan")
@@ -453,13 +547,15 @@ class pm_completion(ctypes.Structure):
 class pm_server_cfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("streams", ctypes.c_uint32),
                 ("max_batch", ctypes.c_uint32), ("queue_cap", ctypes.c_uint32),
-                ("dwords_per_lane", ctypes.c_uint32)]
+                ("dwords_per_lane", ctypes.c_uint32), ("table_reserve_bytes", ctypes.c_uint64)]
 
 
 class pm_server_stat(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_uint64), ("batches", ctypes.c_uint64), ("pending", ctypes.c_uint64),
                 ("arena_used", ctypes.c_uint64), ("arena_high_water", ctypes.c_uint64),
-                ("max_concurrent_batches", ctypes.c_uint32)]
+                ("max_concurrent_batches", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("failed", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
+                ("table_reserve_bytes", ctypes.c_uint64), ("table_bytes_high", ctypes.c_uint64)]
 
 
 _server_sigs_done = False
@@ -490,9 +586,10 @@ def _server_sigs():
 class Server:
     """Continuous-batching server over the engine (see pm_server_* in pm.h)."""
 
-    def __init__(self, hbm_budget_bytes, streams=4, max_batch=64, queue_cap=4096, dwords_per_lane=2):
+    def __init__(self, hbm_budget_bytes, streams=4, max_batch=64, queue_cap=4096, dwords_per_lane=2,
+                 table_reserve_bytes=0):
         L = _server_sigs()
-        cfg = pm_server_cfg(hbm_budget_bytes, streams, max_batch, queue_cap, dwords_per_lane)
+        cfg = pm_server_cfg(hbm_budget_bytes, streams, max_batch, queue_cap, dwords_per_lane, table_reserve_bytes)
         h = ctypes.c_void_p()
         _check(L.pm_server_create(ctypes.byref(cfg), ctypes.byref(h)), "pm_server_create")
         self.h = h.value
@@ -516,20 +613,35 @@ class Server:
         self._keep[t.value] = keep
         return t.value
 
+    @staticmethod
+    def _helper_regions(code, helper_nodes, block_bytes):
+        """Pointers and the shared row stride of the helpers' node blocks."""
+        rows = code.op_rows(OP_HELPER)[0]
+        lds = set()
+        for t in helper_nodes:
+            lds.add(_regions(t, rows, block_bytes)[1])
+        if len(lds) != 1:
+            raise ValueError("helper node tensors must share one row stride")
+        return [t.data_ptr() for t in helper_nodes], lds.pop()
+
     def submit_encode(self, code, X, block_bytes, tag=0):
-        r = pm_request(PM_REQ_ENCODE, code.h, 0, None, X.data_ptr(), X.stride(0), None, 0, block_bytes, tag)
+        xp, xld = _regions(X, code.B, block_bytes)
+        r = pm_request(PM_REQ_ENCODE, code.h, 0, None, xp, xld, None, 0, block_bytes, tag)
         return self._submit(r, (code, X))
 
     def submit_decode(self, code, nodes, Y, block_bytes, tag=0):
+        yp, yld = _regions(Y, code.op_rows(OP_DECODE, nodes)[0], block_bytes)
         ids = _u32arr(nodes)
         r = pm_request(PM_REQ_DECODE, code.h, 0, ctypes.cast(ids, ctypes.POINTER(ctypes.c_uint32)),
-                       Y.data_ptr(), Y.stride(0), None, 0, block_bytes, tag)
+                       yp, yld, None, 0, block_bytes, tag)
         return self._submit(r, (code, Y))
 
     def submit_repair(self, code, failed, helpers, helper_nodes, block_bytes, tag=0):
+        if len(helper_nodes) != len(helpers):
+            raise ValueError("one node tensor per helper")
         ids = _u32arr(helpers)
-        ptrs = (ctypes.c_void_p * len(helper_nodes))(*[t.data_ptr() for t in helper_nodes])
-        ld = helper_nodes[0].stride(0)
+        node_ptrs, ld = self._helper_regions(code, helper_nodes, block_bytes)
+        ptrs = (ctypes.c_void_p * len(helper_nodes))(*node_ptrs)
         r = pm_request(PM_REQ_REPAIR, code.h, failed, ctypes.cast(ids, ctypes.POINTER(ctypes.c_uint32)),
                        None, 0, ctypes.cast(ptrs, ctypes.POINTER(ctypes.c_void_p)), ld, block_bytes, tag)
         return self._submit(r, (code, helper_nodes))
@@ -560,22 +672,27 @@ class Server:
         keep_alive = []
         for i, q in enumerate(requests):
             r = arr[i]
-            r.code, r.block_bytes, r.tag = q["code"].h, q["block_bytes"], i
+            code, bb = q["code"], q["block_bytes"]
+            r.code, r.block_bytes, r.tag = code.h, bb, i
             if q["op"] == "encode":
-                r.op, r.in_, r.in_ld = PM_REQ_ENCODE, q["X"].data_ptr(), q["X"].stride(0)
+                r.op = PM_REQ_ENCODE
+                r.in_, r.in_ld = _regions(q["X"], code.B, bb)
             elif q["op"] == "decode":
                 ids = _u32arr(q["nodes"])
                 keep_alive.append(ids)
                 r.op, r.ids = PM_REQ_DECODE, ctypes.cast(ids, ctypes.POINTER(ctypes.c_uint32))
-                r.in_, r.in_ld = q["Y"].data_ptr(), q["Y"].stride(0)
+                r.in_, r.in_ld = _regions(q["Y"], code.op_rows(OP_DECODE, q["nodes"])[0], bb)
             else:
+                if len(q["helper_nodes"]) != len(q["helpers"]):
+                    raise ValueError("one node tensor per helper")
                 ids = _u32arr(q["helpers"])
-                ptrs = (ctypes.c_void_p * len(q["helper_nodes"]))(*[t.data_ptr() for t in q["helper_nodes"]])
+                node_ptrs, ld = self._helper_regions(code, q["helper_nodes"], bb)
+                ptrs = (ctypes.c_void_p * len(node_ptrs))(*node_ptrs)
                 keep_alive += [ids, ptrs]
                 r.op, r.failed = PM_REQ_REPAIR, q["failed"]
                 r.ids = ctypes.cast(ids, ctypes.POINTER(ctypes.c_uint32))
                 r.helper_nodes = ctypes.cast(ptrs, ctypes.POINTER(ctypes.c_void_p))
-                r.node_ld = q["helper_nodes"][0].stride(0)
+                r.node_ld = ld
         arrivals = (ctypes.c_uint64 * max(1, n))(*[int(t) for t in arrival_ns])
         outs = (pm_completion * max(1, n))()
         _check(_lib().pm_server_replay(self.h, arr, arrivals, n, 1 if keep else 0, outs), "pm_server_replay")
@@ -591,7 +708,9 @@ class Server:
         s = pm_server_stat()
         _check(_lib().pm_server_stats(self.h, ctypes.byref(s)), "pm_server_stats")
         return dict(completed=s.completed, batches=s.batches, pending=s.pending, arena_used=s.arena_used,
-                    arena_high_water=s.arena_high_water, max_concurrent_batches=s.max_concurrent_batches)
+                    arena_high_water=s.arena_high_water, max_concurrent_batches=s.max_concurrent_batches,
+                    failed=s.failed, arena_bytes=s.arena_bytes, table_reserve_bytes=s.table_reserve_bytes,
+                    table_bytes_high=s.table_bytes_high)
 
 
 _hip = None

@@ -18,7 +18,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(E.CLANG), reason="clang++ of 
 SIZES = [2048, 3000, 2049, 5000, 4096 + 17, 2063]
 CASES = [
     # name, code, oracle code, failed node, helpers, decode nodes, slot counts
-    ("msr4", dict(k=4, d=6, n=8), (O.MSR, 4, 6, 8, O.SPARSE), 5, [0, 1, 2, 3, 4, 6], [1, 4, 6, 7], (7, 3)),
+    ("msr4", dict(k=4, d=6, n=8), (O.MSR, 4, 6, 8, O.SPARSE), 5, [0, 1, 2, 3, 4, 6], [1, 4, 6, 7], (7, 3, 40)),
     ("mbr4", dict(k=4, d=5, n=7, kind=pm.PM_MBR), (O.MBR, 4, 5, 7, O.SPARSE), 2, [0, 1, 3, 4, 6], [0, 3, 5, 6],
      (9, 2)),
 ]

@@ -266,8 +266,9 @@ def test_config4_full_size_in_the_bench_launch_configuration():
     """Configuration 4 as bench.py times it: 4096 objects (log-uniform 64 KiB -
     16 MiB, sparse MSR (4,6), (8,14), (16,30), n = 2k, 12.3 GB of source),
     the encode kernels prepared in both forms, one graph-captured batch with
-    autotuned tile width; sampled outputs of a seeded sample of objects
-    against the oracle, and a second replay gives the same bytes."""
+    autotuned tile width; every object equals its plain single call byte for
+    byte, 256 seeded objects' whole 2 KiB tiles and tails equal the oracle,
+    and a second replay gives the same bytes."""
     from paper_1412_3022_amd import workloads
     print("config4 full size", flush=True)
     objs, codes, inbuf, outbuf = workloads.batched_objects(4096, 64 << 10, 16 << 20, synth.CONFIG_SEED + 3, device())
@@ -284,15 +285,27 @@ def test_config4_full_size_in_the_bench_launch_configuration():
     batch.run()
     torch.cuda.synchronize()
     st = synth.Stream(0xC0F4)
-    sample = sorted(set(st.below(len(objs)) for _ in range(48)))
+    # every object, every byte, against its own plain single call
+    for i, o in enumerate(objs):
+        s, c = o["s"], o["code"]
+        single = torch.empty((c.enc_rows, s), dtype=torch.uint8, device=device())
+        c.encode(o["X"], single, s)
+        assert torch.equal(o["P"][:, :s], single), (i, c.k, s)
+    # 256 objects against the oracle: whole 2 KiB tiles (first, a seeded
+    # middle one, the last window) and the tail, plus scattered bytes
+    sample = sorted(set(st.below(len(objs)) for _ in range(256)))
     snap = {}
     for i in sample:
         o = objs[i]
         s, c = o["s"], o["code"]
-        pos = np.unique(np.array([0, s - 1] + [st.below(s) for _ in range(96)]))
+        s16 = s // 16 * 16
+        mid = st.below(max(1, s16 // 2048)) * 2048
+        pos = set(range(0, 2048)) | set(range(mid, mid + 2048)) | set(range(s16 - 2048, s))
+        pos |= {st.below(s) for _ in range(96)}
+        pos = np.array(sorted(p for p in pos if p < s))
         X = o["X"][:, pos].cpu().numpy()
         got = o["P"][:, pos].cpu().numpy()
-        assert np.array_equal(got, O.apply(oracles[c.k].enc, X)), (i, c.k, s)
+        assert np.array_equal(got, O.apply(oracles[c.k].enc, X, nthreads=16)), (i, c.k, s)
         snap[i] = (pos, got)
     outbuf.fill_(0x33)
     batch.run()

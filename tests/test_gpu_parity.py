@@ -129,10 +129,21 @@ def test_small_code_roundtrips_on_gpu(kw, s):
 
 # ------------------------------------------------------- configurations ---
 def _sample_positions(s, seed, count=2048):
+    """Scattered positions plus whole 2 KiB wave tiles of the bit-sliced
+    kernel: the first, a seeded one in the middle and the last full-width
+    window [s16 - 2048, s16) (s16 = s rounded down to 16), so that one wrong
+    tile anywhere in those cannot pass; and the last 64 bytes (the byte
+    tail)."""
     st = synth.Stream(seed)
     pos = {0, 1, 2, s - 1, s - 2}
     pos |= set(range(max(0, s - 64), s))
-    while len(pos) < count:
+    tile = 2048
+    s16 = s // 16 * 16
+    if s16 >= tile:
+        mid = st.below(s16 // tile) * tile
+        for t0 in (0, mid, s16 - tile):
+            pos |= set(range(t0, t0 + tile))
+    while len(pos) < count + 3 * tile:
         pos.add(st.below(s))
     return np.array(sorted(pos))
 

@@ -39,9 +39,21 @@ def _alone(q):
     return out
 
 
+def _oracle_of(c):
+    import oracle as O
+    if c.kind == pm.PM_MBR:
+        return O.Code(O.MBR, c.k, c.d, c.n)
+    return O.Code(O.MSR, c.k, c.d, c.n, O.SPARSE)
+
+
 def test_served_mix_equals_alone_and_overlaps():
+    """Each served result equals the same request run alone; encodes also
+    equal the oracle's encoding in full, repairs the lost node and decodes
+    the object."""
+    import oracle as O
     print("server mix", flush=True)
     wl = workloads.ServeWorkload(21, device(), 1 << 10, 256 << 10, resident_per_family=2)
+    oracles = {c.h: _oracle_of(c) for c in wl.codes.values()}
     reqs, arrivals, nbytes = wl.requests(300, rate_per_s=2e5)
     budget = 32 << 20
     srv = pm.Server(budget, streams=3, max_batch=8)
@@ -58,6 +70,9 @@ def test_served_mix_equals_alone_and_overlaps():
                 assert torch.equal(got, q["obj"]["nodes"][q["failed"]])
             elif q["op"] == "decode":
                 assert torch.equal(got, q["obj"]["X"])
+            else:
+                X = q["X"][:, :s].cpu().numpy()
+                assert np.array_equal(got.cpu().numpy(), O.apply(oracles[q["code"].h].enc, X, nthreads=8)), s
             srv.release(c["ticket"])
         st = srv.stats()
         assert st["completed"] == len(reqs)
@@ -78,14 +93,19 @@ def test_budget_backpressure_completes_everything():
     need = max(q["code"].enc_rows if q["op"] == "encode" else
                (q["code"].B if q["op"] == "decode" else q["code"].alpha + q["code"].d)
                for q in reqs) * max(q["block_bytes"] for q in reqs)
-    budget = need + (1 << 16)          # about one request at a time
-    srv = pm.Server(budget, streams=4, max_batch=4)
+    budget = need + (1 << 16)          # arena for about one request at a time
+    reserve = 32 << 20                 # plus the kernel tables' part of the budget
+    srv = pm.Server(budget + reserve, streams=4, max_batch=4, table_reserve_bytes=reserve)
     try:
         comps = srv.replay(reqs, arrivals, keep=False)
         st = srv.stats()
         assert st["completed"] == len(reqs)
         assert all(c["status"] == pm.PM_OK for c in comps)
         assert st["arena_high_water"] <= budget
+        assert st["arena_bytes"] + st["table_reserve_bytes"] <= budget + reserve
+        assert st["table_bytes_high"] <= reserve
+        assert st["arena_bytes"] + st["table_reserve_bytes"] <= budget + reserve
+        assert st["table_bytes_high"] <= reserve
     finally:
         srv.close()
 
@@ -96,7 +116,9 @@ def test_queue_full_and_oversized_requests():
     c = pm.Code(k=4, d=6, n=8)
     s = 64 << 10
     X = torch.zeros((c.B, s), dtype=torch.uint8, device=dev)
-    srv = pm.Server(c.enc_rows * s + 4096, streams=2, max_batch=2, queue_cap=2)
+    reserve = 16 << 20
+    srv = pm.Server(c.enc_rows * s + 4096 + reserve, streams=2, max_batch=2, queue_cap=2,
+                    table_reserve_bytes=reserve)
     try:
         t0 = srv.submit_encode(c, X, s)
         done = []
@@ -165,7 +187,7 @@ def test_config5_full_size_in_the_bench_configuration():
     server of 8 streams x 128 requests; 1500 requests replayed as fast as
     they can be submitted.  Every repair equals the lost node's blocks and
     every decode the object (whole blocks); encodes are checked against the
-    oracle at sampled byte positions."""
+    oracle on their first 2 KiB tile, their tail and scattered bytes."""
     import oracle as O
     from concurrent.futures import ThreadPoolExecutor
     print("config5 full size", flush=True)
@@ -198,9 +220,100 @@ def test_config5_full_size_in_the_bench_configuration():
             elif q["op"] == "decode":
                 assert torch.equal(got, q["obj"]["X"]), s
             else:
-                pos = np.unique(np.array([0, s - 1] + [st.below(s) for _ in range(32)]))
+                # the first 2 KiB wave tile whole, the tail, and scattered bytes
+                pos = set(range(min(s, 2048))) | set(range(max(0, s - 64), s))
+                pos = np.array(sorted(pos | {st.below(s) for _ in range(32)}))
                 X = q["X"][:, pos].cpu().numpy()
-                assert np.array_equal(got[:, pos].cpu().numpy(), O.apply(oracles[q["code"].h].enc, X)), s
+                assert np.array_equal(got[:, pos].cpu().numpy(),
+                                      O.apply(oracles[q["code"].h].enc, X, nthreads=16)), s
             srv.release(c["ticket"])
+    finally:
+        srv.close()
+
+
+def test_failed_table_upload_fails_its_requests_only():
+    """A kernel-table upload that fails (forced from the host) completes the
+    requests of that micro-batch with PM_ENOMEM instead of reporting success
+    for work that never ran; the server keeps serving, and the same request
+    submitted again succeeds."""
+    print("server upload failure", flush=True)
+    dev = device()
+    c = pm.Code(k=4, d=6, n=8)
+    s = 4096
+    X = torch.from_numpy(synth.random_bytes(synth.CONFIG_SEED + 51, c.B * s).reshape(c.B, s)).to(dev)
+    P = torch.empty((c.enc_rows, s), dtype=torch.uint8, device=dev)
+    c.encode(X, P, s)
+    torch.cuda.synchronize()
+    nmap = torch.from_numpy(c.node_map().astype(np.int64)).to(dev)
+    full = torch.cat([X, P])
+    K = [1, 4, 6, 7]                         # a node set no call has decoded yet
+    Y = torch.cat([full[nmap[i * c.alpha:(i + 1) * c.alpha]] for i in K]).contiguous()
+    srv = pm.Server(256 << 20, streams=2, max_batch=1, table_reserve_bytes=64 << 20)
+    try:
+        pm.debug_fail_uploads(1)
+        t0 = srv.submit_decode(c, K, Y, s)
+        got = []
+        deadline = time.time() + 30
+        while not got and time.time() < deadline:
+            got = srv.poll()
+        assert got and got[0]["ticket"] == t0
+        assert got[0]["status"] == pm.PM_ENOMEM
+        srv.release(t0)
+        t1 = srv.submit_decode(c, K, Y, s)
+        got = []
+        deadline = time.time() + 30
+        while not got and time.time() < deadline:
+            got = srv.poll()
+        assert got and got[0]["ticket"] == t1 and got[0]["status"] == pm.PM_OK
+        out = _result(got[0], c.B, s)
+        assert torch.equal(out, X)
+        st = srv.stats()
+        assert st["failed"] == 1 and st["completed"] == 2
+    finally:
+        pm.debug_fail_uploads(0)
+        srv.close()
+
+
+def test_table_reserve_bounds_kernel_tables():
+    """Decodes of many node sets of the (16,30,32) code each need their own
+    dense 240 x 240 decode tables (over the bit-sliced size limit, so on the
+    table kernels); with a reserve smaller than all of them, the server
+    evicts least recently used patterns so the tables never exceed the
+    reserve, and every decode still returns the object."""
+    print("server table reserve", flush=True)
+    dev = device()
+    c = pm.Code(k=16, d=30, n=32)
+    c.set_cache_limit(1024)
+    s = 2048
+    X = torch.from_numpy(synth.random_bytes(synth.CONFIG_SEED + 52, c.B * s).reshape(c.B, s)).to(dev)
+    P = torch.empty((c.enc_rows, s), dtype=torch.uint8, device=dev)
+    c.encode(X, P, s)
+    torch.cuda.synchronize()
+    nmap = torch.from_numpy(c.node_map().astype(np.int64)).to(dev)
+    full = torch.cat([X, P])
+    rng = synth.Stream(0x7AB1E)
+    sets = [sorted(rng.subset(c.n, c.k)) for _ in range(40)]
+    Ys = [torch.cat([full[nmap[i * c.alpha:(i + 1) * c.alpha]] for i in K]).contiguous() for K in sets]
+    pm.cache_release()
+    base = pm.table_bytes()
+    reserve = base + (12 << 20)             # room for about ten decode tables
+    srv = pm.Server((256 << 20) + reserve, streams=2, max_batch=4, table_reserve_bytes=reserve)
+    try:
+        tickets = [srv.submit_decode(c, K, Y, s) for K, Y in zip(sets, Ys)]
+        assert all(t is not None for t in tickets)
+        done = {}
+        deadline = time.time() + 120
+        while len(done) < len(tickets) and time.time() < deadline:
+            for r in srv.poll():
+                done[r["ticket"]] = r
+        assert len(done) == len(tickets)
+        for t in tickets:
+            r = done[t]
+            assert r["status"] == pm.PM_OK
+            assert torch.equal(_result(r, c.B, s), X)
+            srv.release(t)
+        st = srv.stats()
+        assert st["table_bytes_high"] <= reserve, (st, reserve)
+        assert st["arena_bytes"] + st["table_reserve_bytes"] <= (256 << 20) + reserve
     finally:
         srv.close()

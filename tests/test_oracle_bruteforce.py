@@ -70,6 +70,40 @@ def test_lambda_distinct_for_config_codes():
         assert len(set(c.lam.tolist())) == c.n
 
 
+def test_adjusted_last_lambda_values():
+    """Regression pin of the project's reading for n = 2k (the adjusted last
+    node): the last Lambda is g^t for the smallest t that keeps Lambda
+    distinct and every d-subset of Psi containing the last node invertible.
+    That gives 0x01 (t = 0) for k = 3, 4, 8 and 0x02 (t = 1) for k = 16;
+    the first 2k - 1 values are the printed construction's."""
+    for k, want in ((3, 0x01), (4, 0x01), (8, 0x01), (16, 0x02)):
+        psi, lam = O.msr_sparse(k, 2 * k)
+        _, lam_p = O.msr_sparse_printed(k, 2 * k)
+        assert int(lam[-1]) == want, (k, hex(int(lam[-1])))
+        assert np.array_equal(lam[:-1], lam_p[:-1]), k
+        t = 0
+        while O.gpow(t) != want:
+            t += 1
+        # every smaller exponent collides with a printed Lambda or leaves a
+        # singular helper set
+        for u in range(t):
+            cand = O.gpow(u)
+            assert cand in set(int(v) for v in lam[:-1]) or not _last_lambda_valid(k, psi, cand), (k, u)
+
+
+def _last_lambda_valid(k, psi, lam_last):
+    """Whether Psi with its last row rebuilt for Lambda = lam_last keeps every
+    d-subset that holds the last node invertible."""
+    alpha, n, d = k - 1, 2 * k, 2 * k - 2
+    p = psi.copy()
+    phi = p[-1, :alpha]
+    p[-1, alpha:] = np.array([O.mul(lam_last, int(v)) for v in phi], np.uint8)
+    for H in combinations(range(n - 1), d - 1):
+        if O.invert(p[list(H) + [n - 1]]) is None:
+            return False
+    return True
+
+
 def test_printed_sparse_at_n_equal_2k_has_singular_helper_sets():
     """Reading for n = 2k (the paper checks only n = d + 1): the printed
     construction has helper sets whose Psi_H is singular; the adjusted last

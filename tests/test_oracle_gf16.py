@@ -1,5 +1,5 @@
-"""Pins of the GF(2^16) oracle (Section 3.3: the sparse PM-MSR construction
-is valid for k up to 64 in GF(2^16)).
+"""Pins of the GF(2^16) oracle (Section 3.3, validity range of the sparse
+PM-MSR construction over GF(2^16): k up to 64).
 
 What pins it, other than itself:
 * the field against carry-less multiplication with reduction written here

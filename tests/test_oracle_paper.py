@@ -39,8 +39,8 @@ def test_table1_sparsity():
 
 
 def test_sparse_validity_range():
-    """Section 3.3: the sparse construction is valid for k in {2..39} in
-    GF(2^8) (n = d + 1); k = 40 is outside the stated range and fails."""
+    """Section 3.3, validity range of the sparse construction over GF(2^8):
+    k = 2..39 pass at n = d + 1, and k = 40, past that range, fails."""
     g = _load("validity_range.json")
     for k in range(g["first_valid_k"], g["last_valid_k"] + 2):
         psi, lam = O.msr_sparse_printed(k, 2 * k - 1)
