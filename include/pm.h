@@ -48,7 +48,10 @@ typedef enum {
     PM_ENOMEM = -4,        /* host or device allocation failed */
     PM_EHIP = -5,          /* a HIP runtime call failed */
     PM_EBUSY = -6,         /* a queue is full; retry later */
-    PM_ENOTREADY = -7      /* the operation has not been prepared on this device */
+    PM_ENOTREADY = -7,     /* the operation has not been prepared on this device
+                              (entry points that allocate nothing) */
+    PM_ELIMIT = -8         /* beyond a fixed size limit (the static scratch of
+                              pm_decode_specific_noalloc) */
 } pm_status;
 
 typedef enum {
@@ -208,6 +211,24 @@ pm_status pm_decode_specific_workspace(const pm_code *code, size_t block_bytes, 
 pm_status pm_decode_specific(const pm_code *code, const uint32_t *nodes, const uint8_t *Y, size_t y_ld,
                              uint8_t *X, size_t x_ld, size_t block_bytes, uint8_t *workspace,
                              size_t workspace_bytes, pm_stream stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * specific decode as pm_decode_specific, same arguments minus the workspace,
+ * with the intermediates in a fixed scratch array that the library's code
+ * object holds on every device it is loaded on (128 MiB per device, kept
+ * until the process ends).  It calls no hipMalloc, hipFree, hipRTC or module
+ * load: the node list must have been prepared on the current device first
+ * with pm_prepare(code, 4, 0, nodes, 0, ...), which also looks up the
+ * scratch's device address there; otherwise PM_ENOTREADY.  PM_ELIMIT when
+ * the workspace that pm_decode_specific_workspace reports for block_bytes
+ * exceeds 128 MiB.  GF(2^8) codes only (PM_EUNSUPPORTED for w = 16 and RS).
+ * Every call on a device shares that device's scratch and it keeps the last
+ * call's contents (each pass overwrites what it reads later, so nothing
+ * needs clearing): calls that overlap in time on one device -- on different
+ * streams, or from different threads -- race and must be serialized by the
+ * caller (one stream, or events). */
+pm_status pm_decode_specific_noalloc(const pm_code *code, const uint32_t *nodes, const uint8_t *Y, size_t y_ld,
+                                     uint8_t *X, size_t x_ld, size_t block_bytes, pm_stream stream);
 /* The factor of pass `which` (0..4 above; factor 4 has 0 rows for
  * non-systematic PM-MSR codes, factors 2..4 for PM-MBR) for nodes, host
  * row-major, cap bytes at dst (dst may be NULL to query rows and cols).

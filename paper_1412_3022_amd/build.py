@@ -24,7 +24,7 @@ HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
 HOST_SOURCES = ["gf256.cpp", "construct.cpp", "program.cpp", "capi.cpp", "batch.cpp", "server.cpp", "bitslice.cpp",
                 "gf16.cpp"]
-HIP_SOURCES = ["kernels.hip", "gj.hip", "gf16.hip"]
+HIP_SOURCES = ["kernels.hip", "gj.hip", "gf16.hip", "noalloc.hip"]
 
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__",
               "-I" + os.path.join(ROCM, "include"), "-I" + INCLUDE, "-pthread"]

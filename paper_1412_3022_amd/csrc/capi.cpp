@@ -18,6 +18,7 @@
 #include "engine.hpp"
 #include "gf16.hpp"
 #include "gj.hpp"
+#include "noalloc.hpp"
 #include "put.hpp"
 #include "pm.h"
 #include "program.hpp"
@@ -780,6 +781,7 @@ const char *pm_status_string(pm_status st) {
         case PM_EHIP: return "HIP runtime error";
         case PM_EBUSY: return "busy";
         case PM_ENOTREADY: return "not prepared on this device (call pm_prepare first)";
+        case PM_ELIMIT: return "exceeds the fixed scratch of the no-allocation entry point";
     }
     return "unknown status";
 }
@@ -1013,6 +1015,24 @@ pm_status pm_decode_specific(const pm_code *cc, const uint32_t *nodes, const uin
     return run_specific(c, ops, pe16, Y, y_ld, X, x_ld, s, workspace, reinterpret_cast<hipStream_t>(stream), false);
 }
 
+pm_status pm_decode_specific_noalloc(const pm_code *cc, const uint32_t *nodes, const uint8_t *Y, size_t y_ld,
+                                     uint8_t *X, size_t x_ld, size_t s, pm_stream stream) {
+    if (s == 0 || !cc) return PM_EINVAL;
+    pm_code *c = const_cast<pm_code *>(cc);
+    if (c->w16) return PM_EUNSUPPORTED;
+    if (c->m.kind != KIND_MSR && c->m.kind != KIND_MBR) return PM_EUNSUPPORTED;
+    const size_t ld = (s + 15) / 16 * 16;
+    if (specific_ws_blocks(c->m) * ld > kNoAllocScratchBytes) return PM_ELIMIT;
+    SpecificOps ops;
+    int st = resolve_specific(c, nodes, &ops, true);
+    if (st != ST_OK) return static_cast<pm_status>(st);
+    void *scratch = nullptr;
+    hipError_t e = pmk_noalloc_scratch(&scratch);
+    if (e != hipSuccess) return static_cast<pm_status>(hip_fail(e));
+    return run_specific(c, ops, nullptr, Y, y_ld, X, x_ld, s, static_cast<uint8_t *>(scratch),
+                        reinterpret_cast<hipStream_t>(stream), true);
+}
+
 pm_status pm_decode_specific_factor(const pm_code *cc, const uint32_t *nodes, int which, uint8_t *dst, size_t cap,
                                     uint32_t *rows, uint32_t *cols) {
     if (which < 0 || which >= kSpecificPasses || !cc) return PM_EINVAL;
@@ -1209,6 +1229,16 @@ pm_status pm_prepare(pm_code *c, int op, uint32_t failed, const uint32_t *ids, u
             if (!bp) all = 0;
             else if ((st = bs_compile(*bp, kind)) != ST_OK) return static_cast<pm_status>(st);
             if ((st = stage_on_device(*ops.pe[p], bp.get(), kind)) != ST_OK) return static_cast<pm_status>(st);
+        }
+        // set-up of pm_decode_specific_noalloc: its scratch address on this
+        // device (the first lookup may load the library's code object)
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) {
+            void *scratch = nullptr;
+            hipError_t e = pmk_noalloc_scratch(&scratch);
+            if (e != hipSuccess) return static_cast<pm_status>(hip_fail(e));
+        } else {
+            (void)hipGetLastError();
         }
         if (specialized) *specialized = all;
         return PM_OK;

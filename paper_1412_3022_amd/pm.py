@@ -18,7 +18,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "_lib", "libpmrc.so")
 
 PM_OK, PM_EINVAL, PM_EUNSUPPORTED, PM_ESINGULAR, PM_ENOMEM, PM_EHIP, PM_EBUSY = 0, -1, -2, -3, -4, -5, -6
-PM_ENOTREADY = -7
+PM_ENOTREADY, PM_ELIMIT = -7, -8
 PM_MSR, PM_MBR, PM_RS = 0, 1, 2
 PM_VANILLA, PM_SPARSE = 0, 1
 MAT_PSI, MAT_LAMBDA, MAT_G, MAT_GSYS, MAT_ENC = 0, 1, 2, 3, 4
@@ -79,6 +79,7 @@ def _lib():
         L.pm_prepare.argtypes = [vp, i32, u32, u32p, u32, ctypes.POINTER(ctypes.c_int)]
         L.pm_decode_specific_workspace.argtypes = [vp, sz, ctypes.POINTER(ctypes.c_size_t)]
         L.pm_decode_specific.argtypes = [vp, u32p, vp, sz, vp, sz, sz, vp, sz, vp]
+        L.pm_decode_specific_noalloc.argtypes = [vp, u32p, vp, sz, vp, sz, sz, vp]
         L.pm_repair_workspace.argtypes = [vp, sz, ctypes.POINTER(ctypes.c_size_t)]
         L.pm_repair.argtypes = [vp, u32, u32p, ctypes.POINTER(vp), sz, vp, sz, vp, sz, sz, vp]
         L.pm_code_set_cache_limit.argtypes = [vp, u32]
@@ -217,6 +218,11 @@ def table_bytes():
 
 def debug_fail_uploads(count):
     _check(_lib().pm_debug_fail_uploads(count), "pm_debug_fail_uploads")
+
+
+def pm_decode_specific_noalloc(h, nodes, y_ptr, y_ld, x_ptr, x_ld, block_bytes, stream=0):
+    return _lib().pm_decode_specific_noalloc(h, _u32arr(nodes), y_ptr, y_ld, x_ptr, x_ld, block_bytes,
+                                             stream or None)
 
 
 def pm_decode_matrices(h, sets_ptr, count, d_ptr, d_stride, kept_ptr, status_ptr, stream=0):
@@ -424,6 +430,15 @@ class Code:
         _check(pm_decode_specific(self.h, nodes, yp, yld, xp, xld, block_bytes, workspace.data_ptr(),
                                   workspace.numel(), _stream_handle(stream)), "pm_decode_specific")
         return workspace
+
+    def decode_specific_noalloc(self, nodes, Y, X, block_bytes, stream=None):
+        """Specific decode with the library's fixed device scratch (no
+        allocation; the node list must have been prepared with
+        prepare(OP_DECODE_SPECIFIC, ids=nodes) on this device)."""
+        yp, yld = _regions(Y, self.k * self.alpha, block_bytes)
+        xp, xld = _regions(X, self.B, block_bytes)
+        _check(pm_decode_specific_noalloc(self.h, nodes, yp, yld, xp, xld, block_bytes, _stream_handle(stream)),
+               "pm_decode_specific_noalloc")
 
     def decode_matrix(self, nodes):
         """The host-built decode matrix of pm_decode for nodes and the received
