@@ -526,6 +526,10 @@ pm_status pm_server_release(pm_server *s, uint64_t ticket) {
 pm_status pm_server_stats(pm_server *s, pm_server_stat *st) {
     if (!s || !st) return PM_EINVAL;
     std::lock_guard<std::mutex> lk(s->mu);
+    // releases not yet taken by the scheduler count as done (the arena is
+    // only touched under this lock)
+    for (auto &rel : s->releases) s->arena.release(rel.first, rel.second);
+    s->releases.clear();
     st->completed = s->completed;
     st->batches = s->batches;
     st->pending = s->pending.size();

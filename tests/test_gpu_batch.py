@@ -299,10 +299,13 @@ def test_config4_full_size_in_the_bench_launch_configuration():
         o = objs[i]
         s, c = o["s"], o["code"]
         s16 = s // 16 * 16
-        mid = st.below(max(1, s16 // 2048)) * 2048
-        pos = set(range(0, 2048)) | set(range(mid, mid + 2048)) | set(range(s16 - 2048, s))
+        pos = set(range(0, min(s, 2048))) | set(range(max(0, s - 64), s))
+        if s16 >= 2048:
+            mid = st.below(s16 // 2048) * 2048
+            pos |= set(range(mid, mid + 2048)) | set(range(s16 - 2048, s16))
         pos |= {st.below(s) for _ in range(96)}
-        pos = np.array(sorted(p for p in pos if p < s))
+        pos = np.array(sorted(pos))
+        assert pos.min() >= 0 and pos.max() < s
         X = o["X"][:, pos].cpu().numpy()
         got = o["P"][:, pos].cpu().numpy()
         assert np.array_equal(got, O.apply(oracles[c.k].enc, X, nthreads=16)), (i, c.k, s)

@@ -143,7 +143,7 @@ def _sample_positions(s, seed, count=2048):
         mid = st.below(s16 // tile) * tile
         for t0 in (0, mid, s16 - tile):
             pos |= set(range(t0, t0 + tile))
-    while len(pos) < count + 3 * tile:
+    while len(pos) < min(s, count + 3 * tile):
         pos.add(st.below(s))
     return np.array(sorted(pos))
 
