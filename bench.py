@@ -54,9 +54,10 @@ def parse():
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--init-only", action="store_true",
                     help="only run the GPU-side init measurement (batched decode matrices)")
-    ap.add_argument("--part", choices=("batched", "served", "dense", "gf16"),
-                    help="only run configuration 4 (batched), 5 (served), the other configuration-2 "
-                         "encodes (dense) or the GF(2^16) codes (gf16) and print their fields")
+    ap.add_argument("--part", choices=("batched", "served", "served-only", "dense", "gf16", "repair-decode"),
+                    help="only run configuration 4 (batched), 5 (served, or served-only without the "
+                         "sequential baseline), the other configuration-2 encodes (dense), the GF(2^16) "
+                         "codes (gf16) or the repairs and decodes (repair-decode) and print their fields")
     return ap.parse_args()
 
 
@@ -560,7 +561,7 @@ def batched_case(torch, pm, synth, steps):
     return res
 
 
-def served_case(torch, pm, synth, nreq=20000, rho=0.8):
+def served_case(torch, pm, synth, nreq=20000, rho=0.8, sequential=True):
     """Configuration 5: a Poisson stream of 20 000 requests (70% encode, 20%
     single-node repair, 10% k-subset decode; sizes log-uniform 4 KiB - 64 MiB;
     PM-MSR (4,6), (8,14), (16,30) and PM-MBR (8,14,16)) served under a 64 GB
@@ -618,6 +619,17 @@ def served_case(torch, pm, synth, nreq=20000, rho=0.8):
     srv.close()
     lat = np.array([(c["t_done"] - c["t_submit"]) / 1e3 for c in comps])
     served = span(comps, nbytes)
+    res = {"requests": nreq, "capacity_gbps": round(capacity, 2), "offered_rho": rho,
+           "offered_rate_per_s": round(rate, 1), "mean_request_bytes": round(mean_bytes),
+           "served_gbps": round(served, 2),
+           "p50_us": round(float(np.percentile(lat, 50)), 1), "p99_us": round(float(np.percentile(lat, 99)), 1),
+           "max_concurrent_batches": stats["max_concurrent_batches"], "batches": stats["batches"],
+           "failed": stats["failed"], "init_s": round(init_s, 2),
+           "arena_high_water_bytes": stats["arena_high_water"], "hbm_budget_bytes": budget,
+           "table_bytes_high": stats["table_bytes_high"], "table_reserve_bytes": stats["table_reserve_bytes"],
+           "bytes_counted": "encode and decode: object bytes; repair: the alpha repaired blocks"}
+    if not sequential:
+        return res
     # the same requests as plain single calls, one after another
     stream = torch.cuda.current_stream().cuda_stream
     scratch = torch.empty(max(q["code"].d * q["block_bytes"] for q in reqs if q["op"] == "repair") + 256,
@@ -639,15 +651,8 @@ def served_case(torch, pm, synth, nreq=20000, rho=0.8):
                 pm.pm_repair_newcomer(c.h, q["failed"], q["helpers"], scratch.data_ptr(), s, outb.data_ptr(), s,
                                       s, stream)
     wall_seq, _ = Timer(torch).run(seq, 1, 0)
-    return {"requests": nreq, "capacity_gbps": round(capacity, 2), "offered_rho": rho,
-            "offered_rate_per_s": round(rate, 1), "mean_request_bytes": round(mean_bytes),
-            "served_gbps": round(served, 2),
-            "p50_us": round(float(np.percentile(lat, 50)), 1), "p99_us": round(float(np.percentile(lat, 99)), 1),
-            "max_concurrent_batches": stats["max_concurrent_batches"], "batches": stats["batches"],
-            "init_s": round(init_s, 2),
-            "arena_high_water_bytes": stats["arena_high_water"], "hbm_budget_bytes": budget,
-            "sequential_plain_gbps": round(float(sum(nbytes)) / wall_seq / 1e9, 2),
-            "bytes_counted": "encode and decode: object bytes; repair: the alpha repaired blocks"}
+    res["sequential_plain_gbps"] = round(float(sum(nbytes)) / wall_seq / 1e9, 2)
+    return res
 
 
 def cpu_model():
@@ -724,12 +729,20 @@ def main():
     if args.part == "batched":
         print(json.dumps({"batched": batched_case(torch, pm, synth, max(5, args.steps // 20))}), flush=True)
         return
-    if args.part == "served":
-        print(json.dumps({"served": served_case(torch, pm, synth)}), flush=True)
+    if args.part in ("served", "served-only"):
+        # served-only: the server alone (no sequential plain-call baseline),
+        # for profiles of the served kernels
+        print(json.dumps({"served": served_case(torch, pm, synth, sequential=args.part == "served")}), flush=True)
         return
     if args.part == "gf16":
         print(json.dumps({k: round(v, 2) for k, v in gf16_cases(torch, pm, synth, args.steps, args.warmup).items()}),
               flush=True)
+        return
+    if args.part == "repair-decode":
+        out = {}
+        for fn in (msr_repair_decode, mbr_cases, msr16_decode_case):
+            out.update(fn(torch, pm, synth, args.steps, args.warmup))
+        print(json.dumps({k: (round(v, 3) if isinstance(v, float) else v) for k, v in out.items()}), flush=True)
         return
     if args.part == "dense":
         res = dense_config2(torch, pm, synth, 64 << 20, args.steps, args.warmup)
