@@ -301,8 +301,16 @@ pm_status pm_apply(const uint8_t *A, uint32_t rows, uint32_t cols, const uint8_t
  * hipRTC failure is reported as PM_EHIP.  0, 0 restores the default: the
  * bit-sliced kernel when the operation's matrix has one compiled (by
  * pm_prepare, pm_autotune_encode or a call under variant 32) and the block
- * is at least 2048 bytes, else the table kernel with the cost-model rows
- * per group and 2 dwords per lane.  The default never compiles by itself.
+ * is at least 2048 bytes; else, for a dense matrix (half or more of its
+ * entries nonzero, at least 64 x 64, at most 512 columns) too large to
+ * specialize, the matrix-core kernel (dwords_per_lane 40 with
+ * rows_per_group 8 selects it explicitly: the matrix's GF(2) expansion, 8
+ * rows x 8 columns of bits per coefficient, multiplied with the input bits
+ * on v_mfma with 4-bit float operands and reduced to parities, the
+ * bit-matrix view of Section 4.1 on the matrix cores; for more than 512
+ * columns, or input blocks reaching past 4 GiB from the first, the table
+ * kernel runs instead); else the table kernel with the cost-model rows per
+ * group and 2 dwords per lane.  The default never compiles by itself.
  * Every variant gives the same bytes.  PM_EINVAL for other values. */
 pm_status pm_set_variant(pm_code *code, int op, uint32_t rows_per_group,
                          uint32_t dwords_per_lane);

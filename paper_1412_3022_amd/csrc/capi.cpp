@@ -18,6 +18,7 @@
 #include "engine.hpp"
 #include "gf16.hpp"
 #include "gj.hpp"
+#include "mfma.hpp"
 #include "noalloc.hpp"
 #include "put.hpp"
 #include "pm.h"
@@ -52,7 +53,10 @@ static int upload_stream(int dev, hipStream_t *out) {
     return ST_OK;
 }
 
-ProgEntry::~ProgEntry() { free_device_copies(dev); }
+ProgEntry::~ProgEntry() {
+    free_device_copies(dev);
+    free_device_copies(mf_dev);
+}
 
 static std::atomic<size_t> g_table_bytes{0};
 static std::atomic<uint32_t> g_fail_uploads{0};
@@ -178,6 +182,78 @@ int ProgEntry::device_ptr_sync(const uint32_t **out) {
     return st;
 }
 
+// A dense matrix beyond the specialization limit: at least half of its
+// entries nonzero and at least 64 x 64 of them (the table kernel's cost
+// grows with the nonzeros, the matrix cores' with the whole matrix), and at
+// most 512 columns (the kernel's operands of one M tile in LDS).
+bool ProgEntry::mfma_eligible() {
+    if (A.rows == 0 || A.cols == 0) return false;
+    if (static_cast<uint32_t>(A.cols) > kMfMaxChunks * kMfColsPerChunk) return false;
+    const long cells = static_cast<long>(A.rows) * A.cols;
+    if (cells < 64 * 64 || prog.nnz * 2 < cells) return false;
+    std::shared_ptr<BsProgram> b = bitslice();
+    return !b;
+}
+
+void ProgEntry::build_mfma_locked() {
+    if (mf_tried) return;
+    mf_tried = true;
+    MfmaProgram P = build_mfma_program(A, in_map);
+    mf_words = std::move(P.words);
+    mf_nmtiles = P.nmtiles;
+    mf_nchunks = P.nchunks;
+    mf_cols_off = P.cols_off;
+    mf_rows_off = P.rows_off;
+    mf_ok = true;
+}
+
+size_t ProgEntry::mfma_upload_bytes() {
+    int devid = 0;
+    if (hipGetDevice(&devid) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = mf_dev.find(devid);
+    if (it != mf_dev.end() && it->second.ptr) return 0;
+    build_mfma_locked();
+    return mf_words.size() * sizeof(uint32_t);
+}
+
+int ProgEntry::stage_mfma() {
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        build_mfma_locked();
+    }
+    const void *d = nullptr;
+    return device_copy_sync(mu, mf_dev, mf_words.data(), mf_words.size() * sizeof(uint32_t), &d);
+}
+
+int ProgEntry::launch_mfma(const uint8_t *in, size_t in_ld, uint8_t *out, size_t out_ld, size_t s,
+                           hipStream_t stream, bool resident_only) {
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!mf_tried && resident_only) return ST_ENOTREADY;
+        build_mfma_locked();
+    }
+    if (!mf_ok) return ST_EINVAL;
+    const void *d = nullptr;
+    int st;
+    if (resident_only) {
+        int devid = 0;
+        hipError_t e = hipGetDevice(&devid);
+        if (e != hipSuccess) return hip_fail(e);
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = mf_dev.find(devid);
+        if (it == mf_dev.end() || !it->second.ptr || !it->second.done) return ST_ENOTREADY;
+        d = it->second.ptr;
+    } else if ((st = device_copy(mu, mf_dev, mf_words.data(), mf_words.size() * sizeof(uint32_t), stream, &d)) !=
+               ST_OK) {
+        return st;
+    }
+    const uint32_t *w = static_cast<const uint32_t *>(d);
+    PmkMfma h{in, in_ld, out, out_ld, s, w, w + mf_cols_off, w + mf_rows_off, mf_nmtiles, mf_nchunks, 0, 0, 0, 0};
+    hipError_t e = pmk_mfma(&h, stream);
+    return e == hipSuccess ? ST_OK : hip_fail(e);
+}
+
 std::shared_ptr<BsProgram> ProgEntry::bitslice() {
     std::lock_guard<std::mutex> lk(mu);
     if (!bs_tried) {
@@ -245,7 +321,15 @@ int launch_program(ProgEntry &pe, int vec, const uint8_t *in, size_t in_ld, size
     if ((st = check_regions(out, out_ld, out_n, s)) != ST_OK) return st;
     if (overlaps(in, in_ld, in_n, out, out_ld, out_n, s)) return ST_EINVAL;
     if (pe.prog.ngroups == 0) return ST_OK;
-    if (vec == kVecBitslice && !resident_only) {
+    // the matrix cores take up to 512 columns and address the input within
+    // 4 GiB of its first block; past that the table kernel gives the same
+    // bytes
+    const bool mf_span =
+        static_cast<uint32_t>(pe.A.cols) <= kMfMaxChunks * kMfColsPerChunk && mf_span_ok(in_ld, s, in_n);
+    if (vec == kVecMfma) {
+        if (mf_span) return pe.launch_mfma(in, in_ld, out, out_ld, s, stream, resident_only);
+        vec = 4;
+    } else if (vec == kVecBitslice && !resident_only) {
         // blocks shorter than one tile, and matrices too large for a
         // specialized kernel, run on the table kernel
         if (s >= kBsTileBytes)
@@ -259,6 +343,11 @@ int launch_program(ProgEntry &pe, int vec, const uint8_t *in, size_t in_ld, size
                 // may still be resident
                 if (st != ST_ENOTREADY) return st;
             }
+        // dense matrices over the specialization limit: the matrix cores
+        if (vec == kVecAuto && mf_span && pe.mfma_eligible()) {
+            st = pe.launch_mfma(in, in_ld, out, out_ld, s, stream, resident_only);
+            if (st != ST_ENOTREADY) return st;
+        }
         vec = vec == kVecBitslice ? 4 : kVecTable;
     }
     const uint32_t *dprog = nullptr;
@@ -280,6 +369,7 @@ static size_t entry_device_bytes(ProgEntry &pe) {
     std::lock_guard<std::mutex> lk(pe.mu);
     size_t b = 0;
     for (auto &kv : pe.dev) b += kv.second.bytes;
+    for (auto &kv : pe.mf_dev) b += kv.second.bytes;
     if (pe.bs) b += 1;   // a loaded kernel module: device memory of unknown size
     return b;
 }
@@ -932,7 +1022,8 @@ pm_status pm_set_variant(pm_code *c, int op, uint32_t rg, uint32_t vec) {
     const bool reset = rg == 0 && vec == 0;
     if (!reset && ((rg != 4 && rg != 8 && rg != 16) ||
                    (vec != 2 && vec != 4 && vec != 12 && vec != 14 && vec != 22 && vec != 24 &&
-                    vec != kVecBitslice) || (vec == kVecBitslice && rg != 8)))
+                    vec != kVecBitslice && vec != kVecMfma) ||
+                   ((vec == kVecBitslice || vec == kVecMfma) && rg != 8)))
         return PM_EINVAL;
     if (op == 4) {
         set_apply_variant(static_cast<int>(rg), static_cast<int>(vec));
@@ -1173,6 +1264,7 @@ int stage_on_device(ProgEntry &pe, BsProgram *bp, BsKind kind) {
     const uint32_t *d = nullptr;
     int st = pe.device_ptr_sync(&d);
     if (st == ST_OK && bp) st = bs_load(*bp, kind);
+    if (st == ST_OK && !bp && pe.mfma_eligible()) st = pe.stage_mfma();
     return st;
 }
 
@@ -1394,8 +1486,9 @@ pm_status pm_autotune_encode(pm_code *c, const uint8_t *X, size_t x_ld, uint8_t 
     int brg = 0, bvec = 0;
     pm_status rc = PM_OK;
     for (int rg : {4, 8, 16}) {
-        for (int vec : {2, 4, 12, 14, 22, 24, kVecBitslice}) {
-            if (vec == kVecBitslice && rg != 8) continue;   // one specialization per matrix
+        for (int vec : {2, 4, 12, 14, 22, 24, kVecBitslice, kVecMfma}) {
+            // one specialization per matrix; the matrix cores for dense ones
+            if ((vec == kVecBitslice || vec == kVecMfma) && rg != 8) continue;
             pm_set_variant(c, 0, static_cast<uint32_t>(rg), static_cast<uint32_t>(vec));
             rc = pm_encode(c, X, x_ld, out, out_ld, s, stream);   // warm-up (and upload)
             if (rc != PM_OK) break;

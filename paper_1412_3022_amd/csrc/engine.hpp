@@ -68,6 +68,13 @@ struct ProgEntry {
     std::map<int, DevCopy> dev;
     bool bs_tried = false;
     std::shared_ptr<BsProgram> bs;   // bit-sliced specialization, if eligible
+    // matrix-core form (dense matrices too large to specialize), built on
+    // first use, with its per-device copies
+    bool mf_tried = false;
+    bool mf_ok = false;
+    std::vector<uint32_t> mf_words;
+    uint32_t mf_nmtiles = 0, mf_nchunks = 0, mf_cols_off = 0, mf_rows_off = 0;
+    std::map<int, DevCopy> mf_dev;
     ~ProgEntry();
     // The bit-sliced specialization, generated (not compiled) on first use;
     // nullptr when the matrix is too large to specialize.
@@ -85,6 +92,19 @@ struct ProgEntry {
     // Bytes a device_ptr call would upload on the current device (0 when
     // the copy is there).
     size_t upload_bytes();
+    // Whether the matrix is dense and too large for a specialized kernel:
+    // then the matrix-core kernel runs instead of the table kernel.
+    bool mfma_eligible();
+    // Enqueue the matrix-core product (builds and uploads its operands on
+    // first use; resident_only: ST_ENOTREADY unless they are on the device).
+    int launch_mfma(const uint8_t *in, size_t in_ld, uint8_t *out, size_t out_ld, size_t s, hipStream_t stream,
+                    bool resident_only = false);
+    // Build and upload the matrix-core operands now (init phase; waits for
+    // the upload).
+    int stage_mfma();
+    // Bytes stage_mfma would upload on the current device.
+    size_t mfma_upload_bytes();
+    void build_mfma_locked();
 };
 
 constexpr int kVecBitslice = 32;   // variant code of the bit-sliced specialization
@@ -94,6 +114,7 @@ constexpr int kVecBitslice = 32;   // variant code of the bit-sliced specializat
 // dwords per lane.
 constexpr int kVecAuto = 0;
 constexpr int kVecTable = 2;
+constexpr int kVecMfma = 40;      // variant code of the matrix-core kernel
 
 struct Variant {
     int rg = 0;   // 0 = cost model

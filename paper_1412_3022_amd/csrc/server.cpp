@@ -26,6 +26,7 @@
 
 #include "construct.hpp"
 #include "engine.hpp"
+#include "mfma.hpp"
 #include "pm.h"
 
 using namespace pmrc;
@@ -199,6 +200,15 @@ struct pm_server {
         // items whose matrix has a compiled multi-set bit-sliced kernel, per
         // phase and matrix
         std::map<BsProgram *, std::pair<std::shared_ptr<BsProgram>, std::vector<BsItem>>> bs_lists[kPhases];
+        // items on the matrix cores, per phase
+        struct MfItem {
+            std::shared_ptr<ProgEntry> pe;
+            const uint8_t *in;
+            uint64_t in_ld;
+            uint8_t *out;
+            uint64_t out_ld, s;
+        };
+        std::vector<MfItem> mf_lists[kPhases];
         const int vec = static_cast<int>(cfg.dwords_per_lane ? cfg.dwords_per_lane : 2);
         const uint64_t wave_bytes = static_cast<uint64_t>(pmk_wave_bytes(vec));
         auto add = [&](int phase, const Resolved &rs, const uint8_t *in, uint64_t in_ld, uint8_t *out,
@@ -212,6 +222,19 @@ struct pm_server {
                     e.second.push_back(bs_item(in, in_ld, out, out_ld, s, 0));
                     return ST_OK;
                 }
+            // dense matrices over the specialization limit: the matrix
+            // cores, one launch per item in the phase
+            if (rs.vec == kVecAuto && mf_span_ok(in_ld, s, rs.in_n) && rs.pe->mfma_eligible()) {
+                const size_t need = rs.pe->mfma_upload_bytes();
+                if (need && device_table_bytes() + need > reserve) {
+                    trim_tables(reserve > need ? reserve - need : 0);
+                    if (device_table_bytes() + need > reserve) return ST_ENOMEM;
+                }
+                const int st = rs.pe->stage_mfma();
+                if (st != ST_OK) return st;
+                mf_lists[phase].push_back(MfItem{rs.pe, in, in_ld, out, out_ld, s});
+                return ST_OK;
+            }
             // a table not yet on the device counts against the reserve
             const size_t need = rs.pe->upload_bytes();
             if (need && device_table_bytes() + need > reserve) {
@@ -295,6 +318,10 @@ struct pm_server {
         for (int ph = 0; ph < kPhases; ++ph) {
             for (const BsLaunch &l : bs_launches[ph]) {
                 int rc = bs_launch_items(*l.bp, sl.d_bs + l.start, l.n, l.ntiles, sl.stream);
+                if (rc != ST_OK) return drain(rc);
+            }
+            for (const MfItem &m : mf_lists[ph]) {
+                int rc = m.pe->launch_mfma(m.in, m.in_ld, m.out, m.out_ld, m.s, sl.stream);
                 if (rc != ST_OK) return drain(rc);
             }
             for (int c = 0; c < kClasses; ++c) {

@@ -69,6 +69,50 @@ def test_apply_dense_shapes(shape):
     assert np.array_equal(read(out, s), O.apply(A, X, nthreads=8))
 
 
+@pytest.mark.parametrize("shape,dens", [((16, 8), 1.0), ((13, 9), 1.0), ((240, 240), 1.0), ((112, 84), 0.6),
+                                        ((56, 56), 0.25), ((100, 37), 1.0)])
+@pytest.mark.parametrize("s", [1, 100, 129, 4096, 12289 + 77])
+def test_apply_on_the_matrix_cores(shape, dens, s):
+    """The matrix-core kernel (variant 40) on dense and sparse matrices,
+    padded shapes and every tail case of its 128-byte position blocks."""
+    rows, cols = shape
+    print("apply mfma %s dens=%.2f s=%d" % (shape, dens, s), flush=True)
+    rng = np.random.default_rng(rows * 7919 + cols * 31 + s)
+    A = rng.integers(1, 256, (rows, cols), dtype=np.uint8)
+    A[rng.random((rows, cols)) >= dens] = 0
+    X = _rand(rows + 3 * cols + s, cols, s)
+    pm.lib()
+    pm.pm_set_variant(None, pm.OP_APPLY, 8, 40)
+    try:
+        xin = to_regions(X, extra=1, offset_rows=1)
+        out = out_regions(rows, s, extra=2)
+        pm.apply(A, xin, out, s)
+        assert np.array_equal(read(out, s), O.apply(A, X, nthreads=8))
+    finally:
+        pm.pm_set_variant(None, pm.OP_APPLY, 0, 0)
+
+
+@pytest.mark.parametrize("shape", [(360, 360), (40, 512)])
+@pytest.mark.parametrize("s", [129, 4096 + 77])
+def test_matrix_cores_with_more_than_64_kib_of_lds(shape, s):
+    """45 and 64 chunks of 8 input blocks: the work-group's operands take
+    94 and 132 KiB of LDS (the dynamic limit raised past 64 KiB)."""
+    rows, cols = shape
+    print("apply mfma %s s=%d" % (shape, s), flush=True)
+    rng = np.random.default_rng(rows + cols + s)
+    A = rng.integers(1, 256, (rows, cols), dtype=np.uint8)
+    X = _rand(rows * 3 + cols + s, cols, s)
+    pm.lib()
+    pm.pm_set_variant(None, pm.OP_APPLY, 8, 40)
+    try:
+        xin = to_regions(X, extra=1, offset_rows=1)
+        out = out_regions(rows, s, extra=2)
+        pm.apply(A, xin, out, s)
+        assert np.array_equal(read(out, s), O.apply(A, X, nthreads=8))
+    finally:
+        pm.pm_set_variant(None, pm.OP_APPLY, 0, 0)
+
+
 # ----------------------------------------------------------- small codes --
 SMALL = [
     dict(k=3, d=4, n=6, kind=pm.PM_MSR, construction=pm.PM_VANILLA, x=list(range(1, 7))),
