@@ -412,9 +412,10 @@ def gf16_cases(torch, pm, synth, steps, warmup):
     top of the paper's range), and at k = 8 the repair of node 0 (helper and
     newcomer) and the decode from the last k nodes and from a half-systematic
     node set (its held blocks copied), and at k = 40 and 64 the specific
-    decode (and at k = 40 the linearized one) from the last k nodes, on the
-    GF(2^16) region kernel.  GB/s of source bytes (node bytes for repair and
-    decode); init times in seconds."""
+    decode (and at k = 40 the linearized one) from the last k nodes: on the
+    generated bit-sliced kernels where the matrix is under their size limit
+    (the *_bitsliced fields), else the GF(2^16) table kernel.  GB/s of source
+    bytes (node bytes for repair and decode); init times in seconds."""
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream().cuda_stream
     S = 64 << 20
@@ -435,8 +436,8 @@ def gf16_cases(torch, pm, synth, steps, warmup):
         s = synth.block_bytes_for(S, code.B)
         xs = [synth.random_bytes_torch(0x1600 + k + j, code.B * s, dev).view(code.B, s) for j in range(NBUF)]
         outs = [torch.empty((code.enc_rows, s), dtype=torch.uint8, device=dev) for _ in range(NBUF)]
-        code.prepare(pm.OP_ENCODE)
         key = "gf16_k%d_%s_encode" % (k, "sys" if sys_ else "nonsys")
+        out[key + "_bitsliced"] = code.prepare(pm.OP_ENCODE)
         timed(lambda i: pm.pm_encode(code.h, xs[i % NBUF].data_ptr(), s, outs[i % NBUF].data_ptr(), s, s, stream),
               code.B * s, code.B, code.enc_rows, s, key)
         if k == 8:
@@ -446,8 +447,8 @@ def gf16_cases(torch, pm, synth, steps, warmup):
             rep_out = torch.empty((code.alpha, s), dtype=torch.uint8, device=dev)
             Y = torch.empty((code.B, s), dtype=torch.uint8, device=dev)
             code.prepare(pm.OP_HELPER, failed=f)
-            code.prepare(pm.OP_NEWCOMER, failed=f, ids=H)
-            code.prepare(pm.OP_DECODE, ids=K)
+            out["gf16_k8_newcomer_bitsliced"] = code.prepare(pm.OP_NEWCOMER, failed=f, ids=H)
+            out["gf16_k8_decode_bitsliced"] = code.prepare(pm.OP_DECODE, ids=K)
             timed(lambda i: pm.pm_repair_helper(code.h, f, node.data_ptr(), s, recv.data_ptr(), s, stream),
                   code.alpha * s, code.alpha, 1, s, "gf16_k8_helper")
             timed(lambda i: pm.pm_repair_newcomer(code.h, f, H, recv.data_ptr(), s, rep_out.data_ptr(), s, s,
@@ -456,7 +457,7 @@ def gf16_cases(torch, pm, synth, steps, warmup):
                   code.B * s, code.B, code.B, s, "gf16_k8_decode")
             # half the nodes systematic: their blocks are copied, the lost half computed
             Km = [0, 1, 2, 3, 12, 13, 14, 15]
-            code.prepare(pm.OP_DECODE, ids=Km)
+            out["gf16_k8_decode_mixed_bitsliced"] = code.prepare(pm.OP_DECODE, ids=Km)
             timed(lambda i: pm.pm_decode(code.h, Km, Y.data_ptr(), s, xs[i % NBUF].data_ptr(), s, s, stream),
                   code.B * s, code.B, code.B, s, "gf16_k8_decode_mixed")
         if k >= 40:
@@ -735,7 +736,8 @@ def main():
         print(json.dumps({"served": served_case(torch, pm, synth, sequential=args.part == "served")}), flush=True)
         return
     if args.part == "gf16":
-        print(json.dumps({k: round(v, 2) for k, v in gf16_cases(torch, pm, synth, args.steps, args.warmup).items()}),
+        print(json.dumps({k: (round(v, 2) if isinstance(v, float) else v)
+                          for k, v in gf16_cases(torch, pm, synth, args.steps, args.warmup).items()}),
               flush=True)
         return
     if args.part == "repair-decode":
@@ -769,7 +771,8 @@ def main():
                       for k, v in msr16_decode_case(torch, pm, synth, args.steps, args.warmup).items()})
         extra.update({k: (round(v, 3) if isinstance(v, float) else v)
                       for k, v in gpu_init_case(torch, pm, synth).items()})
-        extra.update({k: round(v, 2) for k, v in gf16_cases(torch, pm, synth, args.steps, args.warmup).items()})
+        extra.update({k: (round(v, 2) if isinstance(v, float) else v)
+                      for k, v in gf16_cases(torch, pm, synth, args.steps, args.warmup).items()})
     batched = served = None
     if not args.no_batch:
         batched = batched_case(torch, pm, synth, max(5, args.steps // 20))

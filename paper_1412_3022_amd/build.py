@@ -23,7 +23,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
 HOST_SOURCES = ["gf256.cpp", "construct.cpp", "program.cpp", "capi.cpp", "batch.cpp", "server.cpp", "bitslice.cpp",
-                "gf16.cpp", "mfma.cpp"]
+                "gf16.cpp", "mfma.cpp", "bitslice16.cpp"]
 HIP_SOURCES = ["kernels.hip", "gj.hip", "gf16.hip", "noalloc.hip", "mfma.hip"]
 
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__",

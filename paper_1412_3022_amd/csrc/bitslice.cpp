@@ -557,12 +557,15 @@ int bs_launch(BsProgram &bp, const uint8_t *in, uint64_t in_ld, uint8_t *out, ui
               hipStream_t st, bool resident_only) {
     // the window tile needs one full tile before it; shorter blocks are
     // refused here and left to the table kernels by the caller
-    if (s < kBsTileBytes) return ST_EINVAL;
-    if (s / kBsTileBytes + 1 > 0xffffffffull) return ST_EINVAL;
+    const uint64_t tb = bp.tile_bytes;
+    if (s < tb) return ST_EINVAL;
+    if (s / tb + 1 > 0xffffffffull) return ST_EINVAL;
     BsModule *m;
     int rc = bs_module(bp, BS_SINGLE, &m, resident_only);
     if (rc != ST_OK) return rc;
-    const BsItem it = bs_item(in, in_ld, out, out_ld, s, 0);
+    const uint64_t s16 = s & ~uint64_t(15), nfull = s16 / tb;
+    const BsItem it{in, in_ld, out, out_ld, s, static_cast<uint32_t>(nfull),
+                    static_cast<uint32_t>(nfull + (s16 % tb ? 1 : 0)), 0, 0};
     struct {
         const uint8_t *in;
         uint64_t ld;

@@ -40,7 +40,8 @@ struct BsKernel {
 
 struct BsProgram {
     int ngroups = 0;
-    long est_ops = 0;   // straight-line VALU operations per 32-byte lane chunk
+    long est_ops = 0;   // straight-line VALU operations per lane chunk
+    uint32_t tile_bytes = 2048;   // bytes of a block per wave tile (4096 for GF(2^16))
     std::mutex mu;
     BsKernel k[2];      // by BsKind
     ~BsProgram();

@@ -1298,16 +1298,25 @@ pm_status pm_prepare(pm_code *c, int op, uint32_t failed, const uint32_t *ids, u
         if (specialized) *specialized = s1 && s2;
         return st;
     }
-    if (c->w16) {   // the matrices and their programs, staged on the device; no specialized kernel
+    if (c->w16) {   // the matrices, their programs and bit-sliced kernels, staged on the device
         if (flags & PM_PREPARE_BATCHED) return PM_EUNSUPPORTED;
         w16::Prog16 *pe[kSpecificPasses] = {};
         int rows[kSpecificPasses], npass = 1;
         size_t in_n = 0, out_n = 0;
         int st = op == 4 ? w16::resolve_specific16(*c->w16, ids, pe, rows, &npass)
                          : w16::resolve16(*c->w16, op, failed, ids, &pe[0], &in_n, &out_n);
+        int all = 1;
+        for (int p = 0; p < npass && st == ST_OK; ++p) {
+            int sp = 0;
+            st = w16::compile16(*pe[p], &sp);
+            all &= sp;
+        }
         int ndev = 0;
         if (st == ST_OK && hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0)
             for (int p = 0; p < npass && st == ST_OK; ++p) st = w16::stage16(*pe[p]);
+        else
+            (void)hipGetLastError();
+        if (specialized && st == ST_OK) *specialized = all;
         return static_cast<pm_status>(st);
     }
     if (op == 4) {   // the passes of the specific decode

@@ -345,7 +345,17 @@ int specific_factors(const Code16 &c, const std::vector<int> &K, Mat16 F[kSpecif
 // generator, the rows alpha i + j of all nodes i read the message symbols of
 // column j of M.  This cuts the records of the k = 8 systematic encode from
 // 392 to 98, and of the k = 64 non-systematic one from 487 760 to 75 612.
-Prog16::Prog16(const Mat16 &A) : rows(A.rows), cols(A.cols) {
+std::shared_ptr<BsProgram> Prog16::bitslice() {
+    std::lock_guard<std::mutex> lk(mu);
+    if (!bs_tried) {
+        bs_tried = true;
+        std::unique_ptr<BsProgram> b = bs16_generate(A);
+        if (b->est_ops <= kBsMaxOps && b->ngroups > 0) bs = std::move(b);
+    }
+    return bs;
+}
+
+Prog16::Prog16(const Mat16 &A_) : rows(A_.rows), cols(A_.cols), A(A_) {
     const int R = static_cast<int>(kPm16Rows);
     std::vector<std::vector<int>> sup(A.rows);
     std::vector<int> order, copies;
@@ -536,6 +546,21 @@ int stage16(Prog16 &p) {
     const void *d = nullptr;
     int st = device_copy_sync(g_tab_mu, g_tab_dev, t.data(), t.size() * sizeof(uint32_t), &d);
     if (st == ST_OK) st = device_copy_sync(p.mu, p.dev, p.words.data(), p.words.size() * sizeof(uint32_t), &d);
+    std::shared_ptr<BsProgram> bp;
+    {
+        std::lock_guard<std::mutex> lk(p.mu);
+        bp = p.bs;
+    }
+    if (st == ST_OK && bp && bs_ready(*bp, BS_SINGLE)) st = bs_load(*bp, BS_SINGLE);
+    return st;
+}
+
+int compile16(Prog16 &p, int *specialized) {
+    std::shared_ptr<BsProgram> bp = p.bitslice();
+    if (specialized) *specialized = 0;
+    if (!bp) return ST_OK;
+    int st = bs_compile(*bp, BS_SINGLE);
+    if (st == ST_OK && specialized) *specialized = 1;
     return st;
 }
 
@@ -547,6 +572,14 @@ int launch16(Prog16 &p, const uint8_t *in, size_t in_ld, size_t in_n, uint8_t *o
     if ((st = check_regions(out, out_ld, out_n, s)) != ST_OK) return st;
     if (overlaps(in, in_ld, in_n, out, out_ld, out_n, s)) return ST_EINVAL;
     if (p.ngroups == 0) return ST_OK;
+    // the bit-sliced kernel once compiled (init phase), for blocks of at
+    // least one of its tiles
+    std::shared_ptr<BsProgram> bp;
+    {
+        std::lock_guard<std::mutex> lk(p.mu);
+        bp = p.bs;
+    }
+    if (bp && bs_ready(*bp, BS_SINGLE) && s >= bp->tile_bytes) return bs_launch(*bp, in, in_ld, out, out_ld, s, stream);
     const uint64_t ntiles = (s + kPm16TileBytes - 1) / kPm16TileBytes;
     // tile numbers are 32-bit and the grid holds at most 2^31 - 1 work-groups of 4 items
     if (ntiles > 0xFFFFFFFFull || ntiles * p.ngroups > 0x1FFFFFFFCull) return ST_EINVAL;

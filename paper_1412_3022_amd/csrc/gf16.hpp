@@ -51,16 +51,27 @@ Mat16 helper_row(const Code16 &c, int failed);
 int newcomer_matrix(const Code16 &c, int failed, const std::vector<int> &helpers, Mat16 &R);
 int decode_matrix(const Code16 &c, const std::vector<int> &nodes, Mat16 &D);
 
-// A matrix packed for the kernel, with its per-device copies.
+// A matrix packed for the kernel, with its per-device copies, and its
+// bit-sliced specialization (bitslice16.cpp) when it is small enough.
 struct Prog16 {
     std::vector<uint32_t> words;
     uint32_t ngroups = 0;
     int rows = 0, cols = 0;
+    Mat16 A;
     std::mutex mu;
     std::map<int, DevCopy> dev;
+    bool bs_tried = false;
+    std::shared_ptr<BsProgram> bs;
     explicit Prog16(const Mat16 &A);
     ~Prog16() { free_device_copies(dev); }
+    // The bit-sliced kernel's source, generated on first use (nullptr when
+    // the matrix is over the size limit).
+    std::shared_ptr<BsProgram> bitslice();
 };
+
+// Straight-line bit-sliced kernel source for a GF(2^16) matrix (not
+// compiled); est_ops over kBsMaxOps means no source.
+std::unique_ptr<BsProgram> bs16_generate(const Mat16 &A);
 
 // The specific PM-MSR decode from the k nodes K as five factors (the
 // GF(2^16) counterpart of specific_decode_factors; F[4] empty for a
@@ -92,8 +103,12 @@ int resolve_specific16(Ctx16 &c, const uint32_t *ids, Prog16 *pe[kSpecificPasses
 // Factor `which` of a node list already resolved, or nullptr.
 const Mat16 *specific_factor16(Ctx16 &c, const uint32_t *ids, int which);
 // Upload the program (and the field tables) to the current device and wait
-// for those copies (no other work is waited for).
+// for those copies (no other work is waited for); with a GPU present also
+// loads the bit-sliced kernel if compile16 compiled one.
 int stage16(Prog16 &p);
+// Init phase: generate and compile the bit-sliced kernel (hipRTC, no GPU
+// needed); *specialized = 1 when it is ready.
+int compile16(Prog16 &p, int *specialized);
 // out (out_n blocks) = A in (in_n blocks), s bytes per block (even).
 int launch16(Prog16 &p, const uint8_t *in, size_t in_ld, size_t in_n, uint8_t *out, size_t out_ld, size_t out_n,
              size_t s, hipStream_t stream);

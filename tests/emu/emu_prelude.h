@@ -22,3 +22,17 @@ static EmuDim threadIdx, blockIdx;
 // through an unsigned type sign-extends, as on the GPU).
 #define __builtin_amdgcn_readfirstlane(x) ((int)(x))
 #define __builtin_nontemporal_store(v, p) (*(p) = (v))
+// v_perm_b32 for byte selectors 0..7: bytes 0..3 from b, 4..7 from a
+static inline unsigned __builtin_amdgcn_perm(unsigned a, unsigned b, unsigned sel) {
+    const unsigned long long v = (static_cast<unsigned long long>(a) << 32) | b;
+    unsigned r = 0;
+    for (int i = 0; i < 4; ++i) {
+        const unsigned s = (sel >> (8 * i)) & 0xFF;
+        if (s > 7) abort();
+        r |= static_cast<unsigned>((v >> (8 * s)) & 0xFF) << (8 * i);
+    }
+    return r;
+}
+#ifndef EMU_TILE
+#define EMU_TILE 2048
+#endif

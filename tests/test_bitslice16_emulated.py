@@ -1,0 +1,153 @@
+"""The generated GF(2^16) bit-sliced kernels (csrc/bitslice16.cpp), compiled
+for the host and run thread by thread, against the oracle's GF(2^16) region
+product: dense matrices, zero rows, rows that copy an input block, rows
+sharing their supports, the code's encode, repair and decode matrices; block
+sizes of whole 4 KiB tiles, a window tile and a byte tail of 1 to 7 symbols;
+fewer and more work-group slots than row groups; buffers under
+AddressSanitizer and at addresses whose low 32 bits are >= 2^31.  The
+generator is the library's own (a small driver linked against it); the
+source a code's prepare call compiles is checked to be the same program.
+Needs no GPU."""
+import os
+import struct
+import subprocess
+
+import numpy as np
+import pytest
+
+import bs_emulator as E
+from oracle import gf16 as F
+from paper_1412_3022_amd import build as B
+from paper_1412_3022_amd import pm
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TILE = 4096
+
+pytestmark = pytest.mark.skipif(not os.path.exists(E.CLANG), reason="clang++ of the ROCm toolchain not found")
+
+
+@pytest.fixture(scope="module")
+def gen(tmp_path_factory):
+    pm.lib()   # the library is built
+    d = tmp_path_factory.mktemp("bs16")
+    exe = str(d / "bs16_gen")
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    subprocess.check_call(["g++", "-std=c++17", "-O1", "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(rocm, "include"),
+                           "-I" + B.CSRC, "-I" + B.INCLUDE, os.path.join(HERE, "emu", "bs16_gen.cpp"),
+                           "-L" + B.LIBDIR, "-lpmrc", "-Wl,-rpath," + B.LIBDIR, "-o", exe])
+    return exe
+
+
+def generate(gen, A, path):
+    """The generated source for matrix A (uint16), or None past the size
+    limit; also the group count."""
+    A = np.ascontiguousarray(A, np.uint16)
+    mfile = path + ".mat"
+    with open(mfile, "wb") as f:
+        f.write(struct.pack("<2I", *A.shape))
+        f.write(A.tobytes())
+    r = subprocess.run([gen, mfile, path], capture_output=True, text=True)
+    assert r.returncode in (0, 3), r.stderr
+    groups = int(r.stdout.split()[0])
+    return (path if r.returncode == 0 else None), groups
+
+
+def check(src, A, sizes, slots, seed, high_too=True):
+    """Run the kernel for each block size in `sizes` and slot count, compare
+    with the oracle (every output byte; nothing past s written)."""
+    rows, cols = A.shape
+    rng = np.random.default_rng(seed)
+    runs = [(True, False)] + ([(False, True)] if high_too else [])
+    exes = {h: E.build(src, False, sanitize=san, tile=TILE) for san, h in runs}
+    for i, s in enumerate(sizes):
+        X = rng.integers(0, 65536, (cols, s // 2), dtype=np.uint16)
+        X[:, -1] = 0xFFFF
+        want = F.apply(A, X)
+        ld = (s + 15) // 16 * 16 + 16 * (i % 3)
+        old = ld + 16 * ((i + 1) % 2)
+        inp = np.ascontiguousarray(X).view(np.uint8).reshape(cols, s)
+        for high, exe in exes.items():
+            for P in slots:
+                got, = E.run(exe, P, [(inp, ld, rows, old, s)], high=high)
+                assert np.array_equal(got.view(np.uint16), want), (s, P, high)
+
+
+SIZES = [TILE, TILE + 2, TILE + 14, TILE + 16 + 6, 3 * TILE + 1000]
+
+
+def _random(rng, rows, cols, dens):
+    A = rng.integers(1, 65536, (rows, cols), dtype=np.uint16)
+    A[rng.random((rows, cols)) >= dens] = 0
+    return A
+
+
+def test_dense_matrix(gen, tmp_path):
+    """Two full row groups reading every column; coefficients with high
+    bits set (the reduction by the field polynomial), 1 and x^15."""
+    rng = np.random.default_rng(1)
+    A = _random(rng, 8, 6, 1.0)
+    A[0, :3] = [1, 0x8000, 0xFFFF]
+    src, G = generate(gen, A, str(tmp_path / "dense.hip"))
+    assert src and G == 2
+    check(src, A, SIZES, (1, 3, 40), 11)
+
+
+def test_zero_copy_and_shared_support_rows(gen, tmp_path):
+    """Zero rows (written as zeros), rows that are an input block times 1
+    (copy groups, two of them), and rows of one support grouped together."""
+    rng = np.random.default_rng(2)
+    rows, cols = 23, 11
+    A = _random(rng, rows, cols, 0.4)
+    A[3] = 0
+    A[17] = 0
+    for r, c in zip(range(5, rows, 2), rng.permutation(cols)):   # 9 unit rows: a full copy group and one more
+        A[r] = 0
+        A[r, c] = 1
+    A[6] = 0
+    A[6, 4] = 1
+    A[8] = 0
+    A[8, [2, 7]] = [5, 9]
+    A[10] = 0
+    A[10, [2, 7]] = [0x1234, 1]
+    src, G = generate(gen, A, str(tmp_path / "mixed.hip"))
+    assert src
+    check(src, A, [TILE + 6, 2 * TILE], (1, 2, 5, 64), 12)
+
+
+def test_code_matrices(gen, tmp_path):
+    """The systematic encode, a helper's projection, a newcomer and a
+    decode matrix (half of the nodes systematic: their rows are copies) of
+    the sparse PM-MSR (4, 6, 8) code over GF(2^16).  (The k = 8 kernels run
+    on the GPU in the parity tests; their host builds take minutes.)"""
+    k, n = 4, 8
+    o = F.Code(k, n)
+    f, H = 1, [h for h in range(n) if h != 1][:o.d]
+    K = list(range(k // 2)) + list(range(n - k // 2, n))
+    mats = [("enc", o.enc), ("decode", o.decode_matrix(K)), ("helper", o.helper_row(f)),
+            ("newcomer", o.newcomer_matrix(f, H))]
+    for name, A in mats:
+        src, G = generate(gen, A, str(tmp_path / ("%s.hip" % name)))
+        assert src, name
+        check(src, A, [TILE + 10, 2 * TILE + 16], (3, 16), 17)
+
+
+def test_over_the_size_limit_is_left_to_the_table_kernel(gen, tmp_path):
+    """A dense 120 x 120 matrix is far past the operation limit: no source."""
+    rng = np.random.default_rng(3)
+    src, G = generate(gen, _random(rng, 120, 120, 1.0), str(tmp_path / "big.hip"))
+    assert src is None and G == 30
+
+
+def test_prepare_compiles_the_generated_program(gen, tmp_path):
+    """A GF(2^16) code's prepare call generates the same source for its
+    encode matrix and compiles it (hipRTC, no device needed): it reports the
+    operation specialized."""
+    c = pm.Code(k=4, d=6, n=8, w=16)
+    dump = str(tmp_path / "prep.hip")
+    os.environ["PMRC_BS_DUMP"] = dump
+    try:
+        assert pm.pm_prepare(c.h, pm.OP_ENCODE) == (pm.PM_OK, 1)
+    finally:
+        del os.environ["PMRC_BS_DUMP"]
+    src, _ = generate(gen, F.Code(4, 8).enc, str(tmp_path / "enc.hip"))
+    assert open(dump).read() == open(src).read()

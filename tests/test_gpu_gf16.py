@@ -95,12 +95,43 @@ def test_decode(k, n, sys_, s):
 
 def test_prepare_stages_the_operation():
     c = pm.Code(k=4, d=6, n=8, w=16)
-    assert c.prepare(pm.OP_ENCODE) is False          # no specialized kernel for GF(2^16)
-    assert c.prepare(pm.OP_DECODE, ids=[7, 5, 3, 1]) is False
+    assert c.prepare(pm.OP_ENCODE) is True           # the bit-sliced kernel, compiled and loaded
+    assert c.prepare(pm.OP_DECODE, ids=[7, 5, 3, 1]) is True
     o = F.Code(4, 8)
     s = 4096
     X = _data(c.B, s, 1901)
     assert np.array_equal(_u16(_encode(c, X, s)), o.encode(_u16(X)))
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("k,n,sys_", [(4, 8, True), (8, 16, True), (8, 16, False)])
+def test_bitsliced_kernels_after_prepare(k, n, sys_):
+    """Once prepared, encode, the newcomer and a decode from a half-systematic
+    node set run the generated bit-sliced kernels (blocks of at least one
+    4 KiB wave tile; a window tile and a byte tail of 1 to 15 symbols):
+    every symbol against the oracle."""
+    c = pm.Code(k=k, d=2 * k - 2, n=n, systematic=sys_, w=16)
+    o = F.Code(k, n, systematic_form=sys_)
+    f = 1
+    H = [h for h in range(n) if h != f][:c.d]
+    K = list(range(k // 2)) + list(range(n - k // 2, n))
+    assert c.prepare(pm.OP_ENCODE) is True
+    assert c.prepare(pm.OP_NEWCOMER, failed=f, ids=H) is True
+    assert c.prepare(pm.OP_DECODE, ids=K) is True
+    for s in (4096, 4096 + 2, 4096 + 30, 3 * 4096 + 1000):
+        print("gf16 bit-sliced", k, n, sys_, s, flush=True)
+        X = _data(c.B, s, 1950 + k + s % 71)
+        P = _encode(c, X, s)
+        assert np.array_equal(_u16(P), o.encode(_u16(X))), s
+        nodes = _nodes(o, X, P)
+        recv = np.stack([F.apply(o.helper_row(f), _u16(nodes[h]))[0] for h in H]).view(np.uint8)
+        out = out_regions(c.alpha, s)
+        c.repair_newcomer(f, H, to_regions(recv), out, s)
+        assert np.array_equal(read(out, s), nodes[f]), s
+        Y = np.concatenate([nodes[i] for i in K])
+        out = out_regions(c.B, s)
+        c.decode(K, to_regions(Y), out, s)
+        assert np.array_equal(read(out, s), X), s
 
 
 @pytest.mark.timeout(300)
@@ -133,6 +164,7 @@ def test_k8_64mib_object_sampled():
     oracle."""
     print("gf16 64MiB", flush=True)
     c = pm.Code(k=8, d=14, n=16, w=16)
+    assert c.prepare(pm.OP_ENCODE) is True   # the bit-sliced kernel, as the benchmark runs it
     o = F.Code(8, 16)
     s = 1198400
     X = synth.random_bytes_torch(0x16, c.B * s, device()).view(c.B, s)
