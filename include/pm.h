@@ -86,8 +86,10 @@ typedef struct {
  * symbols, little-endian (symbol p in bytes 2p and 2p+1), so block_bytes must
  * be even (else PM_EINVAL).  pm_encode, pm_repair_helper, pm_repair_newcomer
  * and pm_decode run on the GF(2^16) region kernel with the same arguments
- * as for w = 8; pm_prepare builds the operation's matrix and stages it on the
- * device (*specialized = 0).  pm_code_matrix writes two bytes per entry,
+ * as for w = 8; pm_prepare builds the operation's matrix, generates and
+ * compiles its bit-sliced kernel when the matrix is under the size limit
+ * (*specialized = 1; blocks of at least 4096 bytes then run on it) and stages
+ * both on the device.  pm_code_matrix writes two bytes per entry,
  * little-endian (cap counts bytes).  pm_decode_specific (and its workspace,
  * factor and pm_prepare forms) runs the specific PM-MSR decoder's passes on
  * the GF(2^16) kernel; pm_decode_specific_factor writes two bytes per entry.
@@ -121,8 +123,9 @@ pm_status pm_code_dims(const pm_code *code, uint32_t *alpha, uint32_t *beta,
                        uint32_t *B, uint32_t *enc_rows);
 
 /* Copy a host matrix of the code into host buffer `dst` of `cap` bytes
- * (row-major; two bytes per entry for w = 16), and its shape into *rows, *cols.  which: 0 = Psi (n x d; RS:
- * the n x k generator), 1 = Lambda (1 x n, MSR), 2 = G linearized
+ * (row-major; two bytes per entry for w = 16), and its shape into *rows,
+ * *cols.  which: 0 = Psi (n x d; RS: the n x k generator), 1 = Lambda
+ * (1 x n, MSR), 2 = G linearized
  * (n alpha x B), 3 = the generator node contents follow (G' or G),
  * 4 = the encode matrix (enc_rows x B).  PM_EINVAL if cap is too small. */
 pm_status pm_code_matrix(const pm_code *code, int which, uint8_t *dst, size_t cap,
@@ -521,9 +524,11 @@ pm_status pm_code_set_cache_limit(pm_code *code, uint32_t entries);
  * captured into a graph. */
 pm_status pm_cache_release(void);
 
-/* Device bytes held by kernel tables of every code on every device (evicted
- * patterns not yet freed included); the server keeps this within its table
- * reserve. */
+/* Device bytes held by the per-matrix kernel tables and matrix-core
+ * operands of every code on every device (evicted patterns not yet freed
+ * included; not the fixed 8 MiB GF(2^16) field table, which a GF(2^16) code
+ * uploads once per device and nothing evicts); the server keeps this within
+ * its table reserve. */
 size_t pm_table_bytes(void);
 
 /* Failure injection for tests of the error paths: the next `count` uploads

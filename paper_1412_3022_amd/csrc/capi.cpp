@@ -69,13 +69,13 @@ static void drop_copy(DevCopy &dc) {
     if (dc.ready) (void)hipEventDestroy(dc.ready);
     if (dc.ptr) {
         (void)hipFree(dc.ptr);
-        g_table_bytes -= dc.bytes;
+        if (dc.counted) g_table_bytes -= dc.bytes;
     }
     dc = DevCopy{};
 }
 
 int device_copy(std::mutex &mu, std::map<int, DevCopy> &dev, const void *host, size_t bytes, hipStream_t user,
-                const void **out) {
+                const void **out, bool counted) {
     int devid = 0;
     hipError_t e = hipGetDevice(&devid);
     if (e != hipSuccess) return hip_fail(e);
@@ -92,7 +92,8 @@ int device_copy(std::mutex &mu, std::map<int, DevCopy> &dev, const void *host, s
             return e == hipErrorOutOfMemory ? ST_ENOMEM : hip_fail(e);
         }
         dc.bytes = bytes;
-        g_table_bytes += bytes;
+        dc.counted = counted;
+        if (counted) g_table_bytes += bytes;
         if ((e = hipMemcpyAsync(dc.ptr, host, bytes, hipMemcpyHostToDevice, up)) != hipSuccess ||
             (e = hipEventCreateWithFlags(&dc.ready, hipEventDisableTiming)) != hipSuccess ||
             (e = hipEventRecord(dc.ready, up)) != hipSuccess) {
@@ -130,8 +131,8 @@ int ProgEntry::device_ptr(hipStream_t user, const uint32_t **out) {
 }
 
 int device_copy_sync(std::mutex &mu, std::map<int, DevCopy> &dev, const void *host, size_t bytes,
-                     const void **out) {
-    int st = device_copy(mu, dev, host, bytes, nullptr, out);
+                     const void **out, bool counted) {
+    int st = device_copy(mu, dev, host, bytes, nullptr, out, counted);
     if (st != ST_OK) return st;
     int devid = 0;
     hipError_t e = hipGetDevice(&devid);
@@ -1261,10 +1262,11 @@ int stage_on_device(ProgEntry &pe, BsProgram *bp, BsKind kind) {
         (void)hipGetLastError();
         return ST_OK;
     }
+    // a dense matrix on the matrix cores needs only their operands there
+    if (!bp && pe.mfma_eligible()) return pe.stage_mfma();
     const uint32_t *d = nullptr;
     int st = pe.device_ptr_sync(&d);
     if (st == ST_OK && bp) st = bs_load(*bp, kind);
-    if (st == ST_OK && !bp && pe.mfma_eligible()) st = pe.stage_mfma();
     return st;
 }
 

@@ -37,10 +37,12 @@ struct DevCopy {
     size_t bytes = 0;
     hipEvent_t ready = nullptr;
     bool done = false;
+    bool counted = true;   // included in device_table_bytes()
 };
 
-// Device bytes held by table copies (all codes, devices and caches, evicted
-// entries that still wait to be freed included).
+// Device bytes held by per-matrix table copies (all codes, devices and
+// caches, evicted entries that still wait to be freed included; not the
+// fixed GF(2^16) field table, which nothing can evict).
 size_t device_table_bytes();
 // Test hook: the next n table uploads fail with ST_ENOMEM before allocating.
 void fail_next_uploads(uint32_t n);
@@ -48,12 +50,13 @@ void fail_next_uploads(uint32_t n);
 // The copy of `bytes` host bytes on the current device in `dev` (guarded by
 // mu), uploaded on first use there on an internal stream; `user` is made to
 // wait for the upload until it is known to be complete.
+// counted: whether the copy counts in device_table_bytes().
 int device_copy(std::mutex &mu, std::map<int, DevCopy> &dev, const void *host, size_t bytes, hipStream_t user,
-                const void **out);
+                const void **out, bool counted = true);
 // Same, but returns only once the copy has landed (for plans, graphs and
 // pm_prepare); no stream is made to wait.
 int device_copy_sync(std::mutex &mu, std::map<int, DevCopy> &dev, const void *host, size_t bytes,
-                     const void **out);
+                     const void **out, bool counted = true);
 void free_device_copies(std::map<int, DevCopy> &dev);
 
 // A program plus its per-device copies.  device_ptr() uploads on first use

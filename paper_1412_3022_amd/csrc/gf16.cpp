@@ -430,7 +430,7 @@ std::map<int, DevCopy> &g_tab_dev = *new std::map<int, DevCopy>();
 int table_ptr(hipStream_t user, const uint32_t **out) {
     const std::vector<uint32_t> &t = tables();
     const void *p = nullptr;
-    int st = device_copy(g_tab_mu, g_tab_dev, t.data(), t.size() * sizeof(uint32_t), user, &p);
+    int st = device_copy(g_tab_mu, g_tab_dev, t.data(), t.size() * sizeof(uint32_t), user, &p, false);
     if (st == ST_OK) *out = static_cast<const uint32_t *>(p);
     return st;
 }
@@ -544,7 +544,7 @@ const Mat16 *specific_factor16(Ctx16 &c, const uint32_t *ids, int which) {
 int stage16(Prog16 &p) {
     const std::vector<uint32_t> &t = tables();
     const void *d = nullptr;
-    int st = device_copy_sync(g_tab_mu, g_tab_dev, t.data(), t.size() * sizeof(uint32_t), &d);
+    int st = device_copy_sync(g_tab_mu, g_tab_dev, t.data(), t.size() * sizeof(uint32_t), &d, false);
     if (st == ST_OK) st = device_copy_sync(p.mu, p.dev, p.words.data(), p.words.size() * sizeof(uint32_t), &d);
     std::shared_ptr<BsProgram> bp;
     {

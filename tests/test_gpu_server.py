@@ -58,10 +58,12 @@ def test_served_mix_equals_alone_and_overlaps():
     budget = 32 << 20
     srv = pm.Server(budget, streams=3, max_batch=8)
     try:
+        t0 = pm.table_bytes()
         comps = srv.replay(reqs, arrivals, keep=True)
         torch.cuda.synchronize()
         for q, c in zip(reqs, comps):
-            assert c["status"] == pm.PM_OK
+            assert c["status"] == pm.PM_OK, (q["op"], q["code"].k, q["code"].kind, q["block_bytes"], c["status"],
+                                             t0, pm.table_bytes(), srv.stats())
             s = q["block_bytes"]
             got = _result(c, c["out_blocks"], s)
             want = _alone(q)
