@@ -503,7 +503,7 @@ static int bs_module(BsProgram &bp, BsKind kind, BsModule **out, bool resident_o
             return hip_fail(e);
         }
         hipFunction_t fn = nullptr;
-        if ((e = hipModuleGetFunction(&fn, m->mod, kind == BS_MULTI ? "pmbs_multi" : "pmbs")) != hipSuccess)
+        if ((e = hipModuleGetFunction(&fn, m->mod, bp.fn_name[kind])) != hipSuccess)
             return hip_fail(e);
         int per_cu = 0, ncu = 0;
         if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * kWaves, 0) != hipSuccess ||

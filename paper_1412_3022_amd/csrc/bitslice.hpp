@@ -42,6 +42,7 @@ struct BsProgram {
     int ngroups = 0;
     long est_ops = 0;   // straight-line VALU operations per lane chunk
     uint32_t tile_bytes = 2048;   // bytes of a block per wave tile (4096 for GF(2^16))
+    const char *fn_name[2] = {"pmbs", "pmbs_multi"};   // kernel names, by BsKind
     std::mutex mu;
     BsKernel k[2];      // by BsKind
     ~BsProgram();

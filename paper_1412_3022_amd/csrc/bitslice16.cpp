@@ -283,6 +283,7 @@ std::unique_ptr<BsProgram> bs16_generate(const Mat16 &A) {
     auto bp = std::make_unique<BsProgram>();
     bp->ngroups = static_cast<int>(gs.size());
     bp->tile_bytes = kTile;
+    bp->fn_name[BS_SINGLE] = "pmbs16";
     bp->est_ops = estimate_ops(gs);
     if (bp->est_ops > kBsMaxOps || gs.empty()) return bp;   // left to the table kernel
     std::ostringstream o;
@@ -298,7 +299,7 @@ std::unique_ptr<BsProgram> bs16_generate(const Mat16 &A) {
     // down to 16) is not a multiple of 4096, tile nfull is the window
     // [s16 - 4096, s16) overlapping the one before.  The (s - s16) / 2
     // symbols after s16 are done one per lane by the wave of the last tile.
-    o << "extern \"C\" __global__ __launch_bounds__(" << 64 * kWaves << ") void pmbs(BsArgs a) {\n"
+    o << "extern \"C\" __global__ __launch_bounds__(" << 64 * kWaves << ") void pmbs16(BsArgs a) {\n"
       << "  const u32 wave = threadIdx.x / 64, lane = threadIdx.x % 64;\n"
       << "  const u32 xcd = blockIdx.x % 8u, slot = blockIdx.x / 8u;\n"
       << "  const u32 per = (a.ntiles + 7u) / 8u, t0 = xcd * per;\n"

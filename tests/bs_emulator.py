@@ -67,9 +67,10 @@ def generated_apply_source(A, workdir=None):
     return path
 
 
-def build(source, multi, sanitize=True, tile=2048):
+def build(source, multi, sanitize=True, tile=2048, kernel="pmbs"):
     """Compile one generated source for the host (tile: bytes of a block per
-    wave tile, 4096 for the GF(2^16) kernels); returns the executable."""
+    wave tile, 4096 for the GF(2^16) kernels; kernel: the single-set
+    kernel's name, pmbs16 for GF(2^16)); returns the executable."""
     src = source + (".multi" if multi else "")
     text = open(src).read()
     barrier = 'asm volatile("" : "+s"(ld), "+s"(old));'
@@ -80,7 +81,7 @@ def build(source, multi, sanitize=True, tile=2048):
     with open(cpp, "w") as f:
         f.write('#include "emu_prelude.h"\n' + text + '#include "emu_main.inc"\n')
     exe = src + (".asan" if sanitize else ".plain")
-    cmd = [CLANG, "-O1", "-std=c++17", "-I" + EMU, "-DEMU_KIND=%d" % int(multi), "-DEMU_TILE=%d" % tile, "-Wno-unused-value", cpp, "-o", exe]
+    cmd = [CLANG, "-O1", "-std=c++17", "-I" + EMU, "-DEMU_KIND=%d" % int(multi), "-DEMU_TILE=%d" % tile, "-DEMU_KERNEL=" + kernel, "-Wno-unused-value", cpp, "-o", exe]
     if sanitize:
         cmd[1:1] = ["-g", "-fsanitize=address"]
     subprocess.check_call(cmd)

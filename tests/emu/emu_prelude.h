@@ -36,3 +36,6 @@ static inline unsigned __builtin_amdgcn_perm(unsigned a, unsigned b, unsigned se
 #ifndef EMU_TILE
 #define EMU_TILE 2048
 #endif
+#ifndef EMU_KERNEL
+#define EMU_KERNEL pmbs
+#endif

@@ -58,7 +58,7 @@ def check(src, A, sizes, slots, seed, high_too=True):
     rows, cols = A.shape
     rng = np.random.default_rng(seed)
     runs = [(True, False)] + ([(False, True)] if high_too else [])
-    exes = {h: E.build(src, False, sanitize=san, tile=TILE) for san, h in runs}
+    exes = {h: E.build(src, False, sanitize=san, tile=TILE, kernel="pmbs16") for san, h in runs}
     for i, s in enumerate(sizes):
         X = rng.integers(0, 65536, (cols, s // 2), dtype=np.uint16)
         X[:, -1] = 0xFFFF
