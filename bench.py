@@ -110,6 +110,15 @@ def measured_traffic(kernel, src):
         return None
 
 
+_T0 = time.perf_counter()
+
+
+def progress(msg):
+    """One line on stderr per finished stage (the JSON result is the only
+    stdout line): a long run shows where it is."""
+    print("bench: %s (%.0f s)" % (msg, time.perf_counter() - _T0), file=sys.stderr, flush=True)
+
+
 class Timer:
     """Wall clock plus HIP events on the stream the kernels run on."""
 
@@ -374,6 +383,7 @@ def msr16_decode_case(torch, pm, synth, steps, warmup):
     t0 = time.perf_counter()
     ready = code.prepare(pm.OP_DECODE_SPECIFIC, ids=K)
     out["msr16_specific_init_s"] = time.perf_counter() - t0
+    progress("(16,30,32) specific decode prepared")
     out["msr16_specific_all_passes_bitsliced"] = bool(ready)
     ws_bytes = pm.pm_decode_specific_workspace(code.h, s)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
@@ -562,7 +572,8 @@ def batched_case(torch, pm, synth, steps):
     return res
 
 
-def served_case(torch, pm, synth, nreq=20000, rho=0.8, sequential=True):
+def served_case(torch, pm, synth, nreq=20000, rho=0.8, sequential=True, streams=8, max_batch=128,
+                max_batch_bytes=0):
     """Configuration 5: a Poisson stream of 20 000 requests (70% encode, 20%
     single-node repair, 10% k-subset decode; sizes log-uniform 4 KiB - 64 MiB;
     PM-MSR (4,6), (8,14), (16,30) and PM-MBR (8,14,16)) served under a 64 GB
@@ -593,11 +604,12 @@ def served_case(torch, pm, synth, nreq=20000, rho=0.8, sequential=True):
     with ThreadPoolExecutor(8) as ex:
         list(ex.map(lambda j: j[0].prepare(j[1], failed=j[2], ids=j[3], batched=j[4]), jobs))
     init_s = time.perf_counter() - t0
+    progress("served: init done")
     budget = 64 * 10**9
     # 8 micro-batches in flight of up to 128 requests: on a 3 000-request
     # replay of this mix, 4 x 64 gave 0.54 TB/s, 8 x 64 0.72, 8 x 128 0.81,
     # 12 or 16 streams no more
-    srv = pm.Server(budget, streams=8, max_batch=128, queue_cap=1 << 16)
+    srv = pm.Server(budget, streams=streams, max_batch=max_batch, queue_cap=1 << 16, max_batch_bytes=max_batch_bytes)
 
     def span(comps, nbytes):
         t0 = min(c["t_submit"] for c in comps)
@@ -610,6 +622,7 @@ def served_case(torch, pm, synth, nreq=20000, rho=0.8, sequential=True):
     srv.replay(sat, [0] * len(sat))
     torch.cuda.synchronize()
     capacity = span(srv.replay(sat, [0] * len(sat)), sat_bytes)
+    progress("served: capacity %.0f GB/s" % capacity)
     mean_bytes = float(np.mean(sat_bytes))
     rate = rho * capacity * 1e9 / mean_bytes
     reqs, arrivals, nbytes = wl.requests(nreq, rate_per_s=rate)
@@ -759,24 +772,33 @@ def main():
                              sweep=args.sweep)
     extra = {"headline_kernel_us": round(head["kernel_us"], 3), "headline_variant": head["variant"],
              "headline_event_gbps": round(S / (head["kernel_us"] * 1e-6) / 1e9, 2)}
+    progress("headline encode done")
     if not args.no_extra:
         for name, r in dense_config2(torch, pm, synth, S, args.steps, args.warmup).items():
             extra[name + "_encode_gbps"] = round(r["gbps"], 2)
             extra[name + "_variant"] = r["variant"]
-        extra.update({k: (round(v, 2) if isinstance(v, float) else v)
-                      for k, v in msr_repair_decode(torch, pm, synth, args.steps, args.warmup).items()})
-        extra.update({k: (round(v, 2) if isinstance(v, float) else v)
-                      for k, v in mbr_cases(torch, pm, synth, args.steps, args.warmup).items()})
-        extra.update({k: (round(v, 2) if isinstance(v, float) else v)
-                      for k, v in msr16_decode_case(torch, pm, synth, args.steps, args.warmup).items()})
+        progress("dense encodes done")
+        for fn, digits in ((msr_repair_decode, 2), (mbr_cases, 2), (msr16_decode_case, 2)):
+            extra.update({k: (round(v, digits) if isinstance(v, float) else v)
+                          for k, v in fn(torch, pm, synth, args.steps, args.warmup).items()})
+            progress(fn.__name__ + " done")
         extra.update({k: (round(v, 3) if isinstance(v, float) else v)
                       for k, v in gpu_init_case(torch, pm, synth).items()})
+        progress("GPU-side init done")
         extra.update({k: (round(v, 2) if isinstance(v, float) else v)
                       for k, v in gf16_cases(torch, pm, synth, args.steps, args.warmup).items()})
+        progress("GF(2^16) cases done")
     batched = served = None
     if not args.no_batch:
         batched = batched_case(torch, pm, synth, max(5, args.steps // 20))
+        progress("batched done")
         served = served_case(torch, pm, synth)
+        progress("served done")
+        # the same mix with micro-batches closed at 64 MiB of results: lower
+        # latency, lower capacity (the server's per-micro-batch host work)
+        served["latency_config"] = served_case(torch, pm, synth, sequential=False, max_batch_bytes=64 << 20)
+        served["latency_config"]["max_batch_bytes"] = 64 << 20
+        progress("served (64 MiB micro-batches) done")
 
     achieved = head["alg_bytes_per_launch"] / (head["kernel_us"] * 1e-6) / 1e9
     kname, ksrc = kernel_name(head["variant"])
@@ -808,6 +830,7 @@ def main():
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(synth)
+        progress("CPU baseline done")
     print(json.dumps(line), flush=True)
 
 

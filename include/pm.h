@@ -453,6 +453,13 @@ typedef struct {
                                       copies of kernel tables (pm_table_bytes);
                                       0 = budget / 32, at least 16 MiB.  The
                                       arena is the rest. */
+    uint64_t max_batch_bytes;   /* result and scratch bytes per micro-batch
+                                   (0 = no limit): admission closes a
+                                   micro-batch before a request would take it
+                                   past this (a micro-batch always takes at
+                                   least one request), so large requests do
+                                   not hold the small ones behind them for
+                                   long */
 } pm_server_cfg;
 
 typedef struct {

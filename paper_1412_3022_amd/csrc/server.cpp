@@ -175,13 +175,19 @@ struct pm_server {
     }
 
     // Reserve arena space for a request's result (and repair scratch).
+    // Arena bytes of a request: its result blocks and, for a repair, the d
+    // received blocks.
+    static uint64_t request_bytes(const Req *q) {
+        const uint64_t ld = (q->r.block_bytes + 15) / 16 * 16;
+        const uint64_t scratch = q->r.op == PM_REQ_REPAIR ? q->main.in_n : 0;
+        return (q->main.out_n + scratch) * ld;
+    }
+
     bool admit(Req *q) {
-        const int op = q->r.op;
         const uint64_t s = q->r.block_bytes;
         const uint64_t ld = (s + 15) / 16 * 16;
         const uint64_t out_blocks = q->main.out_n;
-        const uint64_t scratch = op == PM_REQ_REPAIR ? q->main.in_n : 0;   // d helper blocks
-        q->bytes = (out_blocks + scratch) * ld;
+        q->bytes = request_bytes(q);
         if (!arena.alloc(q->bytes, &q->out_off)) return false;
         q->out_ld = ld;
         q->out_blocks = static_cast<uint32_t>(out_blocks);
@@ -390,12 +396,17 @@ struct pm_server {
                 releases.clear();
                 if (free_slot) {
                     uint32_t items = 0;
+                    uint64_t batch_bytes = 0;
                     while (!pending.empty() && admitted.size() < cfg.max_batch) {
                         Req *q = pending.front();
                         const uint32_t need = q->r.op == PM_REQ_REPAIR ? static_cast<uint32_t>(q->helpers.size()) + 1 : 1;
                         if (items + need > item_cap) break;
+                        if (cfg.max_batch_bytes && !admitted.empty() &&
+                            batch_bytes + request_bytes(q) > cfg.max_batch_bytes)
+                            break;
                         if (!admit(q)) break;   // arrival order: wait for memory
                         items += need;
+                        batch_bytes += q->bytes;
                         pending.pop_front();
                         admitted.push_back(q);
                     }

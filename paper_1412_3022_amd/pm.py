@@ -562,7 +562,8 @@ class pm_completion(ctypes.Structure):
 class pm_server_cfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("streams", ctypes.c_uint32),
                 ("max_batch", ctypes.c_uint32), ("queue_cap", ctypes.c_uint32),
-                ("dwords_per_lane", ctypes.c_uint32), ("table_reserve_bytes", ctypes.c_uint64)]
+                ("dwords_per_lane", ctypes.c_uint32), ("table_reserve_bytes", ctypes.c_uint64),
+                ("max_batch_bytes", ctypes.c_uint64)]
 
 
 class pm_server_stat(ctypes.Structure):
@@ -602,9 +603,10 @@ class Server:
     """Continuous-batching server over the engine (see pm_server_* in pm.h)."""
 
     def __init__(self, hbm_budget_bytes, streams=4, max_batch=64, queue_cap=4096, dwords_per_lane=2,
-                 table_reserve_bytes=0):
+                 table_reserve_bytes=0, max_batch_bytes=0):
         L = _server_sigs()
-        cfg = pm_server_cfg(hbm_budget_bytes, streams, max_batch, queue_cap, dwords_per_lane, table_reserve_bytes)
+        cfg = pm_server_cfg(hbm_budget_bytes, streams, max_batch, queue_cap, dwords_per_lane, table_reserve_bytes,
+                            max_batch_bytes)
         h = ctypes.c_void_p()
         _check(L.pm_server_create(ctypes.byref(cfg), ctypes.byref(h)), "pm_server_create")
         self.h = h.value

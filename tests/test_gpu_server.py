@@ -319,3 +319,31 @@ def test_table_reserve_bounds_kernel_tables():
         assert st["arena_bytes"] + st["table_reserve_bytes"] <= (256 << 20) + reserve
     finally:
         srv.close()
+
+
+def test_max_batch_bytes_closes_micro_batches():
+    """With a byte limit below any request, every micro-batch takes exactly
+    one request; with none, requests share micro-batches.  Results are the
+    same either way."""
+    print("server max_batch_bytes", flush=True)
+    wl = workloads.ServeWorkload(23, device(), 4 << 10, 64 << 10, resident_per_family=1)
+    reqs, arrivals, _ = wl.requests(40, rate_per_s=1e7)
+    outs = {}
+    for cap in (1, 0):
+        srv = pm.Server(256 << 20, streams=2, max_batch=16, max_batch_bytes=cap)
+        try:
+            comps = srv.replay(reqs, [0] * len(reqs), keep=True)
+            torch.cuda.synchronize()
+            assert all(c["status"] == pm.PM_OK for c in comps)
+            outs[cap] = [_result(c, c["out_blocks"], q["block_bytes"]).clone() for q, c in zip(reqs, comps)]
+            for c in comps:
+                srv.release(c["ticket"])
+            st = srv.stats()
+            if cap == 1:
+                assert st["batches"] == len(reqs), st
+            else:
+                assert st["batches"] < len(reqs), st
+        finally:
+            srv.close()
+    for a, b in zip(outs[1], outs[0]):
+        assert torch.equal(a, b)
