@@ -638,6 +638,7 @@ def served_case(torch, pm, synth, nreq=20000, rho=0.8, sequential=True, streams=
            "served_gbps": round(served, 2),
            "p50_us": round(float(np.percentile(lat, 50)), 1), "p99_us": round(float(np.percentile(lat, 99)), 1),
            "max_concurrent_batches": stats["max_concurrent_batches"], "batches": stats["batches"],
+           "launch_host_us_per_batch": round(stats["launch_host_ns"] / max(stats["batches"], 1) / 1e3, 1),
            "failed": stats["failed"], "init_s": round(init_s, 2),
            "arena_high_water_bytes": stats["arena_high_water"], "hbm_budget_bytes": budget,
            "table_bytes_high": stats["table_bytes_high"], "table_reserve_bytes": stats["table_reserve_bytes"],

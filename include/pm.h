@@ -471,6 +471,8 @@ typedef struct {
     uint64_t table_reserve_bytes;
     uint64_t table_bytes_high;         /* most table bytes seen after a micro-batch's
                                           uploads (pm_table_bytes, all codes) */
+    uint64_t launch_host_ns;           /* scheduler time spent packing, uploading
+                                          and enqueuing micro-batches */
 } pm_server_stat;
 
 typedef struct pm_server pm_server;

@@ -147,6 +147,7 @@ struct pm_server {
     uint64_t next_ticket = 1;
     std::atomic<bool> stop{false};
     std::thread sched;
+    uint64_t launch_ns = 0;           // host time in launch(), under mu
     int device = 0;
     // statistics
     uint64_t batches = 0, completed = 0, failed = 0, table_high = 0;
@@ -414,7 +415,9 @@ struct pm_server {
             }
             if (!admitted.empty()) {
                 free_slot->reqs = std::move(admitted);
+                const uint64_t t0 = now_ns();
                 const int st = launch(*free_slot);
+                const uint64_t dt = now_ns() - t0;
                 if (st != ST_OK) {
                     // nothing of this micro-batch is on the GPU any more: its
                     // requests complete now, with the error
@@ -429,6 +432,7 @@ struct pm_server {
                 uint32_t now_busy = 0;
                 for (const Slot &sl : slots) now_busy += sl.busy ? 1u : 0u;
                 std::lock_guard<std::mutex> lk(mu);
+                launch_ns += dt;
                 ++batches;
                 max_busy = std::max(max_busy, now_busy);
                 progressed = true;
@@ -579,6 +583,7 @@ pm_status pm_server_stats(pm_server *s, pm_server_stat *st) {
     st->arena_bytes = s->arena.size;
     st->table_reserve_bytes = s->reserve;
     st->table_bytes_high = s->table_high;
+    st->launch_host_ns = s->launch_ns;
     return static_cast<pm_status>(s->error);
 }
 

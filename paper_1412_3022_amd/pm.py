@@ -571,7 +571,8 @@ class pm_server_stat(ctypes.Structure):
                 ("arena_used", ctypes.c_uint64), ("arena_high_water", ctypes.c_uint64),
                 ("max_concurrent_batches", ctypes.c_uint32), ("pad", ctypes.c_uint32),
                 ("failed", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
-                ("table_reserve_bytes", ctypes.c_uint64), ("table_bytes_high", ctypes.c_uint64)]
+                ("table_reserve_bytes", ctypes.c_uint64), ("table_bytes_high", ctypes.c_uint64),
+                ("launch_host_ns", ctypes.c_uint64)]
 
 
 _server_sigs_done = False
@@ -727,7 +728,7 @@ class Server:
         return dict(completed=s.completed, batches=s.batches, pending=s.pending, arena_used=s.arena_used,
                     arena_high_water=s.arena_high_water, max_concurrent_batches=s.max_concurrent_batches,
                     failed=s.failed, arena_bytes=s.arena_bytes, table_reserve_bytes=s.table_reserve_bytes,
-                    table_bytes_high=s.table_bytes_high)
+                    table_bytes_high=s.table_bytes_high, launch_host_ns=s.launch_host_ns)
 
 
 _hip = None
