@@ -76,6 +76,49 @@ struct Grp {
 
 int popc(unsigned m) { return __builtin_popcount(m); }
 
+// Load order of each table group's columns.  The groups of a tile run on one
+// XCD at about the same pace, so a column that several groups read is given
+// the same load step in all of them: the first fetch brings it into L2 and
+// the others hit there instead of reading it from HBM again.  Greedy, columns
+// read by most groups first, each at the first step free in all its groups;
+// a group then loads its columns in step order (coefficients permuted along).
+void order_columns(std::vector<Grp> &gs) {
+    std::map<uint32_t, std::vector<size_t>> users;
+    for (size_t g = 0; g < gs.size(); ++g)
+        for (uint32_t c : gs[g].cols) users[c].push_back(g);
+    std::vector<uint32_t> cols;
+    for (auto &kv : users) cols.push_back(kv.first);
+    std::stable_sort(cols.begin(), cols.end(),
+                     [&](uint32_t a, uint32_t b) { return users[a].size() > users[b].size(); });
+    std::vector<std::set<int>> taken(gs.size());
+    std::map<uint32_t, int> step;
+    for (uint32_t c : cols) {
+        int s = 0;
+        for (;; ++s) {
+            bool free = true;
+            for (size_t g : users[c]) free &= !taken[g].count(s);
+            if (free) break;
+        }
+        step[c] = s;
+        for (size_t g : users[c]) taken[g].insert(s);
+    }
+    for (Grp &g : gs) {
+        std::vector<size_t> idx(g.cols.size());
+        for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+        std::stable_sort(idx.begin(), idx.end(),
+                         [&](size_t a, size_t b) { return step[g.cols[a]] < step[g.cols[b]]; });
+        Grp h;
+        h.rows = g.rows;
+        for (size_t i : idx) h.cols.push_back(g.cols[i]);
+        for (auto &row : g.coef) {
+            std::vector<uint16_t> v;
+            for (size_t i : idx) v.push_back(row[i]);
+            h.coef.push_back(std::move(v));
+        }
+        g = std::move(h);
+    }
+}
+
 std::vector<Grp> make_groups(const Mat16 &A) {
     std::vector<std::vector<int>> sup(A.rows);
     std::vector<int> order, copies;
@@ -104,6 +147,7 @@ std::vector<Grp> make_groups(const Mat16 &A) {
         }
         gs.push_back(std::move(g));
     }
+    order_columns(gs);
     for (size_t i = 0; i < copies.size(); i += kCopyRows) {
         Grp g;
         g.copy = true;

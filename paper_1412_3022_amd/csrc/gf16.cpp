@@ -3,7 +3,9 @@
 #include "gf16.hpp"
 
 #include <algorithm>
+#include <map>
 #include <numeric>
+#include <set>
 
 #include "gf16k.hpp"
 
@@ -339,7 +341,7 @@ int specific_factors(const Code16 &c, const std::vector<int> &K, Mat16 F[kSpecif
 // Rows that are one input block times 1 (a decode's blocks that the nodes
 // hold as they are: only the lost blocks are computed) form copy groups.
 // The other rows form groups of kPm16Rows, each with the columns any of its
-// rows reads, in increasing order.  Rows are taken in the order of their
+// rows reads (in the load order given below).  Rows are taken in the order of their
 // supports (the sorted lists of columns they read), so rows that read the
 // same columns share a group and its column records: in the linearized
 // generator, the rows alpha i + j of all nodes i read the message symbols of
@@ -371,13 +373,46 @@ Prog16::Prog16(const Mat16 &A_) : rows(A_.rows), cols(A_.cols), A(A_) {
     ngroups = ntable + ncopy;
     words.assign(kPm16Header + static_cast<size_t>(ngroups) * (2 + R), 0);
     words[0] = ngroups;
-    std::vector<int> cols_of;
+    std::vector<std::vector<int>> gcols(ntable);
     for (uint32_t g = 0; g < ntable; ++g) {
         const int i0 = static_cast<int>(g) * R, i1 = std::min(nt, i0 + R);
-        cols_of.clear();
+        std::vector<int> &cols_of = gcols[g];
         for (int i = i0; i < i1; ++i) cols_of.insert(cols_of.end(), sup[order[i]].begin(), sup[order[i]].end());
         std::sort(cols_of.begin(), cols_of.end());
         cols_of.erase(std::unique(cols_of.begin(), cols_of.end()), cols_of.end());
+    }
+    // A column that several groups read gets one position in all of their
+    // record lists where it can (greedy, columns read by most groups first,
+    // each at the first position free in all its groups; a group then reads
+    // its columns in that order).  The groups of a tile run side by side on
+    // one XCD, so the first read brings the column's tile into L2 and the
+    // others find it there.
+    {
+        std::map<int, std::vector<uint32_t>> users;
+        for (uint32_t g = 0; g < ntable; ++g)
+            for (int c : gcols[g]) users[c].push_back(g);
+        std::vector<int> byuse;
+        for (auto &kv : users) byuse.push_back(kv.first);
+        std::stable_sort(byuse.begin(), byuse.end(),
+                         [&](int a, int b) { return users[a].size() > users[b].size(); });
+        std::vector<std::set<int>> taken(ntable);
+        std::map<int, int> step;
+        for (int c : byuse) {
+            int st = 0;
+            for (;; ++st) {
+                bool free = true;
+                for (uint32_t g : users[c]) free &= !taken[g].count(st);
+                if (free) break;
+            }
+            step[c] = st;
+            for (uint32_t g : users[c]) taken[g].insert(st);
+        }
+        for (auto &cl : gcols)
+            std::stable_sort(cl.begin(), cl.end(), [&](int a, int b) { return step[a] < step[b]; });
+    }
+    for (uint32_t g = 0; g < ntable; ++g) {
+        const int i0 = static_cast<int>(g) * R, i1 = std::min(nt, i0 + R);
+        const std::vector<int> &cols_of = gcols[g];
         const size_t first = words.size();
         for (int c : cols_of) {
             words.push_back(static_cast<uint32_t>(c));
