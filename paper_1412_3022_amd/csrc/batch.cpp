@@ -241,6 +241,8 @@ pm_status pm_batch_plan(const pm_batch_item *items, size_t n, uint32_t flags, pm
         b->d_counters = nullptr;
         return static_cast<pm_status>(hip_fail(e));
     }
+    // the work-list kernels leave their counters at zero: only the first launch needs this
+    if ((e = hipMemset(b->d_counters, 0, cbytes)) != hipSuccess) return static_cast<pm_status>(hip_fail(e));
     *out = b.release();
     return PM_OK;
 }

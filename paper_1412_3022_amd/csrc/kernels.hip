@@ -454,14 +454,11 @@ struct BatchItem {
 struct BatchArgs {
     const BatchItem *items;
     uint32_t nitems, nunits;
-    uint32_t *counters;   // 8 queue heads, 64 bytes apart
+    uint32_t *counters;   // 8 queue heads, 64 bytes apart, and the finished-wave count
 };
 
 constexpr uint32_t kCounterStride = 16;
-
-__global__ void pm_batch_reset(uint32_t *counters) {
-    if (threadIdx.x < 8) counters[threadIdx.x * kCounterStride] = 0u;
-}
+constexpr uint32_t kDoneWord = 8;   // waves of the launch that have left the queues
 
 template <int RG, int VEC>
 __global__ __launch_bounds__(kThreads) void pm_batch_kernel(BatchArgs a) {
@@ -526,6 +523,18 @@ __global__ __launch_bounds__(kThreads) void pm_batch_kernel(BatchArgs a) {
             } else {
                 copy_rows<VEC, false>(cols, rows, g[1], in, in_ld, out, out_ld, off, avail);
             }
+        }
+    }
+    // The counters start every launch at zero: the last wave to leave the
+    // queues resets them, so no reset launch precedes each batch kernel.
+    // Every other wave's last queue-head update has returned (the loop
+    // read its value) before that wave's own count is added.  No fence: an
+    // agent-scope release would write back the XCD's L2 for every wave.
+    if (lane == 0) {
+        const uint32_t waves = gridDim.x * (blockDim.x / 64u);
+        if (atomicAdd(a.counters + kDoneWord, 1u) == waves - 1u) {
+            for (uint32_t x = 0; x < 8u; ++x) atomicExch(a.counters + x * kCounterStride, 0u);
+            atomicExch(a.counters + kDoneWord, 0u);
         }
     }
 }
@@ -600,7 +609,8 @@ static hipError_t launch_apply(const PmkApply &h, hipStream_t st) {
 struct PmkBatch {
     const void *items;     // device BatchItem array
     uint32_t nitems, nunits;
-    uint32_t *counters;    // device, 8 * 16 words
+    uint32_t *counters;    // device, 8 * 16 words, zero before the first launch on them (each
+                           // launch leaves them at zero)
 };
 
 extern "C" int pmk_batch_item_bytes() { return static_cast<int>(sizeof(BatchItem)); }
@@ -615,7 +625,6 @@ static hipError_t launch_batch(const PmkBatch &h, hipStream_t st) {
     const uint64_t resident = static_cast<uint64_t>(per_cu) * static_cast<uint64_t>(ncu);
     uint64_t grid = waves < resident ? waves : resident;
     grid = (grid + 7) / 8 * 8;
-    hipLaunchKernelGGL(pm_batch_reset, dim3(1), dim3(64), 0, st, h.counters);
     BatchArgs a{static_cast<const BatchItem *>(h.items), h.nitems, h.nunits, h.counters};
     hipLaunchKernelGGL((pm_batch_kernel<RG, VEC>), dim3(static_cast<uint32_t>(grid)), dim3(kThreads), 0, st, a);
     return hipGetLastError();

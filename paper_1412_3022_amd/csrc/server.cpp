@@ -483,7 +483,9 @@ pm_status pm_server_create(const pm_server_cfg *cfg, pm_server **out) {
                 hipSuccess ||
             (e = hipMalloc(reinterpret_cast<void **>(&sl.d_bs), s->item_cap * sizeof(BsItem))) != hipSuccess ||
             (e = hipMalloc(reinterpret_cast<void **>(&sl.d_counters),
-                           kPhases * kClasses * 8 * 16 * sizeof(uint32_t))) != hipSuccess)
+                           kPhases * kClasses * 8 * 16 * sizeof(uint32_t))) != hipSuccess ||
+            // the work-list kernels leave their counters at zero: only the first launch needs this
+            (e = hipMemset(sl.d_counters, 0, kPhases * kClasses * 8 * 16 * sizeof(uint32_t))) != hipSuccess)
             return static_cast<pm_status>(hip_fail(e));
     }
     pm_server *raw = s.get();
