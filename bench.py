@@ -424,8 +424,10 @@ def gf16_cases(torch, pm, synth, steps, warmup):
     node set (its held blocks copied), and at k = 40 and 64 the specific
     decode (and at k = 40 the linearized one) from the last k nodes: on the
     generated bit-sliced kernels where the matrix is under their size limit
-    (the *_bitsliced fields), else the GF(2^16) table kernel.  GB/s of source
-    bytes (node bytes for repair and decode); init times in seconds."""
+    (the *_bitsliced fields; past one kernel's size and within four, as
+    several kernels compiled side by side: the k = 16 encode and the k = 8
+    decode from the parity nodes), else the GF(2^16) table kernel.  GB/s of
+    source bytes (node bytes for repair and decode); init times in seconds."""
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream().cuda_stream
     S = 64 << 20
@@ -447,7 +449,10 @@ def gf16_cases(torch, pm, synth, steps, warmup):
         xs = [synth.random_bytes_torch(0x1600 + k + j, code.B * s, dev).view(code.B, s) for j in range(NBUF)]
         outs = [torch.empty((code.enc_rows, s), dtype=torch.uint8, device=dev) for _ in range(NBUF)]
         key = "gf16_k%d_%s_encode" % (k, "sys" if sys_ else "nonsys")
+        t0 = time.time()
         out[key + "_bitsliced"] = code.prepare(pm.OP_ENCODE)
+        out[key + "_init_s"] = time.time() - t0   # generation and hipRTC compile of the bit-sliced kernel
+        progress("GF(2^16) k=%d encode prepared" % k)
         timed(lambda i: pm.pm_encode(code.h, xs[i % NBUF].data_ptr(), s, outs[i % NBUF].data_ptr(), s, s, stream),
               code.B * s, code.B, code.enc_rows, s, key)
         if k == 8:
@@ -459,6 +464,7 @@ def gf16_cases(torch, pm, synth, steps, warmup):
             code.prepare(pm.OP_HELPER, failed=f)
             out["gf16_k8_newcomer_bitsliced"] = code.prepare(pm.OP_NEWCOMER, failed=f, ids=H)
             out["gf16_k8_decode_bitsliced"] = code.prepare(pm.OP_DECODE, ids=K)
+            progress("GF(2^16) k=8 repair and decodes prepared")
             timed(lambda i: pm.pm_repair_helper(code.h, f, node.data_ptr(), s, recv.data_ptr(), s, stream),
                   code.alpha * s, code.alpha, 1, s, "gf16_k8_helper")
             timed(lambda i: pm.pm_repair_newcomer(code.h, f, H, recv.data_ptr(), s, rep_out.data_ptr(), s, s,

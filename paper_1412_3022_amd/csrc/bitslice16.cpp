@@ -162,13 +162,15 @@ std::vector<Grp> make_groups(const Mat16 &A) {
 
 // Operations per lane chunk of 32 symbols: per column its permutes and
 // transposes, combinations and two XORs per row plane; per row the output.
+long group_ops(const Grp &g) {
+    if (g.copy) return 0;
+    return static_cast<long>(g.cols.size()) * (16 + 72 + 44 + 32 * static_cast<long>(g.rows.size())) +
+           static_cast<long>(g.rows.size()) * (72 + 16);
+}
+
 long estimate_ops(const std::vector<Grp> &gs) {
     long ops = 0;
-    for (const Grp &g : gs) {
-        if (g.copy) continue;
-        ops += static_cast<long>(g.cols.size()) * (16 + 72 + 44 + 32 * static_cast<long>(g.rows.size()));
-        ops += static_cast<long>(g.rows.size()) * (72 + 16);
-    }
+    for (const Grp &g : gs) ops += group_ops(g);
     return ops;
 }
 
@@ -322,14 +324,11 @@ void emit_tail(std::ostringstream &o, int gi, const Grp &G) {
 
 }  // namespace
 
-std::unique_ptr<BsProgram> bs16_generate(const Mat16 &A) {
-    std::vector<Grp> gs = make_groups(A);
-    auto bp = std::make_unique<BsProgram>();
-    bp->ngroups = static_cast<int>(gs.size());
-    bp->tile_bytes = kTile;
-    bp->fn_name[BS_SINGLE] = "pmbs16";
-    bp->est_ops = estimate_ops(gs);
-    if (bp->est_ops > kBsMaxOps || gs.empty()) return bp;   // left to the table kernel
+namespace {
+
+// The kernel source over the row groups gs (their functions, byte tails and
+// the tile loop).
+std::string emit_source(const std::vector<Grp> &gs) {
     std::ostringstream o;
     // x^16 reduced: x^12 + x^3 + x + 1
     o << "#define POLY16 " << mul(0x8000, 2) << "u\n" << kPrelude16;
@@ -338,7 +337,7 @@ std::unique_ptr<BsProgram> bs16_generate(const Mat16 &A) {
         else emit_table_group(o, static_cast<int>(g), gs[g]);
         emit_tail(o, static_cast<int>(g), gs[g]);
     }
-    const int G = bp->ngroups;
+    const int G = static_cast<int>(gs.size());
     // Tiles 0 .. nfull-1 are the full 4096-byte tiles; when s16 (s rounded
     // down to 16) is not a multiple of 4096, tile nfull is the window
     // [s16 - 4096, s16) overlapping the one before.  The (s - s16) / 2
@@ -361,13 +360,63 @@ std::unique_ptr<BsProgram> bs16_generate(const Mat16 &A) {
     for (int g = 0; g < G; ++g)
         o << "          case " << g << ": b" << g << "(a.in, a.ld, a.out, a.old, s16 + 2u * lane); break;\n";
     o << "        }\n      }\n    }\n    if (a.P >= G) break;\n  }\n}\n";
-    bp->k[BS_SINGLE].source = o.str();
-    if (const char *dump = getenv("PMRC_BS_DUMP")) {   // debugging aid: keep the generated source
-        if (FILE *f = fopen(dump, "w")) {
-            fputs(bp->k[BS_SINGLE].source.c_str(), f);
-            fclose(f);
+    return o.str();
+}
+
+std::unique_ptr<BsProgram> make_part(std::vector<Grp> gs) {
+    auto bp = std::make_unique<BsProgram>();
+    bp->ngroups = static_cast<int>(gs.size());
+    bp->tile_bytes = kTile;
+    bp->fn_name[BS_SINGLE] = "pmbs16";
+    bp->est_ops = estimate_ops(gs);
+    bp->k[BS_SINGLE].source = emit_source(gs);
+    return bp;
+}
+
+}  // namespace
+
+std::vector<std::unique_ptr<BsProgram>> bs16_generate_parts(const Mat16 &A) {
+    std::vector<Grp> gs = make_groups(A);
+    const long est = estimate_ops(gs);
+    std::vector<std::unique_ptr<BsProgram>> parts;
+    if (gs.empty() || est > kBs16MaxParts * kBs16PartOps) return parts;   // left to the table kernel
+    // consecutive groups (rows in support order, so groups that read the
+    // same columns stay in one part) of about est / np operations each
+    const long np = est <= kBsMaxOps ? 1 : kBs16MaxParts;
+    std::vector<Grp> cur;
+    long done = 0;
+    for (size_t g = 0; g < gs.size(); ++g) {
+        done += group_ops(gs[g]);
+        cur.push_back(std::move(gs[g]));
+        const long cut = est * (static_cast<long>(parts.size()) + 1) / np;
+        if (static_cast<long>(parts.size()) + 1 < np && done >= cut) {
+            parts.push_back(make_part(std::move(cur)));
+            cur.clear();
         }
     }
+    if (!cur.empty()) parts.push_back(make_part(std::move(cur)));
+    if (const char *dump = getenv("PMRC_BS_DUMP")) {   // debugging aid: keep the generated sources
+        for (size_t i = 0; i < parts.size(); ++i) {
+            const std::string path = parts.size() == 1 ? std::string(dump) : std::string(dump) + ".part" + std::to_string(i);
+            if (FILE *f = fopen(path.c_str(), "w")) {
+                fputs(parts[i]->k[BS_SINGLE].source.c_str(), f);
+                fclose(f);
+            }
+        }
+    }
+    return parts;
+}
+
+std::unique_ptr<BsProgram> bs16_generate(const Mat16 &A) {
+    std::vector<std::unique_ptr<BsProgram>> parts = bs16_generate_parts(A);
+    if (parts.size() == 1) return std::move(parts[0]);
+    // no single kernel: the whole matrix's group count and size, no source
+    std::vector<Grp> gs = make_groups(A);
+    auto bp = std::make_unique<BsProgram>();
+    bp->ngroups = static_cast<int>(gs.size());
+    bp->tile_bytes = kTile;
+    bp->fn_name[BS_SINGLE] = "pmbs16";
+    bp->est_ops = estimate_ops(gs);
     return bp;
 }
 

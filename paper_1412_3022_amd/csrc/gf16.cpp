@@ -6,6 +6,8 @@
 #include <map>
 #include <numeric>
 #include <set>
+#include <string>
+#include <thread>
 
 #include "gf16k.hpp"
 
@@ -347,12 +349,13 @@ int specific_factors(const Code16 &c, const std::vector<int> &K, Mat16 F[kSpecif
 // generator, the rows alpha i + j of all nodes i read the message symbols of
 // column j of M.  This cuts the records of the k = 8 systematic encode from
 // 392 to 98, and of the k = 64 non-systematic one from 487 760 to 75 612.
-std::shared_ptr<BsProgram> Prog16::bitslice() {
+std::vector<std::shared_ptr<BsProgram>> Prog16::bitslice() {
     std::lock_guard<std::mutex> lk(mu);
     if (!bs_tried) {
         bs_tried = true;
-        std::unique_ptr<BsProgram> b = bs16_generate(A);
-        if (b->est_ops <= kBsMaxOps && b->ngroups > 0) bs = std::move(b);
+        std::vector<std::unique_ptr<BsProgram>> parts = bs16_generate_parts(A);
+        if (static_cast<int>(parts.size()) <= max_parts)
+            for (std::unique_ptr<BsProgram> &b : parts) bs.push_back(std::move(b));
     }
     return bs;
 }
@@ -557,7 +560,12 @@ int resolve_specific16(Ctx16 &c, const uint32_t *ids, Prog16 *pe[kSpecificPasses
         Ctx16::Specific sp;
         for (int p = 0; p < kSpecificPasses; ++p) {
             sp.F[p] = std::move(F[p]);
-            if (sp.F[p].rows) sp.prog[p] = std::make_unique<Prog16>(sp.F[p]);
+            if (sp.F[p].rows) {
+                sp.prog[p] = std::make_unique<Prog16>(sp.F[p]);
+                // one kernel at most: split kernels would cost minutes of
+                // init per node set for passes that are short already
+                sp.prog[p]->max_parts = 1;
+            }
         }
         it = c.specific.emplace(list, std::move(sp)).first;
     }
@@ -576,27 +584,98 @@ const Mat16 *specific_factor16(Ctx16 &c, const uint32_t *ids, int which) {
     return it == c.specific.end() ? nullptr : &it->second.F[which];
 }
 
+namespace {
+
+// Side streams of the split kernels on one device, with the events that
+// fork them from the caller's stream and join them back.
+struct SideStreams {
+    hipStream_t st[kBs16MaxParts - 1] = {};
+    hipEvent_t fork = nullptr, join[kBs16MaxParts - 1] = {};
+};
+std::mutex g_side_mu;   // guards g_side and every fork / join sequence
+std::map<int, SideStreams> &g_side = *new std::map<int, SideStreams>();   // kept to process exit
+
+// The parts of a split kernel write disjoint rows from the same inputs, and
+// each alone fills only part of the GPU (its row groups times the tiles), so
+// they run side by side: part 0 on the caller's stream, the others on side
+// streams that wait for everything the caller enqueued before, and the
+// caller's stream then waits for them.  The enqueue sequence holds a lock,
+// so concurrent calls never interleave their records and waits of the
+// shared events.
+int launch_parts(const std::vector<std::shared_ptr<BsProgram>> &parts, const uint8_t *in, size_t in_ld,
+                 uint8_t *out, size_t out_ld, size_t s, hipStream_t stream) {
+    if (parts.size() == 1) return bs_launch(*parts[0], in, in_ld, out, out_ld, s, stream);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e);
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    SideStreams &sd = g_side[dev];
+    if (!sd.fork) {
+        if ((e = hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming)) != hipSuccess) {
+            sd.fork = nullptr;
+            return hip_fail(e);
+        }
+        for (int i = 0; i < kBs16MaxParts - 1; ++i)
+            if ((e = hipStreamCreateWithFlags(&sd.st[i], hipStreamNonBlocking)) != hipSuccess ||
+                (e = hipEventCreateWithFlags(&sd.join[i], hipEventDisableTiming)) != hipSuccess)
+                return hip_fail(e);
+    }
+    if ((e = hipEventRecord(sd.fork, stream)) != hipSuccess) return hip_fail(e);
+    int st = ST_OK;
+    for (size_t i = 1; i < parts.size() && st == ST_OK; ++i) {
+        hipStream_t side = sd.st[i - 1];
+        if ((e = hipStreamWaitEvent(side, sd.fork, 0)) != hipSuccess) return hip_fail(e);
+        st = bs_launch(*parts[i], in, in_ld, out, out_ld, s, side);
+        if ((e = hipEventRecord(sd.join[i - 1], side)) != hipSuccess) return hip_fail(e);
+    }
+    if (st == ST_OK) st = bs_launch(*parts[0], in, in_ld, out, out_ld, s, stream);
+    // the caller's stream waits for every side stream that was forked,
+    // also when a launch failed
+    for (size_t i = 1; i < parts.size(); ++i)
+        if ((e = hipStreamWaitEvent(stream, sd.join[i - 1], 0)) != hipSuccess) return hip_fail(e);
+    return st;
+}
+
+}  // namespace
+
 int stage16(Prog16 &p) {
     const std::vector<uint32_t> &t = tables();
     const void *d = nullptr;
     int st = device_copy_sync(g_tab_mu, g_tab_dev, t.data(), t.size() * sizeof(uint32_t), &d, false);
     if (st == ST_OK) st = device_copy_sync(p.mu, p.dev, p.words.data(), p.words.size() * sizeof(uint32_t), &d);
-    std::shared_ptr<BsProgram> bp;
+    std::vector<std::shared_ptr<BsProgram>> parts;
     {
         std::lock_guard<std::mutex> lk(p.mu);
-        bp = p.bs;
+        parts = p.bs;
     }
-    if (st == ST_OK && bp && bs_ready(*bp, BS_SINGLE)) st = bs_load(*bp, BS_SINGLE);
+    for (const std::shared_ptr<BsProgram> &bp : parts)
+        if (st == ST_OK && bs_ready(*bp, BS_SINGLE)) st = bs_load(*bp, BS_SINGLE);
     return st;
 }
 
 int compile16(Prog16 &p, int *specialized) {
-    std::shared_ptr<BsProgram> bp = p.bitslice();
+    std::vector<std::shared_ptr<BsProgram>> parts = p.bitslice();
     if (specialized) *specialized = 0;
-    if (!bp) return ST_OK;
-    int st = bs_compile(*bp, BS_SINGLE);
-    if (st == ST_OK && specialized) *specialized = 1;
-    return st;
+    if (parts.empty()) return ST_OK;
+    // the parts compile side by side (hipRTC runs on the calling threads;
+    // every thread is joined before this returns)
+    std::vector<int> st(parts.size(), ST_OK);
+    std::vector<std::string> msg(parts.size());
+    std::vector<std::thread> th;
+    for (size_t i = 1; i < parts.size(); ++i)
+        th.emplace_back([&, i] {
+            st[i] = bs_compile(*parts[i], BS_SINGLE);
+            if (st[i] != ST_OK) msg[i] = g_hip_msg;
+        });
+    st[0] = bs_compile(*parts[0], BS_SINGLE);
+    for (std::thread &t : th) t.join();
+    for (size_t i = 0; i < parts.size(); ++i)
+        if (st[i] != ST_OK) {
+            if (i) g_hip_msg = msg[i];
+            return st[i];
+        }
+    if (specialized) *specialized = 1;
+    return ST_OK;
 }
 
 int launch16(Prog16 &p, const uint8_t *in, size_t in_ld, size_t in_n, uint8_t *out, size_t out_ld, size_t out_n,
@@ -608,13 +687,15 @@ int launch16(Prog16 &p, const uint8_t *in, size_t in_ld, size_t in_n, uint8_t *o
     if (overlaps(in, in_ld, in_n, out, out_ld, out_n, s)) return ST_EINVAL;
     if (p.ngroups == 0) return ST_OK;
     // the bit-sliced kernel once compiled (init phase), for blocks of at
-    // least one of its tiles
-    std::shared_ptr<BsProgram> bp;
+    // least one of its tiles (its parts side by side)
+    std::vector<std::shared_ptr<BsProgram>> parts;
     {
         std::lock_guard<std::mutex> lk(p.mu);
-        bp = p.bs;
+        parts = p.bs;
     }
-    if (bp && bs_ready(*bp, BS_SINGLE) && s >= bp->tile_bytes) return bs_launch(*bp, in, in_ld, out, out_ld, s, stream);
+    bool ready = !parts.empty() && s >= parts[0]->tile_bytes;
+    for (const std::shared_ptr<BsProgram> &bp : parts) ready = ready && bs_ready(*bp, BS_SINGLE);
+    if (ready) return launch_parts(parts, in, in_ld, out, out_ld, s, stream);
     const uint64_t ntiles = (s + kPm16TileBytes - 1) / kPm16TileBytes;
     // tile numbers are 32-bit and the grid holds at most 2^31 - 1 work-groups of 4 items
     if (ntiles > 0xFFFFFFFFull || ntiles * p.ngroups > 0x1FFFFFFFCull) return ST_EINVAL;

@@ -51,6 +51,14 @@ Mat16 helper_row(const Code16 &c, int failed);
 int newcomer_matrix(const Code16 &c, int failed, const std::vector<int> &helpers, Mat16 &R);
 int decode_matrix(const Code16 &c, const std::vector<int> &nodes, Mat16 &D);
 
+// A GF(2^16) matrix past one bit-sliced kernel's limit (kBsMaxOps) and
+// within kBs16MaxParts kernels of at most kBs16PartOps operations is split
+// into that many kernels (parts).  They compile side by side, and a data
+// call runs them side by side on two hardware queues: more parts would share
+// the process's few queues, and each part alone fills only part of the GPU.
+constexpr long kBs16MaxParts = 2;
+constexpr long kBs16PartOps = 256000;
+
 // A matrix packed for the kernel, with its per-device copies, and its
 // bit-sliced specialization (bitslice16.cpp) when it is small enough.
 struct Prog16 {
@@ -61,17 +69,23 @@ struct Prog16 {
     std::mutex mu;
     std::map<int, DevCopy> dev;
     bool bs_tried = false;
-    std::shared_ptr<BsProgram> bs;
+    int max_parts = static_cast<int>(kBs16MaxParts);   // more parts than this: the table kernel
+    std::vector<std::shared_ptr<BsProgram>> bs;   // the bit-sliced kernel's parts
     explicit Prog16(const Mat16 &A);
     ~Prog16() { free_device_copies(dev); }
-    // The bit-sliced kernel's source, generated on first use (nullptr when
-    // the matrix is over the size limit).
-    std::shared_ptr<BsProgram> bitslice();
+    // The bit-sliced kernel's parts, generated on first use (none when the
+    // matrix is over the size limit).
+    std::vector<std::shared_ptr<BsProgram>> bitslice();
 };
 
 // Straight-line bit-sliced kernel source for a GF(2^16) matrix (not
 // compiled); est_ops over kBsMaxOps means no source.
 std::unique_ptr<BsProgram> bs16_generate(const Mat16 &A);
+// The bit-sliced form as kernels over consecutive row groups of about equal
+// size: one when the matrix is within kBsMaxOps, kBs16MaxParts up to
+// kBs16MaxParts x kBs16PartOps operations, none past that (the table kernel
+// runs).
+std::vector<std::unique_ptr<BsProgram>> bs16_generate_parts(const Mat16 &A);
 
 // The specific PM-MSR decode from the k nodes K as five factors (the
 // GF(2^16) counterpart of specific_decode_factors; F[4] empty for a

@@ -138,6 +138,58 @@ def test_over_the_size_limit_is_left_to_the_table_kernel(gen, tmp_path):
     assert src is None and G == 30
 
 
+def _part_rows(path):
+    """Output rows a generated kernel writes: its groups' row tables."""
+    rows = []
+    for line in open(path):
+        if line.startswith("__constant__ u32 tr"):
+            rows += [int(v.rstrip("u")) for v in line.split("{")[1].split("}")[0].split(", ")]
+    return rows
+
+
+@pytest.mark.parametrize("name", ["k16_encode", "k8_parity_decode"])
+def test_matrices_over_one_kernel_are_split_into_parts(gen, tmp_path, name):
+    """The k = 16 systematic encode (240 x 240, about 490 000 operations) and
+    the k = 8 decode from the 8 parity nodes (56 x 56 dense, about 210 000)
+    are past one kernel's operation limit (160 000) and within two parts of
+    at most 256 000: each is generated as 2 kernels over consecutive row
+    groups of about equal size, which together write every row exactly once.
+    (Each part is the same generator's code; the parts run on the GPU in the
+    parity tests, against the oracle.)"""
+    A = F.Code(16, 32).enc if name == "k16_encode" else F.Code(8, 16).decode_matrix(list(range(8, 16)))
+    A = np.ascontiguousarray(A, np.uint16)
+    path = str(tmp_path / name)
+    mfile = path + ".mat"
+    with open(mfile, "wb") as f:
+        f.write(struct.pack("<2I", *A.shape))
+        f.write(A.tobytes())
+    assert subprocess.run([gen, mfile, path], capture_output=True).returncode == 3   # no single kernel
+    r = subprocess.run([gen, mfile, path, "parts"], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    lines = r.stdout.split("\n")
+    nparts = int(lines[0])
+    assert nparts == 2
+    rows = []
+    for i in range(nparts):
+        groups, ops = map(int, lines[1 + i].split())
+        assert groups > 0 and ops <= 256000, (i, ops)
+        rows += _part_rows(path + ".part%d" % i)
+    assert sorted(rows) == list(range(A.shape[0]))
+
+
+def test_past_the_parts_limit_there_are_none(gen, tmp_path):
+    """A dense 120 x 120 matrix (about 950 000 operations) is past two
+    parts too: no bit-sliced form at all."""
+    rng = np.random.default_rng(3)
+    A = np.ascontiguousarray(_random(rng, 120, 120, 1.0), np.uint16)
+    path = str(tmp_path / "big")
+    with open(path + ".mat", "wb") as f:
+        f.write(struct.pack("<2I", *A.shape))
+        f.write(A.tobytes())
+    r = subprocess.run([gen, path + ".mat", path, "parts"], capture_output=True, text=True)
+    assert r.returncode == 3 and r.stdout.split()[0] == "0"
+
+
 def test_prepare_compiles_the_generated_program(gen, tmp_path):
     """A GF(2^16) code's prepare call generates the same source for its
     encode matrix and compiles it (hipRTC, no device needed): it reports the

@@ -135,6 +135,30 @@ def test_bitsliced_kernels_after_prepare(k, n, sys_):
 
 
 @pytest.mark.timeout(300)
+def test_split_bitsliced_kernels_after_prepare():
+    """The k = 16 systematic encode (240 x 240) and the k = 8 decode from
+    the 8 parity nodes (56 x 56 dense) are past one bit-sliced kernel's size:
+    prepared, each runs as several generated kernels over consecutive row
+    groups, side by side (2 parts each).  Every symbol against the
+    oracle at a whole tile, a window tile with a byte tail, and several
+    tiles."""
+    c16, o16 = pm.Code(k=16, d=30, n=32, w=16), F.Code(16, 32)
+    c8, o8 = pm.Code(k=8, d=14, n=16, w=16), F.Code(8, 16)
+    K = list(range(8, 16))
+    assert c16.prepare(pm.OP_ENCODE) is True
+    assert c8.prepare(pm.OP_DECODE, ids=K) is True
+    for s in (4096, 4096 + 30, 3 * 4096 + 1002):
+        print("gf16 split kernels", s, flush=True)
+        X = _data(c16.B, s, 1990 + s % 83)
+        assert np.array_equal(_u16(_encode(c16, X, s)), o16.encode(_u16(X))), s
+        X8 = _data(c8.B, s, 1991 + s % 79)
+        nodes = _nodes(o8, X8, _encode(c8, X8, s))
+        out = out_regions(c8.B, s)
+        c8.decode(K, to_regions(np.concatenate([nodes[i] for i in K])), out, s)
+        assert np.array_equal(read(out, s), X8), s
+
+
+@pytest.mark.timeout(300)
 @pytest.mark.parametrize("k,n,s,f", [(40, 79, 2048 + 14, 41), (64, 127, 1024 + 6, 100)])
 def test_beyond_the_byte_field(k, n, s, f):
     """k = 40 (B = 1560; the construction fails over GF(2^8) from here) and
