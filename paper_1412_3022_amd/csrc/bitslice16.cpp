@@ -43,7 +43,10 @@ typedef unsigned long long u64;
 typedef u32 u32x4 __attribute__((ext_vector_type(4)));
 #define X3(a, b, c) __builtin_amdgcn_bitop3_b32((a), (b), (c), 0x96)
 __device__ __forceinline__ void ST(unsigned char *d, u32x4 v) { __builtin_nontemporal_store(v, (u32x4 *)d); }
-#define DS(a, b, sh, m) { u32 t_ = (((a) >> (sh)) ^ (b)) & (m); (b) ^= t_; (a) ^= t_ << (sh); }
+// delta swap of the bits of b under mask m with those of a under m << sh,
+// as two selects (v_bitop3 truth table 0xD8: c ? b : a)
+#define SEL(a, b, m) __builtin_amdgcn_bitop3_b32((a), (b), (m), 0xD8)
+#define DS(a, b, sh, m) { const u32 a_ = (a), b_ = (b); (a) = SEL(a_, b_ << (sh), (m) << (sh)); (b) = SEL(b_, a_ >> (sh), (m)); }
 #define TR8(A0, A1, A2, A3, A4, A5, A6, A7) { \
   DS(A0, A4, 4, 0x0F0F0F0Fu) DS(A1, A5, 4, 0x0F0F0F0Fu) DS(A2, A6, 4, 0x0F0F0F0Fu) DS(A3, A7, 4, 0x0F0F0F0Fu) \
   DS(A0, A2, 2, 0x33333333u) DS(A1, A3, 2, 0x33333333u) DS(A4, A6, 2, 0x33333333u) DS(A5, A7, 2, 0x33333333u) \

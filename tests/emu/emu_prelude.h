@@ -16,8 +16,16 @@ static EmuDim threadIdx, blockIdx;
 #define __launch_bounds__(x)
 #define __noinline__ __attribute__((noinline))
 #define __forceinline__ inline
-// The kernels use truth table 0x96 only: a ^ b ^ c.
-#define __builtin_amdgcn_bitop3_b32(a, b, c, imm) ((a) ^ (b) ^ (c))
+// v_bitop3_b32: bit i of the result is bit (a_i << 2 | b_i << 1 | c_i) of imm
+// (the kernels use 0x96, a ^ b ^ c, and 0xD8, c ? b : a)
+static inline unsigned __builtin_amdgcn_bitop3_b32(unsigned a, unsigned b, unsigned c, unsigned imm) {
+    if (imm == 0x96) return a ^ b ^ c;          // the two tables the kernels use, without the loop
+    if (imm == 0xD8) return (a & ~c) | (b & c);
+    unsigned r = 0;
+    for (unsigned k = 0; k < 8; ++k)
+        if ((imm >> k) & 1u) r |= ((k & 4u) ? a : ~a) & ((k & 2u) ? b : ~b) & ((k & 1u) ? c : ~c);
+    return r;
+}
 // Like the builtin, returns int (a caller that widens it without going
 // through an unsigned type sign-extends, as on the GPU).
 #define __builtin_amdgcn_readfirstlane(x) ((int)(x))
