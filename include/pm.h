@@ -89,7 +89,12 @@ typedef struct {
  * as for w = 8; pm_prepare builds the operation's matrix, generates and
  * compiles its bit-sliced kernel when the matrix is under the size limit
  * (*specialized = 1; blocks of at least 4096 bytes then run on it) and stages
- * both on the device.  pm_code_matrix writes two bytes per entry,
+ * both on the device.  A matrix past one kernel's limit and within two (the
+ * k = 16 encode, the k = 8 decode from the parity nodes) gets two kernels
+ * over halves of its rows, compiled on two threads (about a minute of
+ * hipRTC for the k = 16 encode) and run side by side: the second on an
+ * internal stream that waits for the caller's stream, which then waits for
+ * it.  The specific decoder's passes get one kernel at most.  pm_code_matrix writes two bytes per entry,
  * little-endian (cap counts bytes).  pm_decode_specific (and its workspace,
  * factor and pm_prepare forms) runs the specific PM-MSR decoder's passes on
  * the GF(2^16) kernel; pm_decode_specific_factor writes two bytes per entry.
