@@ -542,7 +542,8 @@ def gpu_init_case(torch, pm, synth):
 def batched_case(torch, pm, synth, steps):
     """Configuration 4: 4096 objects, sizes log-uniform 64 KiB - 16 MiB,
     sparse PM-MSR (4,6), (8,14), (16,30), n = 2k, all encoded by one
-    graph-captured batch (tile width autotuned), against one plain pm_encode
+    graph-captured batch (tile width and bit-sliced work-group slots autotuned;
+    untuned_batched_gbps: the defaults), against one plain pm_encode
     launch per object on the same stream."""
     from paper_1412_3022_amd import workloads
     dev = torch.device("cuda:0")
@@ -565,11 +566,13 @@ def batched_case(torch, pm, synth, steps):
     wall_plain, ev_plain = Timer(torch).run(plain, 2, 1)
     batch = pm.Batch([dict(code=o["code"], op="encode", inp=o["X"], out=o["P"], block_bytes=o["s"])
                       for o in objs], graph=True)   # uses the prepared multi-set kernels
+    wall_u, _ = Timer(torch).run(lambda i: batch.run(), steps, 2)   # default tile widths and slots
     vec = batch.autotune(reps=2)
     units, classes = batch.info()
     wall_b, ev_b = Timer(torch).run(lambda i: batch.run(), steps, 2)
     res = {"objects": len(objs), "source_bytes": src, "plain_gbps": round(src * 2 / wall_plain / 1e9, 2),
            "batched_gbps": round(src * steps / wall_b / 1e9, 2),
+           "untuned_batched_gbps": round(src * steps / wall_u / 1e9, 2),
            "batched_ms_per_run": round(wall_b / steps * 1e3, 3), "plain_ms_per_pass": round(wall_plain / 2 * 1e3, 3),
            "batch_units": units, "launches": classes, "tuned_dwords_per_lane": vec,
            "init_s": round(init_s, 2)}

@@ -390,8 +390,10 @@ pm_status pm_batch_plan(const pm_batch_item *items, size_t n, uint32_t flags, pm
  * lane per block) for the size class with rows_per_group rows (0 = all). */
 pm_status pm_batch_set_variant(pm_batch *batch, uint32_t rows_per_group, uint32_t dwords_per_lane);
 
-/* Autotuner: times each tile width per size class (reps runs each, HIP
- * events on `stream`), keeps the fastest and reports the last class's pick.
+/* Autotuner: times each tile width per size class of the table work lists
+ * and, for each matrix's bit-sliced multi-set launch, half, all and twice its
+ * resident work-group slots (reps runs each, HIP events on `stream`), keeps
+ * the fastest of each and reports the last table class's tile width.
  * Synchronous; overwrites the items' outputs with valid results. */
 pm_status pm_batch_autotune(pm_batch *batch, uint32_t reps, pm_stream stream,
                             uint32_t *best_dwords_per_lane);

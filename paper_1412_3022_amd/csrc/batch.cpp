@@ -61,6 +61,7 @@ struct BsClass {
     std::vector<BsItem> items;
     BsItem *d_items = nullptr;
     uint32_t ntiles = 0;
+    uint32_t slots = 0;   // work-group slots per XCD of its launch (0 = resident count; the autotuner sets it)
 };
 
 }  // namespace
@@ -151,7 +152,7 @@ int build_bs_class(BsClass &c) {
 
 int launch_all(pm_batch *b, hipStream_t st) {
     for (BsClass &c : b->bs_classes) {
-        int rc = bs_launch_items(*c.bp, c.d_items, static_cast<uint32_t>(c.items.size()), c.ntiles, st);
+        int rc = bs_launch_items(*c.bp, c.d_items, static_cast<uint32_t>(c.items.size()), c.ntiles, st, c.slots);
         if (rc != ST_OK) return rc;
     }
     for (size_t i = 0; i < b->classes.size(); ++i) {
@@ -326,6 +327,33 @@ pm_status pm_batch_autotune(pm_batch *b, uint32_t reps, pm_stream stream, uint32
         }
         if (rc != ST_OK) break;
         if ((rc = build_class(c, static_cast<int>(best_vec))) != ST_OK) break;
+    }
+    // The bit-sliced launches carry most bytes: each matrix's persistent
+    // grid is timed at half, all and twice its resident work-group slots
+    // (fewer waves leave more of L2 to each; more let the dispatcher fill
+    // the gaps that waves finishing early leave), and keeps the fastest.
+    for (BsClass &c : b->bs_classes) {
+        if (rc != ST_OK) break;
+        const uint32_t p0 = bs_default_slots(*c.bp);
+        if (!p0) {
+            rc = ST_EHIP;
+            break;
+        }
+        float best = 1e30f;
+        uint32_t best_p = p0;
+        const uint32_t n = static_cast<uint32_t>(c.items.size());
+        for (uint32_t p : {std::max(1u, p0 / 2), p0, 2 * p0}) {
+            if ((rc = bs_launch_items(*c.bp, c.d_items, n, c.ntiles, st, p)) != ST_OK) break;
+            (void)hipEventRecord(e0, st);
+            for (uint32_t i = 0; i < reps && rc == ST_OK; ++i) rc = bs_launch_items(*c.bp, c.d_items, n, c.ntiles, st, p);
+            (void)hipEventRecord(e1, st);
+            if (rc != ST_OK) break;
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) { rc = hip_fail(e); break; }
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) { best = ms; best_p = p; }
+        }
+        c.slots = best_p;
     }
     b->flags = saved;
     drop_graph(b);

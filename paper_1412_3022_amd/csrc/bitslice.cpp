@@ -579,7 +579,8 @@ int bs_launch(BsProgram &bp, const uint8_t *in, uint64_t in_ld, uint8_t *out, ui
     return bs_go(args, m->fn, args.P, st);
 }
 
-int bs_launch_items(BsProgram &bp, const BsItem *d_items, uint32_t nitems, uint32_t ntiles, hipStream_t st) {
+int bs_launch_items(BsProgram &bp, const BsItem *d_items, uint32_t nitems, uint32_t ntiles, hipStream_t st,
+                    uint32_t slots) {
     if (nitems == 0 || ntiles == 0) return ST_OK;
     BsModule *m;
     int rc = bs_module(bp, BS_MULTI, &m);
@@ -589,8 +590,13 @@ int bs_launch_items(BsProgram &bp, const BsItem *d_items, uint32_t nitems, uint3
         uint32_t nitems, ntiles, P, pad;
     // persistent: each wave walks several tiles, which amortizes the search
     // for their items
-    } args{d_items, nitems, ntiles, static_cast<uint32_t>(m->P), 0};
+    } args{d_items, nitems, ntiles, slots ? slots : static_cast<uint32_t>(m->P), 0};
     return bs_go(args, m->fn, args.P, st);
+}
+
+uint32_t bs_default_slots(BsProgram &bp) {
+    BsModule *m;
+    return bs_module(bp, BS_MULTI, &m) == ST_OK ? static_cast<uint32_t>(m->P) : 0u;
 }
 
 }  // namespace pmrc

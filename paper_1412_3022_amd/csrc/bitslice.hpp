@@ -87,6 +87,11 @@ int bs_launch(BsProgram &bp, const uint8_t *in, uint64_t in_ld, uint8_t *out, ui
 // One launch of the multi-set kernel over nitems items in device memory
 // (d_items, sorted by tile0, tiles numbered back to back, ntiles in all,
 // every item s >= kBsTileBytes), all for this program.
-int bs_launch_items(BsProgram &bp, const BsItem *d_items, uint32_t nitems, uint32_t ntiles, hipStream_t st);
+// slots: work-group slots per XCD (0 = the resident count, bs_default_slots).
+int bs_launch_items(BsProgram &bp, const BsItem *d_items, uint32_t nitems, uint32_t ntiles, hipStream_t st,
+                    uint32_t slots = 0);
+// The resident work-group slots per XCD of the multi-set kernel on the
+// current device (compiles and loads it if needed); 0 on failure.
+uint32_t bs_default_slots(BsProgram &bp);
 
 }  // namespace pmrc

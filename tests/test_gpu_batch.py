@@ -232,6 +232,22 @@ def test_specialized_batch_graph_replays():
         _check(items, expected)
 
 
+def test_specialized_batch_after_autotune():
+    """The autotuner also times the bit-sliced multi-set launches at half,
+    all and twice their resident work-group slots and keeps the fastest:
+    after it, graph replays still give the oracle's bytes."""
+    print("specialized batch, autotuned slots", flush=True)
+    items, expected = _fixed_pattern_items(23, 40, 12000, _fams())
+    b = pm.Batch(items, graph=True, specialize=True)
+    assert b.autotune(reps=2) in (2, 4)
+    for rep in range(2):
+        for it in items:
+            it["out"].fill_(0x5A)
+        torch.cuda.synchronize()
+        b.run()
+        _check(items, expected)
+
+
 def test_specialized_k16_encode_single_and_batched():
     """The k = 16 encode network (30 row groups of 8 x 30): its single-set
     kernel through pm_prepare and its multi-set kernel through a specialized

@@ -181,16 +181,19 @@ def test_beyond_the_byte_field(k, n, s, f):
 
 
 @pytest.mark.timeout(300)
-def test_k8_64mib_object_sampled():
-    """Sparse systematic (8, 14, 16) over GF(2^16), a 64 MiB object (56 blocks
-    of 1 198 400 bytes), in the launch the benchmark times: sampled symbol
-    positions (the first, around each wave tile edge, the last) against the
-    oracle."""
-    print("gf16 64MiB", flush=True)
-    c = pm.Code(k=8, d=14, n=16, w=16)
-    assert c.prepare(pm.OP_ENCODE) is True   # the bit-sliced kernel, as the benchmark runs it
-    o = F.Code(8, 16)
-    s = 1198400
+@pytest.mark.parametrize("k", [8, 16])
+def test_64mib_object_sampled(k):
+    """Sparse systematic (8, 14, 16) and (16, 30, 32) over GF(2^16), a 64 MiB
+    object (56 blocks of 1 198 400 bytes; 240 of 279 680), in the launches the
+    benchmark times (one bit-sliced kernel; two side by side at k = 16):
+    sampled symbol positions (the first, around each wave tile edge, the
+    last) against the oracle."""
+    print("gf16 64MiB", k, flush=True)
+    c = pm.Code(k=k, d=2 * k - 2, n=2 * k, w=16)
+    assert c.prepare(pm.OP_ENCODE) is True   # the bit-sliced kernels, as the benchmark runs them
+    o = F.Code(k, 2 * k)
+    s = synth.block_bytes_for(64 << 20, c.B)
+    assert s == {8: 1198400, 16: 279680}[k]
     X = synth.random_bytes_torch(0x16, c.B * s, device()).view(c.B, s)
     out = torch.empty((c.enc_rows, s), dtype=torch.uint8, device=device())
     c.encode(X, out, s)
