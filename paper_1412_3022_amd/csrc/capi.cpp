@@ -56,6 +56,19 @@ static int upload_stream(int dev, hipStream_t *out) {
 ProgEntry::~ProgEntry() {
     free_device_copies(dev);
     free_device_copies(mf_dev);
+    free_device_copies(mf_copy_dev);
+}
+
+// Rows that are one input block times 1: copies, not products.
+static bool unit_row(const Mat &A, int r, int *nnz) {
+    int nz = 0, last = -1;
+    for (int c = 0; c < A.cols; ++c)
+        if (A.at(r, c)) {
+            ++nz;
+            last = c;
+        }
+    *nnz = nz;
+    return nz == 1 && A.at(r, last) == 1;
 }
 
 static std::atomic<size_t> g_table_bytes{0};
@@ -190,8 +203,21 @@ int ProgEntry::device_ptr_sync(const uint32_t **out) {
 bool ProgEntry::mfma_eligible() {
     if (A.rows == 0 || A.cols == 0) return false;
     if (static_cast<uint32_t>(A.cols) > kMfMaxChunks * kMfColsPerChunk) return false;
-    const long cells = static_cast<long>(A.rows) * A.cols;
-    if (cells < 64 * 64 || prog.nnz * 2 < cells) return false;
+    // the rows that are computed (copies aside): at least 64 x 64 cells and
+    // a third of them nonzero.  (The table kernels' cost grows with the
+    // nonzeros, the matrix cores' with the cells; on a decode of the
+    // (16,30,32) code from 9 systematic and 7 parity nodes, 105 computed rows
+    // 47 % nonzero, the table kernel took 329 us and the matrix cores 272 us
+    // computing all 240 rows.)
+    long nt = 0, nnz = 0;
+    for (int r = 0; r < A.rows; ++r) {
+        int nz = 0;
+        if (unit_row(A, r, &nz)) continue;
+        ++nt;
+        nnz += nz;
+    }
+    const long cells = nt * A.cols;
+    if (cells < 64 * 64 || nnz * 3 < cells) return false;
     std::shared_ptr<BsProgram> b = bitslice();
     return !b;
 }
@@ -199,7 +225,21 @@ bool ProgEntry::mfma_eligible() {
 void ProgEntry::build_mfma_locked() {
     if (mf_tried) return;
     mf_tried = true;
-    MfmaProgram P = build_mfma_program(A, in_map);
+    std::vector<int> rows;
+    std::vector<char> computed(static_cast<size_t>(A.rows), 0);
+    for (int r = 0; r < A.rows; ++r) {
+        int nz = 0;
+        if (!unit_row(A, r, &nz)) {
+            rows.push_back(r);
+            computed[static_cast<size_t>(r)] = 1;
+        }
+    }
+    if (static_cast<int>(rows.size()) < A.rows) {
+        mf_copy = build_program(A, prog.rg, in_map, &computed);   // the copy rows alone
+    } else {
+        rows.clear();   // every row on the matrix cores
+    }
+    MfmaProgram P = build_mfma_program(A, in_map, rows);
     mf_words = std::move(P.words);
     mf_nmtiles = P.nmtiles;
     mf_nchunks = P.nchunks;
@@ -212,10 +252,13 @@ size_t ProgEntry::mfma_upload_bytes() {
     int devid = 0;
     if (hipGetDevice(&devid) != hipSuccess) return 0;
     std::lock_guard<std::mutex> lk(mu);
-    auto it = mf_dev.find(devid);
-    if (it != mf_dev.end() && it->second.ptr) return 0;
     build_mfma_locked();
-    return mf_words.size() * sizeof(uint32_t);
+    size_t b = 0;
+    auto it = mf_dev.find(devid);
+    if (it == mf_dev.end() || !it->second.ptr) b += mf_words.size() * sizeof(uint32_t);
+    auto ic = mf_copy_dev.find(devid);
+    if (mf_copy.ngroups && (ic == mf_copy_dev.end() || !ic->second.ptr)) b += mf_copy.blob.size() * sizeof(uint32_t);
+    return b;
 }
 
 int ProgEntry::stage_mfma() {
@@ -224,7 +267,10 @@ int ProgEntry::stage_mfma() {
         build_mfma_locked();
     }
     const void *d = nullptr;
-    return device_copy_sync(mu, mf_dev, mf_words.data(), mf_words.size() * sizeof(uint32_t), &d);
+    int st = device_copy_sync(mu, mf_dev, mf_words.data(), mf_words.size() * sizeof(uint32_t), &d);
+    if (st == ST_OK && mf_copy.ngroups)
+        st = device_copy_sync(mu, mf_copy_dev, mf_copy.blob.data(), mf_copy.blob.size() * sizeof(uint32_t), &d);
+    return st;
 }
 
 int ProgEntry::launch_mfma(const uint8_t *in, size_t in_ld, uint8_t *out, size_t out_ld, size_t s,
@@ -235,7 +281,7 @@ int ProgEntry::launch_mfma(const uint8_t *in, size_t in_ld, uint8_t *out, size_t
         build_mfma_locked();
     }
     if (!mf_ok) return ST_EINVAL;
-    const void *d = nullptr;
+    const void *d = nullptr, *dc = nullptr;
     int st;
     if (resident_only) {
         int devid = 0;
@@ -245,9 +291,21 @@ int ProgEntry::launch_mfma(const uint8_t *in, size_t in_ld, uint8_t *out, size_t
         auto it = mf_dev.find(devid);
         if (it == mf_dev.end() || !it->second.ptr || !it->second.done) return ST_ENOTREADY;
         d = it->second.ptr;
+        if (mf_copy.ngroups) {
+            auto ic = mf_copy_dev.find(devid);
+            if (ic == mf_copy_dev.end() || !ic->second.ptr || !ic->second.done) return ST_ENOTREADY;
+            dc = ic->second.ptr;
+        }
     } else if ((st = device_copy(mu, mf_dev, mf_words.data(), mf_words.size() * sizeof(uint32_t), stream, &d)) !=
-               ST_OK) {
+                   ST_OK ||
+               (mf_copy.ngroups && (st = device_copy(mu, mf_copy_dev, mf_copy.blob.data(),
+                                                     mf_copy.blob.size() * sizeof(uint32_t), stream, &dc)) != ST_OK)) {
         return st;
+    }
+    if (mf_copy.ngroups) {   // the copy rows, on the table kernel's copy groups
+        PmkApply a{in, in_ld, out, out_ld, s, static_cast<const uint32_t *>(dc), static_cast<uint32_t>(mf_copy.ngroups)};
+        hipError_t e = pmk_apply(mf_copy.rg, kVecTable, &a, stream);
+        if (e != hipSuccess) return hip_fail(e);
     }
     const uint32_t *w = static_cast<const uint32_t *>(d);
     PmkMfma h{in, in_ld, out, out_ld, s, w, w + mf_cols_off, w + mf_rows_off, mf_nmtiles, mf_nchunks, 0, 0, 0, 0};
@@ -371,6 +429,7 @@ static size_t entry_device_bytes(ProgEntry &pe) {
     size_t b = 0;
     for (auto &kv : pe.dev) b += kv.second.bytes;
     for (auto &kv : pe.mf_dev) b += kv.second.bytes;
+    for (auto &kv : pe.mf_copy_dev) b += kv.second.bytes;
     if (pe.bs) b += 1;   // a loaded kernel module: device memory of unknown size
     return b;
 }

@@ -78,6 +78,11 @@ struct ProgEntry {
     std::vector<uint32_t> mf_words;
     uint32_t mf_nmtiles = 0, mf_nchunks = 0, mf_cols_off = 0, mf_rows_off = 0;
     std::map<int, DevCopy> mf_dev;
+    // rows that are one input block times 1 (a decode's blocks that K's
+    // systematic nodes hold) are not computed on the matrix cores: a table
+    // kernel launch of copy groups writes them first (ngroups 0: none)
+    Program mf_copy;
+    std::map<int, DevCopy> mf_copy_dev;
     ~ProgEntry();
     // The bit-sliced specialization, generated (not compiled) on first use;
     // nullptr when the matrix is too large to specialize.
@@ -96,7 +101,9 @@ struct ProgEntry {
     // the copy is there).
     size_t upload_bytes();
     // Whether the matrix is dense and too large for a specialized kernel:
-    // then the matrix-core kernel runs instead of the table kernel.
+    // then the matrix-core kernel runs instead of the table kernel.  Dense
+    // counts the rows that are not copies: at least a third of their
+    // coefficients nonzero.
     bool mfma_eligible();
     // Enqueue the matrix-core product (builds and uploads its operands on
     // first use; resident_only: ST_ENOTREADY unless they are on the device).

@@ -22,9 +22,11 @@ namespace pmrc {
 // given to output row 2 h + q / 2 and bit 4 (q % 2) + t of that row, with
 // q = m / 8, h = (m / 4) % 2, t = m % 4, so that accumulators 0..7 of a lane
 // are bits 0..7 of output row 2 h and 8..15 those of row 2 h + 1.
-MfmaProgram build_mfma_program(const Mat &A, const std::vector<int> &in_map) {
+MfmaProgram build_mfma_program(const Mat &A, const std::vector<int> &in_map, const std::vector<int> &rows) {
     MfmaProgram P;
-    const uint32_t R = static_cast<uint32_t>(A.rows), C = static_cast<uint32_t>(A.cols);
+    const uint32_t R = static_cast<uint32_t>(rows.empty() ? A.rows : static_cast<int>(rows.size()));
+    const uint32_t C = static_cast<uint32_t>(A.cols);
+    auto mrow = [&](uint32_t r) { return rows.empty() ? static_cast<int>(r) : rows[r]; };   // tile row -> matrix row
     // whole M blocks: the kernel runs every tile of a block without a check
     P.nmtiles = (R + kMfRowsPerTile - 1) / kMfRowsPerTile;
     P.nmtiles = (P.nmtiles + kMfTilePad - 1) / kMfTilePad * kMfTilePad;
@@ -47,7 +49,7 @@ MfmaProgram build_mfma_program(const Mat &A, const std::vector<int> &in_map) {
                         const uint32_t beta = 4 * t + q;
                         const uint32_t c = kc * kMfColsPerChunk + 4 * kb + beta / 8, j = beta % 8;
                         if (c >= C) continue;
-                        const uint8_t a = A.at(static_cast<int>(r), static_cast<int>(c));
+                        const uint8_t a = A.at(mrow(r), static_cast<int>(c));
                         if (!a) continue;
                         if ((gmul(a, static_cast<uint8_t>(1u << j)) >> bit) & 1u)
                             tile[l * 4 + q] |= (q % 2 ? 0x2u : 0x4u) << (4 * t);   // 1.0 or 2.0 in e2m1
@@ -56,7 +58,8 @@ MfmaProgram build_mfma_program(const Mat &A, const std::vector<int> &in_map) {
         }
     for (uint32_t c = 0; c < P.nchunks * kMfColsPerChunk; ++c)
         P.words[P.cols_off + c] = c < C ? static_cast<uint32_t>(in_map.empty() ? c : in_map[c]) : 0u;
-    for (uint32_t r = 0; r < P.nmtiles * kMfRowsPerTile; ++r) P.words[P.rows_off + r] = r < R ? r : kMfNoRow;
+    for (uint32_t r = 0; r < P.nmtiles * kMfRowsPerTile; ++r)
+        P.words[P.rows_off + r] = r < R ? static_cast<uint32_t>(mrow(r)) : kMfNoRow;
     return P;
 }
 

@@ -64,7 +64,9 @@ struct MfmaProgram {
     std::vector<uint32_t> words;
 };
 
-// in_map: input block of each matrix column (empty = identity).
-MfmaProgram build_mfma_program(const Mat &A, const std::vector<int> &in_map);
+// in_map: input block of each matrix column (empty = identity).  rows: the
+// matrix rows to compute, each written to its own output row (empty = all;
+// the other rows are left to the caller).
+MfmaProgram build_mfma_program(const Mat &A, const std::vector<int> &in_map, const std::vector<int> &rows = {});
 
 }  // namespace pmrc

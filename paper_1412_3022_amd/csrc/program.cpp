@@ -48,7 +48,7 @@ void pack_tables(uint8_t c, uint32_t out[kTabWords]) {
     out[4] = word(0, 64, 128, 192);   // top 2 bits
 }
 
-Program build_program(const Mat &A, int rg, const std::vector<int> &in_map) {
+Program build_program(const Mat &A, int rg, const std::vector<int> &in_map, const std::vector<char> *skip) {
     Program P;
     P.rg = rg;
     P.rows = A.rows;
@@ -57,6 +57,7 @@ Program build_program(const Mat &A, int rg, const std::vector<int> &in_map) {
     std::map<Support, std::vector<int>> buckets;
     std::vector<int> copy_rows;
     for (int r = 0; r < A.rows; ++r) {
+        if (skip && (*skip)[static_cast<size_t>(r)]) continue;   // a row another kernel writes
         Support s(A.cols);
         int nz = 0, last = -1;
         for (int c = 0; c < A.cols; ++c)

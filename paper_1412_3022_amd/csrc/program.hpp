@@ -37,7 +37,9 @@ struct Program {
 };
 
 // in_map: input block index of each matrix column (empty = identity).
-Program build_program(const Mat &A, int rg, const std::vector<int> &in_map = {});
+// skip: rows left out of every group (written by another kernel), or null.
+Program build_program(const Mat &A, int rg, const std::vector<int> &in_map = {},
+                      const std::vector<char> *skip = nullptr);
 
 // Pack the tables of one coefficient (5 words) -- exposed for tests.
 void pack_tables(uint8_t c, uint32_t out[kTabWords]);

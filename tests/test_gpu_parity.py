@@ -351,6 +351,26 @@ def test_k16_sparse_encode_repair_decode():
         assert np.array_equal(read(xo, s), X)
 
 
+@pytest.mark.parametrize("s", [777, 4096 + 48, 191616])
+def test_k16_mixed_decode_on_the_matrix_cores(s):
+    """A (16,30,32) decode from 9 systematic and 7 parity nodes (the served
+    mix's largest resident object's node set): 135 rows are copies of held
+    blocks and 105 are computed, 47 % of their coefficients nonzero.  The
+    default path copies the first (copy groups of the table kernel) and
+    computes the second on the matrix cores; every byte against the oracle,
+    up to that object's 191 616-byte blocks."""
+    print("k16 mixed decode s=%d" % s, flush=True)
+    c = pm.Code(k=16, d=30, n=32)
+    o = O.Code(O.MSR, 16, 30, 32, O.SPARSE)
+    K = [0, 6, 7, 9, 10, 11, 12, 13, 15, 16, 17, 20, 21, 23, 25, 29]
+    X = _rand(1600 + s % 97, c.B, s)
+    P = o.encode(X, nthreads=8)
+    Y = np.concatenate([o.node_blocks(i, X, P) for i in K])
+    xo = out_regions(c.B, s, extra=1)
+    c.decode(K, to_regions(Y, extra=1), xo, s)
+    assert np.array_equal(read(xo, s), X)
+
+
 # ------------------------------------------------- bit-sliced specialization --
 BS_CODES = [
     ("msr4", dict(k=4, d=6, n=8)),

@@ -49,7 +49,7 @@ def exe(tmp_path_factory):
     return out
 
 
-def _run(exe, tmp_path, A, in_map, X, ncu=None):
+def _run(exe, tmp_path, A, in_map, X, ncu=None, subset=False):
     R, C = A.shape
     nin, s = X.shape
     ld = (s + 15) // 16 * 16
@@ -62,6 +62,8 @@ def _run(exe, tmp_path, A, in_map, X, ncu=None):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
     if ncu:
         env["EMU_NCU"] = str(ncu)
+    if subset:
+        env["EMU_SUBSET"] = "1"
     r = subprocess.run([exe, str(inp), str(outp)], env=env, timeout=600, check=True, capture_output=True, text=True)
     plan = dict(zip(r.stdout.split()[0::2], map(int, r.stdout.split()[1::2])))
     return np.frombuffer(open(outp, "rb").read(), np.uint8).reshape(R, s), plan
@@ -100,3 +102,26 @@ def test_mfma_kernel_on_host_matches_the_oracle(exe, tmp_path, R, C, nin, s, den
     got, plan = _run(exe, tmp_path, A, in_map, X, ncu)
     assert plan["T"] == (4 if (C + 7) // 8 <= 38 else 2)
     assert np.array_equal(got, O.apply(A, X[in_map], nthreads=4))
+
+
+def test_only_the_computed_rows_on_the_matrix_cores(exe, tmp_path):
+    """A decode-like matrix: rows that are one input block times 1 (blocks
+    the node set holds) between dense rows.  With those rows left out of
+    the program, the kernel writes exactly the other rows, each to its own
+    output row, with the oracle's bytes; the unit rows' output stays as it
+    was (zero here), for the library's copy launch."""
+    rng = np.random.default_rng(91)
+    R, C, s = 40, 48, 700
+    A = rng.integers(1, 256, (R, C), dtype=np.uint8)
+    A[rng.random((R, C)) >= 0.5] = 0
+    unit = [0, 3, 4, 5, 17, 30, 39]
+    for k, r in enumerate(unit):
+        A[r, :] = 0
+        A[r, (7 * k) % C] = 1
+    in_map = rng.permutation(C)
+    X = rng.integers(0, 256, (C, s), dtype=np.uint8)
+    got, _ = _run(exe, tmp_path, A, in_map, X, subset=True)
+    want = O.apply(A, X[in_map], nthreads=4)
+    comp = [r for r in range(R) if r not in unit]
+    assert np.array_equal(got[comp], want[comp])
+    assert not got[unit].any()
