@@ -309,9 +309,11 @@ pm_status pm_apply(const uint8_t *A, uint32_t rows, uint32_t cols, const uint8_t
  * hipRTC failure is reported as PM_EHIP.  0, 0 restores the default: the
  * bit-sliced kernel when the operation's matrix has one compiled (by
  * pm_prepare, pm_autotune_encode or a call under variant 32) and the block
- * is at least 2048 bytes; else, for a dense matrix (half or more of its
- * entries nonzero, at least 64 x 64, at most 512 columns) too large to
- * specialize, the matrix-core kernel (dwords_per_lane 40 with
+ * is at least 2048 bytes; else, for a dense matrix (at most 512 columns;
+ * its rows that are not one input block times 1 span at least 64 x 64
+ * entries, a third or more of them nonzero) too large to specialize, the
+ * matrix-core kernel on those rows, the other rows copied first by the
+ * table kernel (dwords_per_lane 40 with
  * rows_per_group 8 selects it explicitly: the matrix's GF(2) expansion, 8
  * rows x 8 columns of bits per coefficient, multiplied with the input bits
  * on v_mfma with 4-bit float operands and reduced to parities, the

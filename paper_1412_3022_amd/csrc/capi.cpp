@@ -196,10 +196,9 @@ int ProgEntry::device_ptr_sync(const uint32_t **out) {
     return st;
 }
 
-// A dense matrix beyond the specialization limit: at least half of its
-// entries nonzero and at least 64 x 64 of them (the table kernel's cost
-// grows with the nonzeros, the matrix cores' with the whole matrix), and at
-// most 512 columns (the kernel's operands of one M tile in LDS).
+// A dense matrix beyond the specialization limit: at most 512 columns (the
+// kernel's operands of one M tile in LDS), and rows other than copies
+// spanning at least 64 x 64 cells, a third of them nonzero.
 bool ProgEntry::mfma_eligible() {
     if (A.rows == 0 || A.cols == 0) return false;
     if (static_cast<uint32_t>(A.cols) > kMfMaxChunks * kMfColsPerChunk) return false;
