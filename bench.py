@@ -359,7 +359,9 @@ def msr16_decode_case(torch, pm, synth, steps, warmup):
     """PM-MSR (16,30,32) sparse, 64 MiB object, decoded from the 16 parity
     nodes (every data block lost): the linearized decode (dense 240 x 240
     inverse) against the specific decode (pm_decode_specific, after
-    pm_prepare op 4 compiled its passes; that init time is reported apart)."""
+    pm_prepare op 4 compiled its passes; that init time is reported apart);
+    and the linearized decode from a mixed node set (9 systematic, 7 parity
+    nodes: 135 blocks copied, 105 computed)."""
     dev = torch.device("cuda:0")
     code = pm.Code(k=16, d=30, n=32)
     S = 64 << 20
@@ -393,7 +395,18 @@ def msr16_decode_case(torch, pm, synth, steps, warmup):
     out["msr16_decode_specific_gbps"] = S * n / ev / 1e9
     torch.cuda.synchronize()
     out["msr16_decode_results_equal"] = bool(torch.equal(xs[:, :s], xl[:, :s]) and torch.equal(xs[:, :s], x[:, :s]))
-    del x, P, Y, xl, xs, ws
+    # a mixed node set (9 systematic, 7 parity): the linearized decode copies
+    # the 135 held blocks and computes the 105 lost ones on the matrix cores
+    Km = [0, 6, 7, 9, 10, 11, 12, 13, 15, 16, 17, 20, 21, 23, 25, 29]
+    Ym = torch.stack([x[v] if v < code.B else P[v - code.B] for i in Km for v in nm[i * code.alpha:(i + 1) * code.alpha]])
+    Ym = Ym.contiguous()
+    xm = torch.empty_like(x)
+    _, ev = Timer(torch).run(lambda i: pm.pm_decode(code.h, Km, Ym.data_ptr(), ld, xm.data_ptr(), ld, s, stream),
+                             n, 2)
+    out["msr16_decode_mixed_linear_gbps"] = S * n / ev / 1e9
+    torch.cuda.synchronize()
+    out["msr16_decode_mixed_equal"] = bool(torch.equal(xm[:, :s], x[:, :s]))
+    del x, P, Y, xl, xs, ws, Ym, xm
     return out
 
 
