@@ -94,7 +94,10 @@ typedef struct {
  * over halves of its rows, compiled on two threads (about a minute of
  * hipRTC for the k = 16 encode) and run side by side: the second on an
  * internal stream that waits for the caller's stream, which then waits for
- * it.  The specific decoder's passes get one kernel at most.  pm_code_matrix writes two bytes per entry,
+ * it.  That internal stream is shared by all calls on the device: while one
+ * thread captures such a call into a graph, other threads should not make
+ * such calls until the capture ends.  The specific decoder's passes get one
+ * kernel at most.  pm_code_matrix writes two bytes per entry,
  * little-endian (cap counts bytes).  pm_decode_specific (and its workspace,
  * factor and pm_prepare forms) runs the specific PM-MSR decoder's passes on
  * the GF(2^16) kernel; pm_decode_specific_factor writes two bytes per entry.
