@@ -85,3 +85,13 @@ def test_specific_decode_factors_multiply_to_the_decode_matrix(k, n, sys_, K):
             prod = F.matmul(f, prod)
     assert np.array_equal(prod, o.decode_matrix(K))
     assert (Fs[4].size > 0) == sys_
+
+
+def test_split_kernels_compile_side_by_side_without_a_gpu():
+    """The k = 8 decode from the 8 parity nodes (56 x 56 dense, past one
+    bit-sliced kernel's size) is generated as two kernels whose hipRTC
+    compiles run on two threads, joined before pm_prepare returns; with no
+    device nothing is staged, and the call reports the operation
+    specialized."""
+    c = pm.Code(k=8, d=14, n=16, w=16)
+    assert pm.pm_prepare(c.h, pm.OP_DECODE, ids=list(range(8, 16))) == (pm.PM_OK, 1)
